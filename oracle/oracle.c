@@ -1,0 +1,321 @@
+/*
+ * Plain, slow CPU oracle for the compressed key sort
+ * (Kwon et al., "Compressed Key Sort and Fast Index Reconstruction").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this file's library.  It shares no code,
+ * header, table or helper with the HIP library; both sides only see the same
+ * seeded input bytes.  Every routine favours being checkable by eye against the
+ * paper over being fast.
+ *
+ * Conventions (Sec. 3.1): a key is a string of bits; position 0 is the most
+ * significant bit of byte 0, position p lives in byte p/8 under mask
+ * 0x80 >> (p%8).  Variable-length keys are logically padded with zero bytes up
+ * to the key width L (Sec. 4.1, multi-column keys; varchar keys carry a NUL
+ * terminator which the zero padding supplies).  Record IDs are the row indices
+ * 0..n-1 (Sec. 5, step 2), so ties between equal keys go by row index.
+ */
+#define _GNU_SOURCE
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Key access                                                                 */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const uint8_t  *bytes;
+    const uint64_t *offsets; /* NULL: fixed width, key i at bytes + i*stride */
+    uint64_t n;
+    uint32_t L;
+    uint32_t stride;
+} keyset;
+
+/* Pointer to key i and its stored length (<= L for variable-length keys). */
+static const uint8_t *key_ptr(const keyset *k, uint64_t i, uint32_t *len)
+{
+    if (k->offsets) {
+        *len = (uint32_t)(k->offsets[i + 1] - k->offsets[i]);
+        return k->bytes + k->offsets[i];
+    }
+    *len = k->L;
+    return k->bytes + i * (uint64_t)k->stride;
+}
+
+/* Byte j of key i, zero past the stored length (Sec. 4.1 zero padding). */
+static uint8_t key_byte(const keyset *k, uint64_t i, uint32_t j)
+{
+    uint32_t len;
+    const uint8_t *p = key_ptr(k, i, &len);
+    return j < len ? p[j] : 0;
+}
+
+/* Bit at position p (MSB-first) of key i. */
+static int key_bit(const keyset *k, uint64_t i, uint32_t p)
+{
+    return (key_byte(k, i, p >> 3) >> (7 - (p & 7))) & 1;
+}
+
+/* Lexicographic comparison of the zero-padded L-byte strings. */
+static int key_cmp(const keyset *k, uint64_t a, uint64_t b)
+{
+    for (uint32_t j = 0; j < k->L; ++j) {
+        uint8_t x = key_byte(k, a, j), y = key_byte(k, b, j);
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+/* D-bit(a, b): the most significant position where keys a and b differ
+ * (Sec. 3.1), or -1 when they are equal. */
+static int64_t key_dbit(const keyset *k, uint64_t a, uint64_t b)
+{
+    for (uint32_t j = 0; j < k->L; ++j) {
+        uint8_t x = key_byte(k, a, j) ^ key_byte(k, b, j);
+        if (x) {
+            int hb = 7;
+            while (!((x >> hb) & 1)) --hb;
+            return (int64_t)j * 8 + (7 - hb);
+        }
+    }
+    return -1;
+}
+
+static void set_bit(uint8_t *bitmap, uint32_t p) { bitmap[p >> 3] |= (uint8_t)(0x80u >> (p & 7)); }
+static int get_bit(const uint8_t *bitmap, uint32_t p) { return (bitmap[p >> 3] >> (7 - (p & 7))) & 1; }
+
+/* ------------------------------------------------------------------------- */
+/* Full-key sort: the order that compressed key sort must reproduce.          */
+/* ------------------------------------------------------------------------- */
+
+static int cmp_full(const void *pa, const void *pb, void *ctx)
+{
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    int c = key_cmp((const keyset *)ctx, a, b);
+    if (c) return c;
+    return a < b ? -1 : (a > b); /* record ID tie-break (Sec. 5, step 2) */
+}
+
+/* perm[r] = row of the r-th smallest (key, row) pair. */
+int oracle_full_sort(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                     uint32_t L, uint32_t stride, uint32_t *perm)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    qsort_r(perm, n, sizeof(uint32_t), cmp_full, &k);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Distinction bits (Sec. 3.1, Theorem 1): union over adjacent sorted pairs.  */
+/* ------------------------------------------------------------------------- */
+
+/* bitmap (L bytes) receives D = { D-bit(key[perm[i-1]], key[perm[i]]) }.
+ * Equal adjacent keys contribute nothing.  Returns 1 if some adjacent pair
+ * is in descending order (the earlier key has a 1 at the D position), else 0. */
+int oracle_dbits(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                 uint32_t L, uint32_t stride, const uint32_t *perm, uint8_t *bitmap)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    int descending = 0;
+    memset(bitmap, 0, L);
+    for (uint64_t i = 1; i < n; ++i) {
+        uint64_t a = perm ? perm[i - 1] : i - 1, b = perm ? perm[i] : i;
+        int64_t p = key_dbit(&k, a, b);
+        if (p < 0) continue;
+        if (key_bit(&k, a, (uint32_t)p)) descending = 1;
+        set_bit(bitmap, (uint32_t)p);
+    }
+    return descending;
+}
+
+/* D-bit of an arbitrary pair of rows; -1 if equal.  Used by the Lemma 1 pin. */
+int64_t oracle_dbit_pair(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                         uint32_t L, uint32_t stride, uint64_t a, uint64_t b)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    return key_dbit(&k, a, b);
+}
+
+/* ------------------------------------------------------------------------- */
+/* D-offset (Sec. 5.3): D-offset[c] = position of the (c+1)-st 1 in the map.  */
+/* ------------------------------------------------------------------------- */
+
+uint32_t oracle_doffset(const uint8_t *bitmap, uint32_t L, uint32_t *doff)
+{
+    uint32_t c = 0;
+    for (uint32_t p = 0; p < 8 * L; ++p)
+        if (get_bit(bitmap, p)) {
+            if (doff) doff[c] = p;
+            ++c;
+        }
+    return c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Compress (Sec. 3.2): the key's bits at the bitmap's 1-positions, in        */
+/* ascending position order.  The string is stored left-aligned, MSB first,  */
+/* in w = ceil(|D|/64) 64-bit words, word-major: ckeys[k*n + i] is word k of */
+/* row i; bits past |D| are zero.                                             */
+/* ------------------------------------------------------------------------- */
+
+/* Bit-by-bit definition. */
+int oracle_compress(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                    uint32_t L, uint32_t stride, const uint8_t *bitmap,
+                    uint32_t w, uint64_t *ckeys)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    memset(ckeys, 0, sizeof(uint64_t) * (size_t)w * n);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t c = 0;
+        for (uint32_t p = 0; p < 8 * L; ++p) {
+            if (!get_bit(bitmap, p)) continue;
+            if ((c >> 6) >= w) return -1;
+            if (key_bit(&k, i, p))
+                ckeys[(uint64_t)(c >> 6) * n + i] |= 1ull << (63 - (c & 63));
+            ++c;
+        }
+    }
+    return 0;
+}
+
+/* The extraction procedure of Sec. 5.1: cut the bitmap into 8-byte masks,
+ * each starting at the byte holding the next 1 not yet covered; pull each
+ * key's bits under a mask into the low-order end of a word (the effect of a
+ * PEXT, here done one bit at a time); join the pieces by shift and OR. */
+uint32_t oracle_windows(const uint8_t *bitmap, uint32_t L, uint32_t *start, uint64_t *mask)
+{
+    uint32_t nw = 0, j = 0;
+    while (j < L) {
+        if (!bitmap[j]) { ++j; continue; }
+        uint64_t m = 0;
+        for (uint32_t t = 0; t < 8; ++t) m = (m << 8) | (j + t < L ? bitmap[j + t] : 0);
+        if (start) start[nw] = j;
+        if (mask) mask[nw] = m;
+        ++nw;
+        j += 8;
+    }
+    return nw;
+}
+
+static uint64_t soft_pext(uint64_t v, uint64_t m, uint32_t *cnt)
+{
+    uint64_t r = 0;
+    uint32_t c = 0;
+    for (int b = 63; b >= 0; --b)
+        if ((m >> b) & 1) { r = (r << 1) | ((v >> b) & 1); ++c; }
+    *cnt = c;
+    return r;
+}
+
+int oracle_compress_windows(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                            uint32_t L, uint32_t stride, const uint8_t *bitmap,
+                            uint32_t w, uint64_t *ckeys)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    uint32_t nwin = oracle_windows(bitmap, L, NULL, NULL);
+    uint32_t *st = (uint32_t *)malloc(sizeof(uint32_t) * (nwin + 1));
+    uint64_t *mk = (uint64_t *)malloc(sizeof(uint64_t) * (nwin + 1));
+    oracle_windows(bitmap, L, st, mk);
+    memset(ckeys, 0, sizeof(uint64_t) * (size_t)w * n);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t c = 0; /* bits emitted so far */
+        for (uint32_t q = 0; q < nwin; ++q) {
+            uint64_t v = 0;
+            for (uint32_t t = 0; t < 8; ++t) v = (v << 8) | key_byte(&k, i, st[q] + t);
+            uint32_t cnt;
+            uint64_t piece = soft_pext(v, mk[q], &cnt);
+            /* shift-and-OR the cnt-bit piece onto the running string */
+            for (int b = (int)cnt - 1; b >= 0; --b, ++c) {
+                if ((c >> 6) >= w) { free(st); free(mk); return -1; }
+                if ((piece >> b) & 1) ckeys[(uint64_t)(c >> 6) * n + i] |= 1ull << (63 - (c & 63));
+            }
+        }
+    }
+    free(st);
+    free(mk);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Sort of compressed keys (Sec. 3.2): order by the compressed strings, then  */
+/* by record ID.                                                              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { const uint64_t *ck; uint32_t w; uint64_t n; } ckset;
+
+static int cmp_comp(const void *pa, const void *pb, void *ctx)
+{
+    const ckset *s = (const ckset *)ctx;
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    for (uint32_t k = 0; k < s->w; ++k) {
+        uint64_t x = s->ck[(uint64_t)k * s->n + a], y = s->ck[(uint64_t)k * s->n + b];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return a < b ? -1 : (a > b);
+}
+
+int oracle_csort(const uint64_t *ckeys, uint32_t w, uint64_t n, uint32_t *perm)
+{
+    ckset s = {ckeys, w, n};
+    for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    qsort_r(perm, n, sizeof(uint32_t), cmp_comp, &s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* DS-metadata refresh at rebuild (Sec. 4.3): distinction positions of the    */
+/* adjacent sorted compressed keys, mapped back to full-key positions via     */
+/* D-offset (Sec. 5.3).                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* ckeys: word-major, in row order; perm: the sorted order.  bitmap_out (L
+ * bytes) receives the new D-bitmap; pair_pos[i-1] (optional) the full-key
+ * D position of sorted pair (i-1, i), 0xFFFFFFFF when the compressed keys are
+ * equal.  Returns -1 if a D index falls outside the bitmap's 1-positions. */
+int oracle_refine(const uint64_t *ckeys, uint32_t w, uint64_t n, const uint32_t *perm,
+                  const uint8_t *bitmap_in, uint32_t L, uint8_t *bitmap_out, uint32_t *pair_pos)
+{
+    uint32_t nd = oracle_doffset(bitmap_in, L, NULL);
+    uint32_t *doff = (uint32_t *)malloc(sizeof(uint32_t) * (nd + 1));
+    oracle_doffset(bitmap_in, L, doff);
+    memset(bitmap_out, 0, L);
+    for (uint64_t i = 1; i < n; ++i) {
+        uint64_t a = perm[i - 1], b = perm[i];
+        int64_t c = -1;
+        for (uint32_t k = 0; k < w && c < 0; ++k) {
+            uint64_t x = ckeys[(uint64_t)k * n + a] ^ ckeys[(uint64_t)k * n + b];
+            if (x) {
+                int lead = 0;
+                while (!((x >> (63 - lead)) & 1)) ++lead;
+                c = (int64_t)k * 64 + lead;
+            }
+        }
+        if (c < 0) {
+            if (pair_pos) pair_pos[i - 1] = 0xFFFFFFFFu;
+            continue;
+        }
+        if ((uint64_t)c >= nd) { free(doff); return -1; }
+        set_bit(bitmap_out, doff[c]);
+        if (pair_pos) pair_pos[i - 1] = doff[c];
+    }
+    free(doff);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Variant bitmap and reference key (Sec. 4.2-4.3).                           */
+/* ------------------------------------------------------------------------- */
+
+/* variant (L bytes) = OR over all keys of (key XOR reference), with the
+ * reference key taken as row ref_row. */
+int oracle_variant(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                   uint32_t L, uint32_t stride, uint64_t ref_row, uint8_t *variant)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    memset(variant, 0, L);
+    for (uint64_t i = 0; i < n; ++i)
+        for (uint32_t j = 0; j < L; ++j) variant[j] |= key_byte(&k, i, j) ^ key_byte(&k, ref_row, j);
+    return 0;
+}

@@ -1,0 +1,121 @@
+"""Seeded synthetic index keys.
+
+Inputs only: nothing here computes distinction bits, compressed keys or sort
+orders.  The same bytes feed the HIP library and the CPU oracle.  Randomness
+comes from numpy's PCG64 generator seeded per workload.
+
+Key formats follow the paper's index key format (Sec. 4.1): fixed strings as
+they are, signed integers big-endian with the sign bit flipped so that byte
+order equals numeric order, varchar keys zero-padded (the first pad byte is the
+NUL terminator), multi-column keys concatenated.
+"""
+import numpy as np
+
+ACGT = np.frombuffer(b"ACGT", dtype=np.uint8).copy()
+_ACGT_CODE = np.zeros(256, np.uint8)
+_ACGT_CODE[ACGT] = np.arange(4, dtype=np.uint8)
+
+
+def rng_for(seed):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------- encoders --
+
+def encode_i32(v):
+    """int32 values -> (n, 4) big-endian bytes with the sign bit toggled."""
+    u = (np.asarray(v, np.int64).astype(np.uint32) ^ np.uint32(0x80000000)).astype(">u4")
+    return u.view(np.uint8).reshape(-1, 4)
+
+
+def encode_i64(v):
+    """int64 values -> (n, 8) big-endian bytes with the sign bit toggled."""
+    u = (np.asarray(v, np.int64).view(np.uint64) ^ np.uint64(1 << 63)).astype(">u8")
+    return u.view(np.uint8).reshape(-1, 8)
+
+
+def zipf_sampler(rng, s, K, size):
+    """Ranks 0..K-1 with P(rank r) proportional to (r+1)^-s (inverse CDF)."""
+    w = np.arange(1, K + 1, dtype=np.float64) ** (-float(s))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.random(size)
+    return np.minimum(np.searchsorted(cdf, u, side="right"), K - 1)
+
+
+# ------------------------------------------------------------ workloads --
+
+def uniform_prefix_keys(n=1 << 20, seed=1, key_bytes=16, prefix_bytes=6):
+    """16-byte binary keys: a fixed seeded prefix (bytes 0-5), the rest
+    uniform (2^20 rows by default)."""
+    rng = rng_for(seed)
+    prefix = rng.integers(0, 256, prefix_bytes, dtype=np.uint8)
+    keys = np.empty((n, key_bytes), np.uint8)
+    keys[:, :prefix_bytes] = prefix
+    keys[:, prefix_bytes:] = rng.integers(0, 256, (n, key_bytes - prefix_bytes), dtype=np.uint8)
+    return keys
+
+
+def dna_window_keys(n=1 << 26, seed=1, key_bytes=64, seq_len=1 << 27, p_mut=0.01):
+    """64-byte ASCII keys over {A,C,G,T}: windows at uniform offsets into one
+    seeded uniform sequence of 2^27 bases; each window position is then
+    independently, with probability ``p_mut``, replaced by one of the other
+    three bases chosen uniformly."""
+    rng = rng_for(seed)
+    seq = ACGT[rng.integers(0, 4, seq_len, dtype=np.uint8)]
+    offs = rng.integers(0, seq_len - key_bytes + 1, n)
+    win = np.lib.stride_tricks.sliding_window_view(seq, key_bytes)
+    keys = win[offs]
+    flat = keys.reshape(-1)
+    total = flat.size
+    if p_mut > 0 and total:
+        pos_parts = []
+        last = -1
+        while True:
+            m = int(total * p_mut * 1.05) + 1024
+            gaps = rng.geometric(p_mut, size=m).astype(np.int64)
+            pos = last + np.cumsum(gaps)
+            pos_parts.append(pos[pos < total])
+            if pos[-1] >= total:
+                break
+            last = int(pos[-1])
+        pos = np.concatenate(pos_parts)
+        shift = rng.integers(1, 4, pos.size, dtype=np.uint8)
+        flat[pos] = ACGT[(_ACGT_CODE[flat[pos]] + shift) & 3]
+    return keys
+
+
+def uniform_keys(n=1 << 28, seed=1, key_bytes=32):
+    """Uniform random bytes, ``key_bytes`` per row."""
+    rng = rng_for(seed)
+    return np.frombuffer(rng.bytes(n * key_bytes), np.uint8).reshape(n, key_bytes).copy()
+
+
+def cluster_keys(n=1 << 28, seed=1, key_bytes=32, clusters=1 << 16):
+    """Rows drawn from ``clusters`` random (key_bytes-1)-byte stems, each row's
+    cluster uniform, its last byte uniform."""
+    rng = rng_for(seed)
+    stems = rng.integers(0, 256, (clusters, key_bytes - 1), dtype=np.uint8)
+    cid = rng.integers(0, clusters, n)
+    keys = np.empty((n, key_bytes), np.uint8)
+    keys[:, : key_bytes - 1] = stems[cid]
+    keys[:, key_bytes - 1] = rng.integers(0, 256, n, dtype=np.uint8)
+    return keys
+
+
+def random_small_keys(n, key_bytes, seed, alphabet=None):
+    """Tiny test sets: bytes from ``alphabet`` (default all 256 values)."""
+    rng = rng_for(seed)
+    if alphabet is None:
+        return rng.integers(0, 256, (n, key_bytes), dtype=np.uint8)
+    alphabet = np.asarray(alphabet, np.uint8)
+    return alphabet[rng.integers(0, len(alphabet), (n, key_bytes))]
+
+
+def pack_varlen(rows, lengths):
+    """(n, W) zero-padded rows + lengths -> (flat bytes, uint64 offsets[n+1])."""
+    lengths = np.asarray(lengths, np.int64)
+    offsets = np.zeros(len(lengths) + 1, np.uint64)
+    np.cumsum(lengths, out=offsets[1:])
+    mask = np.arange(rows.shape[1])[None, :] < lengths[:, None]
+    return np.ascontiguousarray(rows[mask]), offsets

@@ -1,0 +1,336 @@
+"""Pins of the CPU oracle against what the paper and plain mathematics fix.
+
+Each check here is computed independently of the oracle's C code (Python
+integers, Python's ``sorted``, numpy ``lexsort``, brute force) or comes from a
+value the paper prints.  The oracle is then trusted as the reference for the
+HIP library.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_11543_amd import datagen
+
+
+# ------------------------------------------------------------ independent --
+
+def as_int(row):
+    return int.from_bytes(bytes(row), "big")
+
+
+def dbit_int(a, b, L):
+    """D-bit via Python integers: 8L - bit_length(a xor b); None if equal."""
+    x = as_int(a) ^ as_int(b)
+    return None if x == 0 else 8 * L - x.bit_length()
+
+
+def py_sorted_perm(rows):
+    return [i for _, i in sorted((bytes(r), i) for i, r in enumerate(rows))]
+
+
+def bits_at(row, positions, L):
+    v = as_int(row)
+    return "".join(str((v >> (8 * L - 1 - p)) & 1) for p in positions)
+
+
+def bitmap_from_positions(positions, L):
+    bm = np.zeros(L, np.uint8)
+    for p in positions:
+        bm[p >> 3] |= 0x80 >> (p & 7)
+    return bm
+
+
+def positions_of(bm):
+    L = len(bm)
+    v = as_int(bm)
+    return [p for p in range(8 * L) if (v >> (8 * L - 1 - p)) & 1]
+
+
+# ---------------------------------------------------------------- golden --
+
+def load(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        return json.load(f)
+
+
+def test_constructed_dbit_example(golden_dir):
+    """Sec. 3.1 / 3.2 / 4.2 statements, on the constructed key set."""
+    g = load(golden_dir, "fig_dbit_constructed.json")
+    rows = np.array([list(bytes.fromhex(h)) for h in g["keys_hex"]], np.uint8)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    assert list(perm) == list(range(len(rows)))  # listed in sorted order
+    bm, desc = O.dbits(k, perm)
+    assert not desc
+    assert bm.tobytes().hex().upper() == g["dbitmap_hex"]
+    adj = [O.dbit_pair(k, i - 1, i) for i in range(1, len(rows))]
+    assert adj == g["adjacent_dbits"]
+    for a, b, d in g["dbit_pairs"]:
+        assert O.dbit_pair(k, a, b) == d
+    assert O.variant(k, 0).tobytes().hex().upper() == g["variant_bitmap_hex"]
+    ck = O.compress(k, bm)
+    assert ck.shape == (1, 6)
+    got = [format(int(c) >> 60, "04b") for c in ck[0]]
+    assert got == g["compress_bits"]
+    # partial key of key_1: the pk bits following D_1 (Sec. 4.2)
+    d1 = adj[0]
+    assert bits_at(rows[1], range(d1 + 1, d1 + 5), 2) == g["partial_key_key1_pk4"]
+    # invariant positions among the 12 key bits are the variant bitmap's zeros
+    var = positions_of(O.variant(k, 0))
+    assert sorted(set(range(12)) - set(var)) == [0, 3, 4, 8, 9, 10]
+    assert sorted(set(var) - set(positions_of(bm))) == [6, 11]
+
+
+def test_remark1_nonminimal(golden_dir):
+    """Remark 1: D is sufficient but not minimal; brute force over subsets."""
+    g = load(golden_dir, "remark1_constructed.json")
+    rows = np.array([[int(b, 2) << 4] for b in g["keys_bits"]], np.uint8)
+    k = O.Keys(rows)
+    bm, _ = O.dbits(k, O.full_sort(k))
+    assert positions_of(bm) == g["dbits"]
+    best = None
+    for size in range(1, 5):
+        for sub in itertools.combinations(range(4), size):
+            sl = [bits_at(r, sub, 1) for r in rows]
+            if all(sl[i] < sl[i + 1] for i in range(len(sl) - 1)):
+                best = list(sub) if best is None else best
+        if best is not None:
+            break
+    assert best == g["minimal_subset"]
+    assert len(best) < len(g["dbits"])
+
+
+def test_varchar_nul_dbit():
+    """Sec. 4.1 C: AB<NUL> vs ABA<NUL>: the D-bit falls in the shorter key's NUL."""
+    flat = np.frombuffer(b"AB\x00ABA\x00", np.uint8)
+    offs = np.array([0, 3, 7], np.uint64)
+    k = O.Keys(flat, L=8, offsets=offs)
+    assert list(O.full_sort(k)) == [0, 1]
+    assert O.dbit_pair(k, 0, 1) == 17
+    assert 16 <= 17 < 24  # byte 2 = the NUL of "AB"
+    # and with the NUL omitted, zero padding supplies it (Sec. 4.1, multi-column padding)
+    k2 = O.Keys(np.frombuffer(b"ABABA", np.uint8), L=8, offsets=np.array([0, 2, 5], np.uint64))
+    assert O.dbit_pair(k2, 0, 1) == 17
+
+
+def test_table3_bitmap_and_windows(golden_dir):
+    g = load(golden_dir, "table3_indbtab_dbitmap.json")
+    bm = np.array([int(b, 2) for b in g["bytes_1_to_35"]], np.uint8)
+    assert len(bm) == g["key_bytes"]
+    pos = O.doffset(bm)
+    assert len(pos) == g["distinction_bits_table2"]
+    assert max(pos) // 8 + 1 == g["last_distinction_byte_1based"]
+    assert math.ceil(len(pos) / 8) <= g["compressed_bytes_at_most"]
+    assert O.nwords(bm) == 1
+    st, mk = O.windows(bm)
+    w = g["windows_sec51_rule"]
+    assert list(st) == w["start_bytes_0based"]
+    assert [format(int(m), "016x") for m in mk] == w["masks_hex"]
+    assert [bin(int(m)).count("1") for m in mk] == w["popcounts"]
+    bits = len(pos) + g["rid_variant_bits_table2"]
+    assert math.ceil(bits / 64) * 8 == g["compressed_sort_key_bytes_table2"]
+
+
+def sort_key_bytes(key_bits, rid_bits):
+    """Sort key size in 8-byte words (Sec. 6.2)."""
+    return math.ceil((key_bits + rid_bits) / 64) * 8
+
+
+def test_table2_arithmetic(golden_dir):
+    g = load(golden_dir, "table2_dataset_stats.json")
+    cr, skr, share = [], [], []
+    for i, _ in enumerate(g["datasets"]):
+        fb = g["full_key_bits"][i]
+        assert fb == 8 * g["max_key_bytes"][i]
+        full = sort_key_bytes(fb, 8 * g["rid_bytes"])
+        comp = sort_key_bytes(g["distinction_bits"][i], g["rid_variant_bits"][i])
+        assert full == g["full_sort_key_bytes"][i]
+        assert comp == g["compressed_sort_key_bytes"][i]
+        cr.append(fb / g["distinction_bits"][i])
+        skr.append(full / comp)
+        share.append(g["distinction_bits"][i] / fb)
+        assert round(cr[-1] + 1e-9, 2) == pytest.approx(g["compression_ratio"][i], abs=0.006)
+        assert round(skr[-1], 2) == pytest.approx(g["sort_key_ratio"][i], abs=0.006)
+    assert round(sum(cr) / 6, 2) == g["avg_compression_ratio"]
+    assert round(sum(skr) / 6, 2) == g["avg_sort_key_ratio"]
+    assert round(100 * sum(share) / 6, 1) == g["avg_distinction_share_percent"]
+
+
+# ------------------------------------------------------- invariants & brute --
+
+@pytest.mark.parametrize("seed", range(6))
+def test_theorem1_all_pairs(seed):
+    """Theorem 1: D over all pairs == D over adjacent sorted pairs."""
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(1, 5))
+    n = int(rng.integers(2, 200))
+    alphabet = None if seed % 2 else rng.integers(0, 256, 3)
+    rows = datagen.random_small_keys(n, L, seed, alphabet)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    assert list(perm) == py_sorted_perm(rows)
+    bm, desc = O.dbits(k, perm)
+    assert not desc
+    d_all = {dbit_int(rows[a], rows[b], L) for a in range(n) for b in range(a + 1, n)} - {None}
+    assert set(positions_of(bm)) == d_all
+    assert len(d_all) <= n - 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lemma1_min_over_adjacent(seed):
+    rows = datagen.random_small_keys(40, 2, seed, [0, 1, 2, 0x80, 0xC3])
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    srt = rows[perm]
+    uniq = [srt[0]]
+    for r in srt[1:]:
+        if bytes(r) != bytes(uniq[-1]):
+            uniq.append(r)
+    adj = [dbit_int(uniq[i - 1], uniq[i], 2) for i in range(1, len(uniq))]
+    for i in range(len(uniq)):
+        for j in range(i + 1, len(uniq)):
+            assert dbit_int(uniq[i], uniq[j], 2) == min(adj[i:j])
+
+
+def test_insert_identity():
+    """Sec. 4.3 insert: D-bit(A,B) = min(D-bit(A,K), D-bit(K,B)) for A < K < B."""
+    rng = np.random.default_rng(7)
+    for _ in range(2000):
+        trio = sorted({bytes(rng.integers(0, 256, 3, dtype=np.uint8)) for _ in range(3)})
+        if len(trio) < 3:
+            continue
+        a, kk, b = (np.frombuffer(t, np.uint8) for t in trio)
+        rows = np.stack([a, kk, b])
+        k = O.Keys(rows)
+        dab, dak, dkb = O.dbit_pair(k, 0, 2), O.dbit_pair(k, 0, 1), O.dbit_pair(k, 1, 2)
+        assert dab == min(dak, dkb) == dbit_int(a, b, 3)
+        assert dak != dkb
+
+
+def test_theorem2_every_permutation():
+    """Theorem 2 by brute force: every input order of a tiny set with
+    duplicates gives the same permutation through compressed keys as through
+    full keys, for D and for supersets of D."""
+    base = np.array([[0x12, 0x34], [0x12, 0x35], [0x52, 0x34], [0x12, 0x34],
+                     [0x13, 0x00], [0xF0, 0x0F], [0x52, 0x34]], np.uint8)
+    d_true, _ = O.dbits(O.Keys(base), O.full_sort(O.Keys(base)))
+    supersets = [d_true, np.full(2, 0xFF, np.uint8), d_true | np.array([0x01, 0x80], np.uint8)]
+    for order in itertools.permutations(range(len(base))):
+        rows = base[list(order)]
+        k = O.Keys(rows)
+        pf = O.full_sort(k)
+        assert list(pf) == py_sorted_perm(rows)
+        for bm in supersets:
+            pc = O.csort(O.compress(k, bm))
+            assert list(pc) == list(pf)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_compress_matches_python_and_windows(seed):
+    rng = np.random.default_rng(100 + seed)
+    L = int(rng.integers(1, 40))
+    n = 64
+    rows = datagen.random_small_keys(n, L, seed)
+    positions = sorted(set(rng.integers(0, 8 * L, int(rng.integers(1, 8 * L + 1))).tolist()))
+    bm = bitmap_from_positions(positions, L)
+    k = O.Keys(rows)
+    ck = O.compress(k, bm)
+    ckw = O.compress_windows(k, bm)
+    np.testing.assert_array_equal(ck, ckw)
+    w = ck.shape[0]
+    assert w == max(1, math.ceil(len(positions) / 64))
+    for i in range(n):
+        s = bits_at(rows[i], positions, L).ljust(64 * w, "0")
+        for kk in range(w):
+            assert int(ck[kk, i]) == int(s[64 * kk: 64 * kk + 64], 2)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_csort_matches_lexsort(seed):
+    rng = np.random.default_rng(seed)
+    w, n = 3, 3000
+    ck = rng.integers(0, 4, (w, n), dtype=np.uint64) << np.uint64(62)
+    perm = O.csort(ck)
+    # numpy lexsort: last key is primary; rid (index) is the final tie-break
+    ref = np.lexsort((np.arange(n),) + tuple(ck[k] for k in reversed(range(w))))
+    np.testing.assert_array_equal(perm, ref)
+
+
+def test_full_sort_matches_lexsort_words():
+    rows = datagen.dna_window_keys(4096, 3, seq_len=1 << 13)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    words = rows.view(">u8").astype(np.uint64)
+    ref = np.lexsort((np.arange(len(rows)),) + tuple(words[:, j] for j in reversed(range(8))))
+    np.testing.assert_array_equal(perm, ref)
+    assert list(perm) == py_sorted_perm(rows)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_refine_returns_true_d(seed):
+    """Sec. 4.3 rebuild: any superset bitmap refines to the true D."""
+    rows = datagen.random_small_keys(500, 6, seed, [0x00, 0x41, 0x43, 0x47, 0x54, 0xFF])
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    srt = [bytes(r) for r in rows[perm]]
+    d_true = {dbit_int(np.frombuffer(srt[i - 1], np.uint8), np.frombuffer(srt[i], np.uint8), 6)
+              for i in range(1, len(srt))} - {None}
+    bm_true = bitmap_from_positions(sorted(d_true), 6)
+    rng = np.random.default_rng(seed)
+    cands = [bm_true, np.full(6, 0xFF, np.uint8), O.variant(k, 3),
+             bm_true | rng.integers(0, 256, 6, dtype=np.uint8)]
+    for bm in cands:
+        ck = O.compress(k, bm)
+        pc = O.csort(ck)
+        assert list(pc) == list(perm)
+        new, pos = O.refine(ck, pc, bm)
+        np.testing.assert_array_equal(new, bm_true)
+        for i in range(1, len(srt)):
+            d = dbit_int(np.frombuffer(srt[i - 1], np.uint8), np.frombuffer(srt[i], np.uint8), 6)
+            assert int(pos[i - 1]) == (0xFFFFFFFF if d is None else d)
+
+
+def test_descending_flag():
+    rows = np.array([[5], [3], [9]], np.uint8)
+    _, desc = O.dbits(O.Keys(rows), None)
+    assert desc
+    _, desc = O.dbits(O.Keys(rows), np.array([1, 0, 2], np.uint32))
+    assert not desc
+
+
+def test_dna_bit_structure():
+    """A=0x41, C=0x43, G=0x47, T=0x54 first differ at in-byte positions 3, 5, 6;
+    Table 2's Human set (DNA, 101-byte keys) has 303 = 3 x 101 distinction bits."""
+    codes = [0x41, 0x43, 0x47, 0x54]
+    per_byte = {dbit_int([a], [b], 1) for a in codes for b in codes if a < b}
+    assert per_byte == {3, 5, 6}
+    assert 303 == 3 * 101
+    rows = datagen.dna_window_keys(1 << 15, 1, seq_len=1 << 16)
+    k = O.Keys(rows)
+    bm, desc = O.dbits(k, O.full_sort(k))
+    assert not desc
+    pos = positions_of(bm)
+    assert {p % 8 for p in pos} <= {3, 5, 6}
+    assert len(pos) == 192
+
+
+def test_varlen_matches_padded():
+    rng = np.random.default_rng(5)
+    n, L = 300, 12
+    lens = rng.integers(0, L, n)
+    rows = rng.choice(np.frombuffer(b"ab", np.uint8), (n, L))
+    rows[np.arange(L)[None, :] >= lens[:, None]] = 0
+    flat, offs = datagen.pack_varlen(rows, lens)
+    kv = O.Keys(flat, L=L, offsets=offs)
+    kf = O.Keys(rows)
+    pv, pf = O.full_sort(kv), O.full_sort(kf)
+    np.testing.assert_array_equal(pv, pf)
+    bv, _ = O.dbits(kv, pv)
+    bf, _ = O.dbits(kf, pf)
+    np.testing.assert_array_equal(bv, bf)
+    np.testing.assert_array_equal(O.compress(kv, bv), O.compress(kf, bf))
