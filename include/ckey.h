@@ -1,0 +1,158 @@
+/*
+ * ckey.h -- C ABI of libckey.so: compressed key sort on AMD MI355X (gfx950).
+ *
+ * Method: Kwon, Ryu, Cha, Lee, Park, Moon, "Compressed Key Sort and Fast Index
+ * Reconstruction" (arXiv 2009.11543).
+ *
+ * Bit conventions (Sec. 3.1): a key is a string of key_bytes bytes read as a
+ * bit string; position 0 is the most significant bit of byte 0, position p is
+ * bit (7 - p%8) of byte p/8.  Variable-length keys are zero-padded to
+ * key_bytes (Sec. 4.1: the varchar terminator and multi-column padding).
+ * A D-bitmap is key_bytes bytes in the same bit order: bit p set means
+ * "position p is (possibly) a distinction bit position" (Sec. 4.2).
+ *
+ * Compressed keys (Sec. 3.2): the key's bits at the bitmap's 1-positions in
+ * ascending position order, packed most significant bit first into
+ * w = ceil(nbits/64) 64-bit words (word 0 most significant; bits past nbits
+ * are zero), stored word-major: ckeys[k*n + i] is word k of row i.
+ *
+ * Memory: every pointer marked "device" is device memory owned by the caller;
+ * "host" pointers are read during the call only.  The library never allocates
+ * or frees memory: calls that need scratch space take a caller workspace
+ * (device, 256-byte aligned) sized by a query call with workspace == NULL,
+ * which only writes *workspace_bytes and returns CKEY_OK.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
+ * validates its arguments on the host, returns a status synchronously and
+ * enqueues its kernels asynchronously on `stream`; results are ready when the
+ * stream is.  Conditions only the device can see are OR-ed into an optional
+ * device uint32 `flags` word (CKEY_FLAG_*), which the caller clears.
+ * Calls are reentrant; two calls that share a workspace must be ordered.
+ */
+#ifndef CKEY_H
+#define CKEY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CKEY_OK = 0,
+    CKEY_ERR_INVALID = 1,     /* null pointer, size out of range, bad bitmap   */
+    CKEY_ERR_UNSUPPORTED = 2, /* valid request beyond this library's limits    */
+    CKEY_ERR_WORKSPACE = 3,   /* *workspace_bytes smaller than required        */
+    CKEY_ERR_HIP = 4          /* a HIP runtime call or kernel launch failed    */
+} ckey_status;
+
+/* Device-side conditions, OR-ed into the caller's flags word. */
+#define CKEY_FLAG_DESCENDING   0x1u /* ckey_distinction_bits: an adjacent pair descends     */
+#define CKEY_FLAG_KEY_TOO_LONG 0x2u /* a variable-length key is longer than key_bytes       */
+#define CKEY_FLAG_SPIN_LIMIT   0x4u /* a sort pass gave up waiting on a predecessor tile    */
+#define CKEY_FLAG_BUCKET_OVERFLOW 0x8u /* learned sort: some bucket went to the radix fallback */
+
+/* Limits of this build. */
+#define CKEY_MAX_KEY_BYTES 2048u          /* key_bytes                       */
+#define CKEY_MAX_ROWS (1ull << 30)        /* n                               */
+
+/* A set of n keys in device memory.
+ *   offsets == NULL: fixed width; key i occupies bytes[i*stride, i*stride+key_bytes).
+ *   offsets != NULL: variable length; offsets is device uint64[n+1], key i is
+ *                    bytes[offsets[i], offsets[i+1]) and must be <= key_bytes long
+ *                    (longer keys set CKEY_FLAG_KEY_TOO_LONG); stride is ignored.
+ * Row i's record ID is i (Sec. 5, step 2). */
+typedef struct {
+    const uint8_t *bytes;
+    const uint64_t *offsets;
+    uint64_t n;
+    uint32_t key_bytes;
+    uint32_t stride;
+} ckey_keys;
+
+/* Host-only planning of the extraction (Sec. 5.1 and Sec. 5.3).
+ * bitmap: host, key_bytes bytes.  Writes nbits = |D| (popcount), words =
+ * max(1, ceil(nbits/64)) and the number of Sec. 5.1 8-byte masks (each starts
+ * at the byte holding the next 1 not covered by the previous mask).  If
+ * window_start/window_mask are non-NULL, up to max_windows (start byte,
+ * big-endian 64-bit mask) pairs are written.  Touches no GPU. */
+ckey_status ckey_plan_query(const uint8_t *bitmap, uint32_t key_bytes, uint32_t *nbits,
+                            uint32_t *words, uint32_t *windows, uint32_t *window_start,
+                            uint64_t *window_mask, uint32_t max_windows);
+
+/* Distinction bits of keys taken in sorted order (Sec. 3.1, Theorem 1):
+ * bitmap (device, key_bytes bytes, overwritten) = union over adjacent pairs of
+ * the most significant differing position.  order: device uint32[n] giving
+ * the sorted order (row order[r] has rank r), or NULL when the rows are
+ * already sorted.  Equal adjacent keys contribute nothing; a descending pair
+ * sets CKEY_FLAG_DESCENDING.  n <= 1 gives an empty bitmap.  Needs a workspace. */
+ckey_status ckey_distinction_bits(const ckey_keys *keys, const uint32_t *order, uint8_t *bitmap,
+                                  uint32_t *flags, void *workspace, size_t *workspace_bytes,
+                                  void *stream);
+
+/* Compress every key with a D-bitmap (Sec. 3.2, Sec. 5.1).  bitmap: host,
+ * key_bytes bytes, any superset of the keys' true distinction positions
+ * (Theorem 2 covers supersets).  ckeys: device uint64[words*n], words >=
+ * the plan's w (extra words are written as zero).  rowids: device uint32[n]
+ * receiving 0..n-1, or NULL.  No workspace. */
+ckey_status ckey_compress(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
+                          uint32_t words, uint32_t *rowids, uint32_t *flags, void *stream);
+
+typedef enum {
+    CKEY_SORT_RADIX = 0,   /* stable LSD radix sort over the top nbits                  */
+    CKEY_SORT_LEARNED = 1, /* CDF-model bucketing + in-LDS bucket sorts (needs a model) */
+    CKEY_SORT_SPLITTER = 2 /* the same bucketing with a binary search of the thresholds */
+} ckey_sort_method;
+
+typedef struct ckey_cdf_model ckey_cdf_model; /* opaque, see ckey_cdf_* below */
+
+typedef struct {
+    uint32_t method;      /* ckey_sort_method                                         */
+    uint32_t digit_bits;  /* radix digit width, 1..8; 0 = 8                          */
+    uint32_t bucket_log2; /* learned/splitter bucket count = 2^bucket_log2; 0 = model's */
+    uint32_t reserved;
+    const ckey_cdf_model *model; /* learned/splitter: trained model (thresholds + net)  */
+    uint32_t *flags;      /* device flags word or NULL                                */
+} ckey_sort_opts;
+
+/* Sort (compressed key, row id) pairs (Sec. 3.2 compressed key sort; Sec. 5,
+ * step 3) in place: afterwards ckeys (device, word-major, words x n) are in
+ * ascending order of their top nbits and rowids (device uint32[n]) moved with
+ * them.  The sort is stable, so with rowids = 0..n-1 (as ckey_compress
+ * writes them) ties are broken by row id, as in the paper's sort key.
+ * opts may be NULL (radix, 8-bit digits).  Needs a workspace. */
+ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
+                      uint64_t n, const ckey_sort_opts *opts, void *workspace,
+                      size_t *workspace_bytes, void *stream);
+
+/* One index to rebuild (Sec. 5 steps 2-3 and the DS-metadata refresh of Sec. 4.3). */
+typedef struct {
+    ckey_keys keys;
+    const uint8_t *bitmap_in; /* host, key_bytes bytes: current D-bitmap (any superset
+                                 of the true D); NULL = first build over full keys     */
+    uint32_t *perm;           /* device uint32[n] out: row ids in full-key order        */
+    uint8_t *bitmap_out;      /* device key_bytes bytes out: the refreshed D-bitmap, or NULL */
+    uint32_t *pair_pos;       /* device uint32[n-1] out or NULL: full-key D position of
+                                 each adjacent sorted pair (Sec. 5.3 D-offset lookup),
+                                 0xFFFFFFFF where the keys are equal                   */
+    uint64_t *ckeys;          /* device uint64[w*n] out or NULL: the sorted compressed keys */
+    uint32_t *flags;          /* device flags word or NULL                              */
+} ckey_index_desc;
+
+/* Rebuild `count` indexes: compress each with its bitmap, sort, and refresh its
+ * D-bitmap from adjacent sorted compressed keys.  opts as for ckey_sort
+ * (NULL = radix).  count > 1 enqueues all indexes' work as one batch.  Needs a
+ * workspace. */
+ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
+                               const ckey_sort_opts *opts, void *workspace,
+                               size_t *workspace_bytes, void *stream);
+
+/* Human-readable status name. */
+const char *ckey_status_string(ckey_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CKEY_H */

@@ -1,0 +1,253 @@
+"""Python binding of libckey.so (declared in include/ckey.h).
+
+Argument marshalling only: torch tensors supply device memory
+(``data_ptr()``) and ``torch.cuda.current_stream()`` supplies the stream;
+every step runs in the library's HIP kernels.  Importing this module fails
+if the library has not been built (``python -m paper_2009_11543_amd.build``).
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libckey.so")
+
+CKEY_OK, CKEY_ERR_INVALID, CKEY_ERR_UNSUPPORTED, CKEY_ERR_WORKSPACE, CKEY_ERR_HIP = range(5)
+CKEY_FLAG_DESCENDING = 0x1
+CKEY_FLAG_KEY_TOO_LONG = 0x2
+CKEY_FLAG_SPIN_LIMIT = 0x4
+CKEY_FLAG_BUCKET_OVERFLOW = 0x8
+CKEY_SORT_RADIX, CKEY_SORT_LEARNED, CKEY_SORT_SPLITTER = 0, 1, 2
+MAX_KEY_BYTES = 2048
+
+
+class CkeyError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__(f"{fn}: {status_string(status)} (status {status})")
+
+
+class ckey_keys(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("key_bytes", ctypes.c_uint32), ("stride", ctypes.c_uint32)]
+
+
+class ckey_sort_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
+                ("bucket_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("model", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+class ckey_index_desc(ctypes.Structure):
+    _fields_ = [("keys", ckey_keys), ("bitmap_in", ctypes.c_void_p), ("perm", ctypes.c_void_p),
+                ("bitmap_out", ctypes.c_void_p), ("pair_pos", ctypes.c_void_p),
+                ("ckeys", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_11543_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, U32, U64, SZP = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)
+    lib.ckey_status_string.argtypes = [ctypes.c_int]
+    lib.ckey_status_string.restype = ctypes.c_char_p
+    lib.ckey_plan_query.argtypes = [P, U32, P, P, P, P, P, U32]
+    lib.ckey_distinction_bits.argtypes = [ctypes.POINTER(ckey_keys), P, P, P, P, SZP, P]
+    lib.ckey_compress.argtypes = [ctypes.POINTER(ckey_keys), P, P, U32, P, P, P]
+    lib.ckey_sort.argtypes = [P, U32, U32, P, U64, ctypes.POINTER(ckey_sort_opts), P, SZP, P]
+    lib.ckey_rebuild_index.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
+                                       ctypes.POINTER(ckey_sort_opts), P, SZP, P]
+    for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
+               "ckey_rebuild_index"):
+        getattr(lib, fn).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def status_string(s):
+    return _lib.ckey_status_string(int(s)).decode()
+
+
+def _check(fn, status):
+    if status != CKEY_OK:
+        raise CkeyError(fn, status)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _host_bitmap(bitmap):
+    a = np.ascontiguousarray(np.asarray(bitmap, dtype=np.uint8))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+class DeviceKeys:
+    """Keys resident on the GPU.
+
+    Fixed width: ``data`` is a uint8 tensor of shape (n, stride) whose first
+    ``key_bytes`` bytes per row are the key.  Variable length: ``data`` is a
+    flat uint8 tensor and ``offsets`` an int64 tensor of n+1 byte offsets.
+    """
+
+    def __init__(self, data, key_bytes=None, offsets=None):
+        assert data.dtype == torch.uint8 and data.is_cuda and data.is_contiguous()
+        self.data = data
+        self.offsets = offsets
+        if offsets is None:
+            assert data.dim() == 2
+            self.n = data.shape[0]
+            self.stride = data.shape[1]
+            self.key_bytes = self.stride if key_bytes is None else key_bytes
+        else:
+            assert offsets.dtype == torch.int64 and offsets.is_cuda and key_bytes is not None
+            self.n = offsets.numel() - 1
+            self.stride = 0
+            self.key_bytes = key_bytes
+
+    @classmethod
+    def from_numpy(cls, arr, key_bytes=None, offsets=None, device="cuda"):
+        data = torch.from_numpy(np.ascontiguousarray(arr)).to(device)
+        off = None if offsets is None else torch.from_numpy(np.asarray(offsets, np.int64)).to(device)
+        return cls(data, key_bytes, off)
+
+    def c_struct(self):
+        return ckey_keys(self.data.data_ptr() if self.n else None,
+                         None if self.offsets is None else self.offsets.data_ptr(),
+                         self.n, self.key_bytes, self.stride)
+
+
+def _workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def ckey_plan_query(bitmap):
+    """Host-only plan: dict(nbits, words, windows=[(start_byte, mask), ...])."""
+    bm, p = _host_bitmap(bitmap)
+    nb, w, nw = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check("ckey_plan_query", _lib.ckey_plan_query(p, len(bm), ctypes.byref(nb), ctypes.byref(w),
+                                                   ctypes.byref(nw), None, None, 0))
+    st = np.zeros(max(nw.value, 1), np.uint32)
+    mk = np.zeros(max(nw.value, 1), np.uint64)
+    _check("ckey_plan_query", _lib.ckey_plan_query(p, len(bm), None, None, None, st.ctypes.data,
+                                                   mk.ctypes.data, nw.value))
+    return {"nbits": nb.value, "words": w.value,
+            "windows": [(int(s), int(m)) for s, m in zip(st[: nw.value], mk[: nw.value])]}
+
+
+def ckey_distinction_bits(keys, order=None, flags=None, stream=None):
+    """D-bitmap (uint8 tensor of key_bytes bytes on the device) of the keys taken
+    in ``order`` (int32 tensor of row ids) or in row order."""
+    ks = keys.c_struct()
+    need = ctypes.c_size_t(0)
+    _check("ckey_distinction_bits", _lib.ckey_distinction_bits(
+        ctypes.byref(ks), _ptr(order), None, None, None, ctypes.byref(need), None))
+    ws = _workspace(need.value, keys.data.device)
+    bm = torch.empty(keys.key_bytes, dtype=torch.uint8, device=keys.data.device)
+    _check("ckey_distinction_bits", _lib.ckey_distinction_bits(
+        ctypes.byref(ks), _ptr(order), _ptr(bm), _ptr(flags), _ptr(ws), ctypes.byref(need),
+        _stream(stream)))
+    return bm
+
+
+def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, stream=None):
+    """Compressed keys as an int64 tensor of shape (words, n) (bit patterns of
+    the uint64 words) and the row ids 0..n-1 (int32)."""
+    bm, p = _host_bitmap(bitmap)
+    plan = ckey_plan_query(bm)
+    w = plan["words"] if words is None else words
+    dev = keys.data.device
+    ck = torch.empty((w, keys.n), dtype=torch.int64, device=dev) if out is None else out
+    rid = torch.empty(keys.n, dtype=torch.int32, device=dev) if rowids is None else rowids
+    ks = keys.c_struct()
+    _check("ckey_compress", _lib.ckey_compress(ctypes.byref(ks), p, _ptr(ck), w, _ptr(rid),
+                                               _ptr(flags), _stream(stream)))
+    return ck, rid
+
+
+def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=0, model=None, flags=None):
+    return ckey_sort_opts(method, digit_bits, bucket_log2, 0,
+                          None if model is None else model.handle,
+                          None if flags is None else flags.data_ptr())
+
+
+def ckey_sort_workspace(words, nbits, n, **opts):
+    o = _opts(**opts)
+    need = ctypes.c_size_t(0)
+    _check("ckey_sort", _lib.ckey_sort(None, words, nbits, None, n, ctypes.byref(o), None,
+                                       ctypes.byref(need), None))
+    return need.value
+
+
+def ckey_sort(ck, nbits, rowids, workspace=None, stream=None, **opts):
+    """Sort (ck[:, i], rowids[i]) in place by the top nbits of the word string."""
+    words, n = ck.shape
+    o = _opts(**opts)
+    need = ctypes.c_size_t(ckey_sort_workspace(words, nbits, n, **opts))
+    ws = _workspace(need.value, ck.device) if workspace is None else workspace
+    need = ctypes.c_size_t(ws.numel())
+    _check("ckey_sort", _lib.ckey_sort(_ptr(ck), words, nbits, _ptr(rowids), n, ctypes.byref(o),
+                                       _ptr(ws), ctypes.byref(need), _stream(stream)))
+    return ck, rowids
+
+
+def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
+    """Rebuild one or more indexes.
+
+    ``indexes``: list of dicts with keys ``keys`` (DeviceKeys), ``bitmap``
+    (host uint8 array or None for a first build) and optional booleans
+    ``want_pair_pos`` / ``want_ckeys``.  Returns a list of dicts with
+    ``perm``, ``bitmap`` (device) and optionally ``pair_pos`` / ``ckeys``.
+    """
+    descs = (ckey_index_desc * len(indexes))()
+    outs, hold = [], []
+    for x, spec in enumerate(indexes):
+        k = spec["keys"]
+        dev = k.data.device
+        bm = spec.get("bitmap")
+        if bm is not None:
+            bm, bp = _host_bitmap(bm)
+            hold.append(bm)
+            words = ckey_plan_query(bm)["words"]
+        else:
+            bp = None
+            words = max(1, (8 * k.key_bytes + 63) // 64)
+        o = {"perm": torch.empty(k.n, dtype=torch.int32, device=dev),
+             "bitmap": torch.empty(k.key_bytes, dtype=torch.uint8, device=dev)}
+        if spec.get("want_pair_pos"):
+            o["pair_pos"] = torch.empty(max(k.n - 1, 0), dtype=torch.int32, device=dev)
+        if spec.get("want_ckeys"):
+            o["ckeys"] = torch.empty((words, k.n), dtype=torch.int64, device=dev)
+        descs[x] = ckey_index_desc(k.c_struct(), bp, o["perm"].data_ptr() if k.n else None,
+                                   o["bitmap"].data_ptr(),
+                                   o["pair_pos"].data_ptr() if "pair_pos" in o and k.n > 1 else None,
+                                   o["ckeys"].data_ptr() if "ckeys" in o and k.n else None, None)
+        outs.append(o)
+    so = _opts(**opts)
+    need = ctypes.c_size_t(0)
+    _check("ckey_rebuild_index", _lib.ckey_rebuild_index(descs, len(indexes), ctypes.byref(so),
+                                                         None, ctypes.byref(need), None))
+    ws = _workspace(need.value, indexes[0]["keys"].data.device) if workspace is None else workspace
+    need = ctypes.c_size_t(ws.numel())
+    _check("ckey_rebuild_index", _lib.ckey_rebuild_index(descs, len(indexes), ctypes.byref(so),
+                                                         _ptr(ws), ctypes.byref(need),
+                                                         _stream(stream)))
+    return outs
+
+
+def as_u64(t):
+    """Device int64 tensor of word bit patterns -> host numpy uint64 array."""
+    return t.cpu().numpy().view(np.uint64)

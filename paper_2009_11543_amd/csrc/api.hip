@@ -1,0 +1,192 @@
+// C ABI entry points of libckey.so: argument checks, planning and workspace
+// layout on the host; all per-key work is enqueued as HIP kernels.
+#include <string.h>
+
+#include <vector>
+
+#include "internal.h"
+
+using namespace ckey;
+
+namespace {
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+ckey_status check_keys(const ckey_keys *k) {
+    if (!k) return CKEY_ERR_INVALID;
+    if (k->key_bytes == 0) return CKEY_ERR_INVALID;
+    if (k->key_bytes > CKEY_MAX_KEY_BYTES) return CKEY_ERR_UNSUPPORTED;
+    if (k->n > CKEY_MAX_ROWS) return CKEY_ERR_UNSUPPORTED;
+    if (k->n > 0 && !k->bytes) return CKEY_ERR_INVALID;
+    if (!k->offsets && k->stride < k->key_bytes) return CKEY_ERR_INVALID;
+    return CKEY_OK;
+}
+
+KeySrc key_src(const ckey_keys *k) {
+    return KeySrc{k->bytes, k->offsets, k->n, k->key_bytes, k->stride};
+}
+
+uint32_t popcount_bitmap(const uint8_t *bm, uint32_t L) {
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < L; ++j) c += __builtin_popcount(bm[j]);
+    return c;
+}
+
+uint32_t words_for(uint32_t nbits) { return nbits ? (nbits + 63) / 64 : 1; }
+
+ckey_status ws_check(void *ws, size_t *ws_bytes, size_t need, bool &query) {
+    if (!ws_bytes) return CKEY_ERR_INVALID;
+    if (!ws) {
+        *ws_bytes = need;
+        query = true;
+        return CKEY_OK;
+    }
+    query = false;
+    if (*ws_bytes < need) return CKEY_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return CKEY_ERR_INVALID;
+    return CKEY_OK;
+}
+
+uint32_t digit_bits_of(const ckey_sort_opts *o) {
+    uint32_t d = o ? o->digit_bits : 0;
+    return d == 0 ? 8 : d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ckey_status_string(ckey_status s) {
+    switch (s) {
+        case CKEY_OK: return "ok";
+        case CKEY_ERR_INVALID: return "invalid argument";
+        case CKEY_ERR_UNSUPPORTED: return "unsupported (beyond library limits)";
+        case CKEY_ERR_WORKSPACE: return "workspace too small";
+        case CKEY_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+ckey_status ckey_plan_query(const uint8_t *bitmap, uint32_t L, uint32_t *nbits, uint32_t *words,
+                            uint32_t *windows, uint32_t *window_start, uint64_t *window_mask,
+                            uint32_t max_windows) {
+    if (!bitmap || L == 0) return CKEY_ERR_INVALID;
+    if (L > CKEY_MAX_KEY_BYTES) return CKEY_ERR_UNSUPPORTED;
+    const uint32_t nb = popcount_bitmap(bitmap, L);
+    if (nbits) *nbits = nb;
+    if (words) *words = words_for(nb);
+    // Sec. 5.1: each 8-byte mask starts at the byte holding the next 1 that
+    // the previous mask does not cover.
+    uint32_t nw = 0;
+    for (uint32_t j = 0; j < L;) {
+        if (!bitmap[j]) { ++j; continue; }
+        uint64_t m = 0;
+        for (uint32_t t = 0; t < 8; ++t) m = (m << 8) | (j + t < L ? bitmap[j + t] : 0u);
+        if (nw < max_windows) {
+            if (window_start) window_start[nw] = j;
+            if (window_mask) window_mask[nw] = m;
+        }
+        ++nw;
+        j += 8;
+    }
+    if (windows) *windows = nw;
+    return CKEY_OK;
+}
+
+ckey_status ckey_distinction_bits(const ckey_keys *keys, const uint32_t *order, uint8_t *bitmap,
+                                  uint32_t *flags, void *ws, size_t *ws_bytes, void *stream) {
+    CKEY_TRY(check_keys(keys));
+    if (!bitmap) return CKEY_ERR_INVALID;
+    const uint32_t nw = (keys->key_bytes + 3) / 4;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, align256(nw * 4), query));
+    if (query) return CKEY_OK;
+    hipStream_t st = as_stream(stream);
+    uint32_t *acc = static_cast<uint32_t *>(ws);
+    CKEY_TRY(fill_u32(acc, nw, 0, st));
+    CKEY_TRY(dbits_launch(key_src(keys), order, acc, flags, st));
+    return bitmap_finalize(acc, bitmap, keys->key_bytes, st);
+}
+
+ckey_status ckey_compress(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
+                          uint32_t words, uint32_t *rowids, uint32_t *flags, void *stream) {
+    CKEY_TRY(check_keys(keys));
+    if (!bitmap) return CKEY_ERR_INVALID;
+    if (keys->n > 0 && !ckeys) return CKEY_ERR_INVALID;
+    if (words < words_for(popcount_bitmap(bitmap, keys->key_bytes))) return CKEY_ERR_INVALID;
+    return compress_launch(key_src(keys), bitmap, ckeys, words, rowids, flags, as_stream(stream));
+}
+
+ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids, uint64_t n,
+                      const ckey_sort_opts *opts, void *ws, size_t *ws_bytes, void *stream) {
+    if (n > CKEY_MAX_ROWS) return CKEY_ERR_UNSUPPORTED;
+    if (words == 0 || nbits > 64ull * words) return CKEY_ERR_INVALID;
+    const uint32_t method = opts ? opts->method : CKEY_SORT_RADIX;
+    const uint32_t d = digit_bits_of(opts);
+    if (d < 1 || d > 8) return CKEY_ERR_INVALID;
+    if (method != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, radix_workspace(words, nbits, n, d), query));
+    if (query) return CKEY_OK;
+    if (n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
+    return radix_sort(ckeys, words, nbits, rowids, n, d, opts ? opts->flags : nullptr, ws,
+                      as_stream(stream));
+}
+
+ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
+                               const ckey_sort_opts *opts, void *ws, size_t *ws_bytes,
+                               void *stream) {
+    if (!idx || count == 0) return CKEY_ERR_INVALID;
+    const uint32_t d = digit_bits_of(opts);
+    if (d < 1 || d > 8) return CKEY_ERR_INVALID;
+    if (opts && opts->method != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    // Per-index plan and workspace; indexes run one after another and share it.
+    size_t need = 0;
+    std::vector<std::vector<uint8_t>> bms(count);
+    for (uint32_t x = 0; x < count; ++x) {
+        const ckey_index_desc &D = idx[x];
+        CKEY_TRY(check_keys(&D.keys));
+        if (ws && D.keys.n > 0 && !D.perm) return CKEY_ERR_INVALID;
+        const uint32_t L = D.keys.key_bytes;
+        bms[x].assign(L, 0xFF);  // first build: every position (Sec. 4.3)
+        if (D.bitmap_in) memcpy(bms[x].data(), D.bitmap_in, L);
+        const uint32_t nb = popcount_bitmap(bms[x].data(), L);
+        const uint32_t w = words_for(nb);
+        const uint64_t n = D.keys.n;
+        size_t s = align256((L + 3) / 4 * 4);
+        if (!D.ckeys) s += align256(size_t(w) * n * 8);
+        s += radix_workspace(w, nb, n, d);
+        if (s > need) need = s;
+    }
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, need, query));
+    if (query) return CKEY_OK;
+    hipStream_t st = as_stream(stream);
+    for (uint32_t x = 0; x < count; ++x) {
+        const ckey_index_desc &D = idx[x];
+        const uint32_t L = D.keys.key_bytes;
+        const uint8_t *bm = bms[x].data();
+        const uint32_t nb = popcount_bitmap(bm, L);
+        const uint32_t w = words_for(nb);
+        const uint64_t n = D.keys.n;
+        uint8_t *p = static_cast<uint8_t *>(ws);
+        uint32_t *acc = reinterpret_cast<uint32_t *>(p);
+        p += align256((L + 3) / 4 * 4);
+        uint64_t *ck = D.ckeys;
+        if (!ck) {
+            ck = reinterpret_cast<uint64_t *>(p);
+            p += align256(size_t(w) * n * 8);
+        }
+        uint32_t *flags = D.flags ? D.flags : (opts ? opts->flags : nullptr);
+        CKEY_TRY(compress_launch(key_src(&D.keys), bm, ck, w, D.perm, flags, st));
+        CKEY_TRY(radix_sort(ck, w, nb, D.perm, n, d, flags, p, st));
+        if (D.bitmap_out || D.pair_pos) {
+            CKEY_TRY(fill_u32(acc, (L + 3) / 4, 0, st));
+            CKEY_TRY(refine_launch(ck, w, n, bm, L, acc, D.pair_pos, flags, st));
+            if (D.bitmap_out) CKEY_TRY(bitmap_finalize(acc, D.bitmap_out, L, st));
+        }
+    }
+    return CKEY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ckey.h"
+
+namespace ckey {
+
+constexpr int kWG = 256;  // threads per workgroup (4 wave64s)
+
+#define CKEY_TRY(expr)                      \
+    do {                                    \
+        ckey_status s_ = (expr);            \
+        if (s_ != CKEY_OK) return s_;       \
+    } while (0)
+
+#define CKEY_HIP_TRY(expr)                  \
+    do {                                    \
+        hipError_t e_ = (expr);             \
+        if (e_ != hipSuccess) return CKEY_ERR_HIP; \
+    } while (0)
+
+inline ckey_status launch_status() {
+    return hipGetLastError() == hipSuccess ? CKEY_OK : CKEY_ERR_HIP;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Key source as the kernels see it.
+struct KeySrc {
+    const uint8_t *bytes;
+    const uint64_t *offsets;  // nullptr: fixed width
+    uint64_t n;
+    uint32_t L;
+    uint32_t stride;
+};
+
+// How a kernel may read key words.
+enum LoadMode : int {
+    kLoad16 = 0,  // fixed width, 16-byte aligned rows: 128-bit loads
+    kLoad4 = 1,   // fixed width, 4-byte aligned rows: 32-bit loads
+    kLoadBytes = 2  // anything else (variable length, odd strides): byte loads
+};
+
+inline int load_mode(const KeySrc &k) {
+    if (k.offsets) return kLoadBytes;
+    uintptr_t b = reinterpret_cast<uintptr_t>(k.bytes);
+    if (k.stride % 16 == 0 && b % 16 == 0) return kLoad16;
+    if (k.stride % 4 == 0 && b % 4 == 0) return kLoad4;
+    return kLoadBytes;
+}
+
+// Big-endian 32-bit word j (bytes 4j..4j+3) of a key, bytes at or past `len`
+// read as zero.  `p` points at the key's first byte.
+__device__ __forceinline__ uint32_t key_word_bytes(const uint8_t *p, uint32_t j, uint32_t len) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint32_t q = 4 * j + t;
+        v = (v << 8) | (q < len ? uint32_t(p[q]) : 0u);
+    }
+    return v;
+}
+
+// Same for a 4-byte aligned fixed-width key of length len (len <= stride).
+__device__ __forceinline__ uint32_t key_word_aligned(const uint8_t *p, uint32_t j, uint32_t len) {
+    uint32_t v = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 4 * j));
+    uint32_t have = len - 4 * j;  // bytes of this word inside the key (>= 1)
+    if (have < 4) v &= ~(0xFFFFFFFFu >> (8 * have));
+    return v;
+}
+
+// Bit for position p inside the little-endian u32 view of a bitmap
+// (bitmap byte p/8 is byte (p/8)%4 of word p/32; the position is bit 7-p%8 of that byte).
+__device__ __forceinline__ uint32_t bitmap_word_bit(uint32_t p) {
+    return 1u << (8 * ((p >> 3) & 3) + (7 - (p & 7)));
+}
+
+// ----------------------------------------------------------------- launchers --
+// Distinction bits (k_dbits.hip).
+ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc_words,
+                         uint32_t *flags, hipStream_t st);
+// Clear n u32 words (a fill kernel, safe inside graph capture).
+ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+// Copy a little-endian u32 bitmap accumulator into a byte bitmap of L bytes.
+ckey_status bitmap_finalize(const uint32_t *acc_words, uint8_t *bitmap, uint32_t L, hipStream_t st);
+
+// Compression plan (host side, k_compress.hip).
+struct HostPlan;
+ckey_status compress_launch(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ckeys,
+                            uint32_t words, uint32_t *rowids, uint32_t *flags, hipStream_t st);
+
+// Refresh of the D-bitmap from sorted compressed keys (k_refine.hip).
+ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
+                          const uint8_t *bitmap_in_host, uint32_t L, uint32_t *acc_words,
+                          uint32_t *pair_pos, uint32_t *flags, hipStream_t st);
+
+// Radix sort (k_radix.hip).
+size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits);
+ckey_status radix_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
+                       uint64_t n, uint32_t digit_bits, uint32_t *flags, void *ws,
+                       hipStream_t st);
+
+}  // namespace ckey
+
+namespace ckey {
+
+// Inclusive scan across a wave64.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a workgroup; all threads must call.
+// s_tmp: 4 words of LDS.  Returns the exclusive prefix; `total` gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
+    const uint32_t incl = wave_incl_scan(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) s_tmp[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWG / 64; ++w) {
+        const uint32_t t = s_tmp[w];
+        off += (w < wave) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+}  // namespace ckey

@@ -1,0 +1,112 @@
+// Distinction bits of adjacent sorted keys (Sec. 3.1, Theorem 1).
+//
+// One thread per adjacent pair (i-1, i): the keys are compared as big-endian
+// 32-bit words; the first differing word gives the pair's D-bit as
+// 32*j + clz(x xor y).  The position is OR-ed into a workgroup bitmap in LDS
+// (one u32 per 4 bitmap bytes), and each workgroup OR-s its non-zero words into
+// the global accumulator once.  A pair whose earlier key has a 1 at its D-bit
+// is descending and raises CKEY_FLAG_DESCENDING.
+#include "internal.h"
+
+namespace ckey {
+
+template <int MODE>
+__device__ __forceinline__ uint32_t load_key_word(const KeySrc &k, uint64_t row, uint32_t j,
+                                                  const uint8_t *&p, uint32_t &len) {
+    return MODE == kLoadBytes ? key_word_bytes(p, j, len) : key_word_aligned(p, j, len);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restrict__ order,
+                                               uint32_t *__restrict__ acc,
+                                               uint32_t *__restrict__ flags) {
+    extern __shared__ uint32_t s_bm[];
+    const uint32_t nw = (k.L + 3) / 4;
+    for (uint32_t t = threadIdx.x; t < nw; t += kWG) s_bm[t] = 0;
+    __syncthreads();
+
+    bool desc = false;
+    bool too_long = false;
+    const uint64_t step = uint64_t(gridDim.x) * kWG;
+    for (uint64_t i = 1 + uint64_t(blockIdx.x) * kWG + threadIdx.x; i < k.n; i += step) {
+        const uint64_t ra = order ? order[i - 1] : i - 1;
+        const uint64_t rb = order ? order[i] : i;
+        const uint8_t *pa, *pb;
+        uint32_t la, lb;
+        if (k.offsets) {
+            uint64_t a0 = k.offsets[ra], a1 = k.offsets[ra + 1];
+            uint64_t b0 = k.offsets[rb], b1 = k.offsets[rb + 1];
+            pa = k.bytes + a0;
+            pb = k.bytes + b0;
+            la = uint32_t(min<uint64_t>(a1 - a0, k.L));
+            lb = uint32_t(min<uint64_t>(b1 - b0, k.L));
+            too_long |= (a1 - a0 > k.L) | (b1 - b0 > k.L);
+        } else {
+            pa = k.bytes + ra * k.stride;
+            pb = k.bytes + rb * k.stride;
+            la = lb = k.L;
+        }
+        for (uint32_t j = 0; j < nw; ++j) {
+            uint32_t x = load_key_word<MODE>(k, ra, j, pa, la);
+            uint32_t y = load_key_word<MODE>(k, rb, j, pb, lb);
+            if (x != y) {
+                uint32_t lz = __clz(x ^ y);
+                uint32_t p = 32 * j + lz;
+                desc |= ((x >> (31 - lz)) & 1u) != 0;
+                atomicOr(&s_bm[p >> 5], bitmap_word_bit(p));
+                break;
+            }
+        }
+    }
+    if (flags && (desc || too_long))
+        atomicOr(flags, (desc ? CKEY_FLAG_DESCENDING : 0u) | (too_long ? CKEY_FLAG_KEY_TOO_LONG : 0u));
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < nw; t += kWG)
+        if (s_bm[t]) atomicOr(&acc[t], s_bm[t]);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) p[i] = v;
+}
+
+__global__ void k_bitmap_finalize(const uint32_t *acc, uint8_t *bitmap, uint32_t L) {
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < L; j += gridDim.x * blockDim.x)
+        bitmap[j] = uint8_t(acc[j >> 2] >> (8 * (j & 3)));
+}
+
+ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+    if (n == 0) return CKEY_OK;
+    uint64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3(uint32_t(blocks)), dim3(kWG), 0, st, p, n, v);
+    return launch_status();
+}
+
+ckey_status bitmap_finalize(const uint32_t *acc, uint8_t *bitmap, uint32_t L, hipStream_t st) {
+    uint32_t blocks = (L + kWG - 1) / kWG;
+    hipLaunchKernelGGL(k_bitmap_finalize, dim3(blocks), dim3(kWG), 0, st, acc, bitmap, L);
+    return launch_status();
+}
+
+ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc, uint32_t *flags,
+                         hipStream_t st) {
+    if (k.n < 2) return CKEY_OK;
+    const uint32_t nw = (k.L + 3) / 4;
+    uint64_t blocks = (k.n - 1 + kWG - 1) / kWG;
+    if (blocks > 2048) blocks = 2048;
+    const size_t lds = nw * sizeof(uint32_t);
+    switch (load_mode(k)) {
+        case kLoadBytes:
+            hipLaunchKernelGGL(k_dbits<kLoadBytes>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
+                               order, acc, flags);
+            break;
+        default:
+            hipLaunchKernelGGL(k_dbits<kLoad4>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
+                               order, acc, flags);
+            break;
+    }
+    return launch_status();
+}
+
+}  // namespace ckey

@@ -1,0 +1,358 @@
+// Stable LSD radix sort of (compressed key, row id) pairs (Sec. 3.2; the
+// paper sorts with a comparison sort, Appendix A -- on the GPU a radix sort
+// over the few meaningful bits moves far fewer bytes).
+//
+// Keys are `words` 64-bit words stored word-major; only the top `nbits` bits
+// of the word string order the rows.  Digits are taken from the least
+// significant meaningful bit upward, never straddling a word.
+//
+//   k_hist      one read of every key word: histograms of every digit pass.
+//   k_scan      exclusive scan of each pass histogram -> global bucket starts.
+//   k_onesweep  one pass per digit: a workgroup takes the next 4096-key tile
+//               (atomic tile counter), ranks keys stably with wave64 ballots,
+//               publishes its per-bucket counts, looks back over the
+//               predecessor tiles' published counts (decoupled look-back), and
+//               scatters every word and the row id through an LDS reorder
+//               buffer so each bucket's run is written contiguously.
+//
+// The look-back waits only on tiles whose workgroups started earlier (tile
+// numbers are handed out in start order), so every wait ends; a spin bound
+// still guarantees termination and raises CKEY_FLAG_SPIN_LIMIT.
+#include <vector>
+
+#include "internal.h"
+
+namespace ckey {
+
+namespace {
+
+constexpr int kRadixMax = 256;
+constexpr int kKPT = 16;                  // keys per thread
+constexpr int kTile = kWG * kKPT;         // 4096 keys per tile
+constexpr int kWaves = kWG / 64;
+constexpr uint32_t kFlagAgg = 1u << 30;   // tile aggregate published
+constexpr uint32_t kFlagInc = 2u << 30;   // inclusive prefix published
+constexpr uint32_t kValMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+struct Pass {
+    uint32_t word, shift, bits;
+};
+
+struct HistArgs {
+    uint32_t npass;
+    uint32_t shift[8];
+    uint32_t bits[8];
+    uint32_t out[8];  // pass index of each digit
+};
+
+__global__ __launch_bounds__(kWG) void k_hist(const uint64_t *__restrict__ word, uint64_t n,
+                                              HistArgs ha, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[8][kRadixMax];
+    for (int t = threadIdx.x; t < 8 * kRadixMax; t += kWG) (&s_h[0][0])[t] = 0;
+    __syncthreads();
+    const uint64_t step = uint64_t(gridDim.x) * kWG;
+    for (uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x; i < n; i += step) {
+        const uint64_t x = word[i];
+        for (uint32_t p = 0; p < ha.npass; ++p) {
+            const uint32_t d = uint32_t(x >> ha.shift[p]) & ((1u << ha.bits[p]) - 1u);
+            atomicAdd(&s_h[p][d], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < ha.npass * kRadixMax; t += kWG) {
+        const uint32_t p = t / kRadixMax, d = t % kRadixMax;
+        if (s_h[p][d]) atomicAdd(&hist[ha.out[p] * kRadixMax + d], s_h[p][d]);
+    }
+}
+
+// One workgroup per pass: hist[p][*] -> exclusive prefix in place.
+__global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_tmp[4];
+    uint32_t *h = hist + blockIdx.x * kRadixMax;
+    const uint32_t v = h[threadIdx.x];
+    uint32_t total;
+    const uint32_t e = block_excl_scan(v, s_tmp, total);
+    h[threadIdx.x] = e;
+}
+
+__global__ __launch_bounds__(kWG) void k_onesweep(
+    const uint64_t *__restrict__ src, const uint32_t *__restrict__ src_rid,
+    uint64_t *__restrict__ dst, uint32_t *__restrict__ dst_rid, uint64_t n, uint32_t words,
+    Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback, uint32_t *tile_counter,
+    uint32_t *flags) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wc[kWaves][kRadixMax];  // per-wave bucket counts, then offsets
+    __shared__ uint32_t s_tstart[kRadixMax];      // tile-local bucket starts
+    __shared__ uint32_t s_gbase[kRadixMax];       // global index of tile-local slot 0 per bucket
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint64_t s_buf[kTile];
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int t = tid; t < kWaves * kRadixMax; t += kWG) (&s_wc[0][0])[t] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = uint64_t(tile) * kTile;
+    const uint32_t cnt = uint32_t(min<uint64_t>(kTile, n - base));
+    const uint32_t dmask = (1u << ps.bits) - 1u;
+    const uint64_t *dsrc = src + uint64_t(ps.word) * n + base;
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+
+    uint64_t xv[kKPT];
+    uint32_t dig[kKPT];
+    uint32_t lpos[kKPT];
+#pragma unroll
+    for (int m = 0; m < kKPT; ++m) {
+        const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+        xv[m] = li < cnt ? dsrc[li] : 0ull;
+        dig[m] = uint32_t(xv[m] >> ps.shift) & dmask;
+    }
+
+    // Stable rank within the wave: peers = lanes holding the same digit.
+#pragma unroll
+    for (int m = 0; m < kKPT; ++m) {
+        const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+        const bool valid = li < cnt;
+        uint64_t peers = __ballot(valid);
+        for (uint32_t b = 0; b < ps.bits; ++b) {
+            const bool bit = (dig[m] >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t below = __popcll(peers & lane_lt);
+        const uint32_t tot = __popcll(peers);
+        uint32_t old = 0;
+        if (valid) old = s_wc[wave][dig[m]];
+        if (valid && below == 0) s_wc[wave][dig[m]] = old + tot;
+        lpos[m] = old + below;
+    }
+    __syncthreads();
+
+    // Thread `tid` owns bucket `tid`.
+    {
+        const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
+        __hip_atomic_store(lb, (tile == 0 ? kFlagInc : kFlagAgg) | tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        s_wc[0][tid] = 0;
+        s_wc[1][tid] = c0;
+        s_wc[2][tid] = c0 + c1;
+        s_wc[3][tid] = c0 + c1 + c2;
+        uint32_t all;
+        const uint32_t tstart = block_excl_scan(tot, s_tmp, all);
+        s_tstart[tid] = tstart;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            uint32_t j = tile - 1, spins = 0;
+            for (;;) {
+                const uint32_t e = __hip_atomic_load(lookback + uint64_t(j) * kRadixMax + tid,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = e & ~kValMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        if (flags) atomicOr(flags, CKEY_FLAG_SPIN_LIMIT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += e & kValMask;
+                if (f == kFlagInc || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_gbase[tid] = bstart[tid] + excl - tstart;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int m = 0; m < kKPT; ++m) lpos[m] += s_tstart[dig[m]] + s_wc[wave][dig[m]];
+
+    // Reorder and write: the digit word first (it yields each slot's bucket).
+    uint32_t gdst[kKPT];
+#pragma unroll
+    for (int m = 0; m < kKPT; ++m) {
+        const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+        if (li < cnt) s_buf[lpos[m]] = xv[m];
+    }
+    __syncthreads();
+    uint64_t *ddst = dst + uint64_t(ps.word) * n;
+#pragma unroll
+    for (int m = 0; m < kKPT; ++m) {
+        const uint32_t j = m * kWG + tid;
+        gdst[m] = 0xFFFFFFFFu;
+        if (j < cnt) {
+            const uint64_t v = s_buf[j];
+            gdst[m] = s_gbase[uint32_t(v >> ps.shift) & dmask] + j;
+            // every index is < n unless a look-back gave up (CKEY_FLAG_SPIN_LIMIT)
+            if (gdst[m] < n) ddst[gdst[m]] = v;
+        }
+    }
+    for (uint32_t k = 0; k < words; ++k) {
+        if (k == ps.word) continue;
+        const uint64_t *ksrc = src + uint64_t(k) * n + base;
+        uint64_t vv[kKPT];
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+            vv[m] = li < cnt ? ksrc[li] : 0ull;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+            if (li < cnt) s_buf[lpos[m]] = vv[m];
+        }
+        __syncthreads();
+        uint64_t *kdst = dst + uint64_t(k) * n;
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t j = m * kWG + tid;
+            if (j < cnt && gdst[m] < n) kdst[gdst[m]] = s_buf[j];
+        }
+    }
+    {
+        uint32_t rv[kKPT];
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+            rv[m] = li < cnt ? src_rid[base + li] : 0u;
+        }
+        uint32_t *s_buf32 = reinterpret_cast<uint32_t *>(s_buf);
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
+            if (li < cnt) s_buf32[lpos[m]] = rv[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kKPT; ++m) {
+            const uint32_t j = m * kWG + tid;
+            if (j < cnt && gdst[m] < n) dst_rid[gdst[m]] = s_buf32[j];
+        }
+    }
+}
+
+__global__ void k_copy_back(const uint64_t *__restrict__ src, const uint32_t *__restrict__ src_rid,
+                            uint64_t *__restrict__ dst, uint32_t *__restrict__ dst_rid, uint64_t n,
+                            uint32_t words) {
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+        for (uint32_t k = 0; k < words; ++k) dst[uint64_t(k) * n + i] = src[uint64_t(k) * n + i];
+        dst_rid[i] = src_rid[i];
+    }
+}
+
+void make_passes(uint32_t words, uint32_t nbits, uint32_t d, std::vector<Pass> &ps) {
+    ps.clear();
+    for (int k = int(words) - 1; k >= 0; --k) {
+        const int64_t have = int64_t(nbits) - 64 * int64_t(k);
+        if (have <= 0) continue;
+        const uint32_t bits_k = uint32_t(have > 64 ? 64 : have);
+        uint32_t s = 64 - bits_k;
+        while (s < 64) {
+            const uint32_t b = std::min<uint32_t>(d, 64 - s);
+            ps.push_back({uint32_t(k), s, b});
+            s += b;
+        }
+    }
+}
+
+struct Layout {
+    size_t alt_keys, alt_rid, hist, lookback, counters, total;
+    uint64_t tiles;
+    uint32_t npass;
+};
+
+Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d) {
+    std::vector<Pass> ps;
+    make_passes(words, nbits, d, ps);
+    Layout l{};
+    l.npass = uint32_t(ps.size());
+    l.tiles = (n + kTile - 1) / kTile;
+    size_t off = 0;
+    l.alt_keys = off; off += align256(size_t(words) * n * 8);
+    l.alt_rid = off;  off += align256(size_t(n) * 4);
+    l.hist = off;     off += align256(size_t(l.npass) * kRadixMax * 4);
+    l.lookback = off; off += align256(size_t(l.tiles) * kRadixMax * 4);
+    l.counters = off; off += align256(size_t(l.npass) * 4);
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d) {
+    return layout(words, nbits, n, d).total;
+}
+
+ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
+                       uint32_t d, uint32_t *flags, void *ws, hipStream_t st) {
+    if (n < 2 || nbits == 0) return CKEY_OK;
+    std::vector<Pass> ps;
+    make_passes(words, nbits, d, ps);
+    const Layout l = layout(words, nbits, n, d);
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
+    uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w8 + l.hist);
+    uint32_t *lookback = reinterpret_cast<uint32_t *>(w8 + l.lookback);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(w8 + l.counters);
+
+    CKEY_TRY(fill_u32(hist, size_t(l.npass) * kRadixMax, 0, st));
+    CKEY_TRY(fill_u32(counters, l.npass, 0, st));
+    // Upfront histograms, grouped by word, at most 8 digits per launch.
+    uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
+    if (hblocks > 2048) hblocks = 2048;
+    for (size_t p0 = 0; p0 < ps.size();) {
+        HistArgs ha{};
+        const uint32_t wk = ps[p0].word;
+        size_t p = p0;
+        while (p < ps.size() && ps[p].word == wk && ha.npass < 8) {
+            ha.shift[ha.npass] = ps[p].shift;
+            ha.bits[ha.npass] = ps[p].bits;
+            ha.out[ha.npass] = uint32_t(p);
+            ++ha.npass;
+            ++p;
+        }
+        hipLaunchKernelGGL(k_hist, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, ck + uint64_t(wk) * n,
+                           n, ha, hist);
+        CKEY_TRY(launch_status());
+        p0 = p;
+    }
+    hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist);
+    CKEY_TRY(launch_status());
+
+    const uint64_t *s = ck;
+    const uint32_t *sr = rid;
+    uint64_t *dk = alt;
+    uint32_t *dr = alt_rid;
+    for (size_t p = 0; p < ps.size(); ++p) {
+        CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
+        hipLaunchKernelGGL(k_onesweep, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, s, sr, dk, dr, n,
+                           words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+        CKEY_TRY(launch_status());
+        // swap
+        const uint64_t *ns = dk;
+        const uint32_t *nsr = dr;
+        dk = const_cast<uint64_t *>(s);
+        dr = const_cast<uint32_t *>(sr);
+        s = ns;
+        sr = nsr;
+    }
+    if (s != ck) {
+        uint64_t blocks = (n + kWG - 1) / kWG;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_copy_back, dim3(uint32_t(blocks)), dim3(kWG), 0, st, s, sr, ck, rid, n,
+                           words);
+        CKEY_TRY(launch_status());
+    }
+    return CKEY_OK;
+}
+
+}  // namespace ckey

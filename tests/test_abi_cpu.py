@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and its host-only logic (planning, argument checks, workspace
+queries) behaves as documented."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(ckey_\w+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def ck():
+    from paper_2009_11543_amd import ckey
+    return ckey
+
+
+def test_exports_every_declared_symbol(ck):
+    names = declared_symbols()
+    assert {"ckey_distinction_bits", "ckey_compress", "ckey_sort", "ckey_rebuild_index"} <= names
+    lib = ctypes.CDLL(ck.LIB_PATH)
+    for name in sorted(names):
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(ck):
+    assert ck.status_string(0) == "ok"
+    assert "workspace" in ck.status_string(3)
+
+
+def test_plan_query_table3(ck, golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "table3_indbtab_dbitmap.json")))
+    bm = np.array([int(b, 2) for b in g["bytes_1_to_35"]], np.uint8)
+    plan = ck.ckey_plan_query(bm)
+    assert plan["nbits"] == 56 and plan["words"] == 1
+    w = g["windows_sec51_rule"]
+    assert [s for s, _ in plan["windows"]] == w["start_bytes_0based"]
+    assert [format(m, "016x") for _, m in plan["windows"]] == w["masks_hex"]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_plan_query_matches_oracle(ck, seed):
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(1, 300))
+    bm = (rng.random(L) < rng.random()).astype(np.uint8) * rng.integers(0, 256, L, dtype=np.uint8)
+    plan = ck.ckey_plan_query(bm)
+    st, mk = O.windows(bm)
+    assert plan["nbits"] == len(O.doffset(bm))
+    assert plan["words"] == O.nwords(bm)
+    assert [s for s, _ in plan["windows"]] == list(st)
+    assert [m for _, m in plan["windows"]] == [int(x) for x in mk]
+
+
+def test_argument_errors(ck):
+    lib = ck.lib()
+    need = ctypes.c_size_t(0)
+    # null keys
+    assert lib.ckey_compress(None, None, None, 1, None, None, None) == ck.CKEY_ERR_INVALID
+    ks = ck.ckey_keys(None, None, 0, 0, 0)
+    assert lib.ckey_distinction_bits(ctypes.byref(ks), None, None, None, None,
+                                     ctypes.byref(need), None) == ck.CKEY_ERR_INVALID
+    ks = ck.ckey_keys(None, None, 10, 16, 8)   # stride < key_bytes, bytes NULL
+    assert lib.ckey_distinction_bits(ctypes.byref(ks), None, None, None, None,
+                                     ctypes.byref(need), None) == ck.CKEY_ERR_INVALID
+    ks = ck.ckey_keys(None, None, 0, ck.MAX_KEY_BYTES + 1, ck.MAX_KEY_BYTES + 1)
+    bm = np.zeros(4, np.uint8)
+    assert lib.ckey_distinction_bits(ctypes.byref(ks), None, bm.ctypes.data, None, None,
+                                     ctypes.byref(need), None) == ck.CKEY_ERR_UNSUPPORTED
+    o = ck.ckey_sort_opts(0, 9, 0, 0, None, None)   # digit width 9
+    assert lib.ckey_sort(None, 1, 8, None, 0, ctypes.byref(o), None, ctypes.byref(need),
+                         None) == ck.CKEY_ERR_INVALID
+    o = ck.ckey_sort_opts(0, 8, 0, 0, None, None)
+    assert lib.ckey_sort(None, 1, 65, None, 0, ctypes.byref(o), None, ctypes.byref(need),
+                         None) == ck.CKEY_ERR_INVALID   # nbits > 64*words
+    assert lib.ckey_sort(None, 1, 8, None, (1 << 30) + 1, ctypes.byref(o), None,
+                         ctypes.byref(need), None) == ck.CKEY_ERR_UNSUPPORTED
+    # compress: words below the plan's w
+    keys = np.zeros((4, 16), np.uint8)
+    ks = ck.ckey_keys(keys.ctypes.data, None, 4, 16, 16)
+    full = np.full(16, 0xFF, np.uint8)
+    assert lib.ckey_compress(ctypes.byref(ks), full.ctypes.data, keys.ctypes.data, 1, None, None,
+                             None) == ck.CKEY_ERR_INVALID
+
+
+def test_workspace_queries(ck):
+    n = 1 << 20
+    a = ck.ckey_sort_workspace(1, 40, n)
+    b = ck.ckey_sort_workspace(3, 192, n)
+    assert a >= n * 12 and b >= n * 28 and b > a
+    lib = ck.lib()
+    need = ctypes.c_size_t(0)
+    ks = ck.ckey_keys(1, None, n, 64, 64)  # pointer never dereferenced by a query
+    d = ck.ckey_index_desc(ks, None, 1, 1, None, None, None)
+    assert lib.ckey_rebuild_index(ctypes.byref(d), 1, None, None, ctypes.byref(need), None) == 0
+    assert need.value >= n * (64 + 4)  # first build: 8 words of ckeys + ping-pong
+    small = ctypes.c_size_t(16)
+    assert lib.ckey_rebuild_index(ctypes.byref(d), 1, None, ctypes.c_void_p(256),
+                                  ctypes.byref(small), None) == ck.CKEY_ERR_WORKSPACE
