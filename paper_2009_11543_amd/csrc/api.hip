@@ -96,11 +96,11 @@ ckey_status ckey_plan_query(const uint8_t *bitmap, uint32_t L, uint32_t *nbits, 
 ckey_status ckey_distinction_bits(const ckey_keys *keys, const uint32_t *order, uint8_t *bitmap,
                                   uint32_t *flags, void *ws, size_t *ws_bytes, void *stream) {
     CKEY_TRY(check_keys(keys));
-    if (!bitmap) return CKEY_ERR_INVALID;
     const uint32_t nw = (keys->key_bytes + 3) / 4;
     bool query;
     CKEY_TRY(ws_check(ws, ws_bytes, align256(nw * 4), query));
     if (query) return CKEY_OK;
+    if (!bitmap) return CKEY_ERR_INVALID;
     hipStream_t st = as_stream(stream);
     uint32_t *acc = static_cast<uint32_t *>(ws);
     CKEY_TRY(fill_u32(acc, nw, 0, st));

@@ -77,6 +77,9 @@ def test_argument_errors(ck):
     ks = ck.ckey_keys(None, None, 10, 16, 8)   # stride < key_bytes, bytes NULL
     assert lib.ckey_distinction_bits(ctypes.byref(ks), None, None, None, None,
                                      ctypes.byref(need), None) == ck.CKEY_ERR_INVALID
+    ks = ck.ckey_keys(None, None, 4, 4, 4)   # real call (workspace given) with a null bitmap
+    assert lib.ckey_distinction_bits(ctypes.byref(ks), None, None, None, ctypes.c_void_p(256),
+                                     ctypes.byref(ctypes.c_size_t(256)), None) == ck.CKEY_ERR_INVALID
     ks = ck.ckey_keys(None, None, 0, ck.MAX_KEY_BYTES + 1, ck.MAX_KEY_BYTES + 1)
     bm = np.zeros(4, np.uint8)
     assert lib.ckey_distinction_bits(ctypes.byref(ks), None, bm.ctypes.data, None, None,
