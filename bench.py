@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the compressed key sort on one MI355X.
+
+A step is one pass of the timed hot path -- ckey_compress (gather of the
+D-bitmap's bits into packed 64-bit words) followed by ckey_sort (stable
+sort of the (compressed key, row id) pairs) -- over device-resident keys with
+the D-bitmap given (it is index metadata computed by an earlier build, here a
+first build over full keys done before the timed region).
+
+Default workload: 2^26 keys of 64 ASCII bytes over {A,C,G,T}, windows at
+uniform offsets into one seeded 2^27-base sequence with 1% point mutations.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "compress+sort keys/s & HBM GB/s at 2^26 keys vs plain GPU full-key sort"
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2009_11543_amd import datagen
+    if name == "dna64_2p26":
+        return datagen.dna_window_keys(1 << 26, seed=1), "2^26 x 64-byte DNA windows, 1% mutations, seed 1"
+    if name == "prefix16_2p20":
+        return datagen.uniform_prefix_keys(1 << 20, seed=1), "2^20 x 16-byte keys, 6-byte constant prefix, seed 1"
+    if name == "uniform32_2p28":
+        return datagen.uniform_keys(1 << 28, seed=1), "2^28 x 32 uniform bytes, seed 1"
+    if name == "cluster32_2p28":
+        return datagen.cluster_keys(1 << 28, seed=1), "2^28 x 32 bytes, 2^16 stems + uniform last byte, seed 1"
+    raise SystemExit(f"unknown workload {name}")
+
+
+class Prof:
+    def __init__(self, lib):
+        self.lib = lib
+        lib.ckey_profile_enable.argtypes = [ctypes.c_int]
+        lib.ckey_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+
+    def on(self, flag=True):
+        self.lib.ckey_profile_reset()
+        self.lib.ckey_profile_enable(1 if flag else 0)
+
+    def read(self, name):
+        ms, cnt = ctypes.c_double(), ctypes.c_uint64()
+        rc = self.lib.ckey_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(cnt))
+        assert rc == 0
+        return ms.value, cnt.value
+
+
+def traffic_for(kernel, wl, src_file):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{wl}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    sha = hashlib.sha256(open(src_file, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(rows_all, n_sample):
+    """The CPU oracle, as it stands, on the first n_sample rows: compress with the
+    sample's D-bitmap, then sort the compressed keys (single thread)."""
+    import oracle as O
+    rows = np.ascontiguousarray(rows_all[:n_sample])
+    k = O.Keys(rows)
+    d, _ = O.dbits(k, O.full_sort(k))
+    t0 = time.perf_counter()
+    ck = O.compress(k, d)
+    perm = O.csort(ck)
+    dt = time.perf_counter() - t0
+    assert len(perm) == n_sample
+    return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample} rows of the workload; oracle compress (bit by bit) + "
+                      f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dna64_2p26")
+    ap.add_argument("--method", default="radix", choices=["radix"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-key", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_11543_amd import ckey
+    prof = Prof(ckey.lib())
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+
+    log(f"generating workload {args.workload}")
+    rows, desc = workload(args.workload)
+    n, L = rows.shape
+    keys = ckey.DeviceKeys(torch.from_numpy(rows).to(dev))
+    torch.cuda.synchronize()
+    log(f"keys resident: n={n} L={L}")
+
+    # copy probe: achievable HBM bandwidth
+    buf_a = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
+    buf_b = torch.empty_like(buf_a)
+    lib = ckey.lib()
+    lib.ckey_bench_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(2):
+        lib.ckey_bench_copy(buf_b.data_ptr(), buf_a.data_ptr(), buf_a.numel(), st)
+    prof.on()
+    for _ in range(5):
+        lib.ckey_bench_copy(buf_b.data_ptr(), buf_a.data_ptr(), buf_a.numel(), st)
+    cms, cnt = prof.read("stream_copy")
+    copy_gbps = 2 * buf_a.numel() / (cms / cnt / 1e3) / 1e9
+    prof.on(False)
+    del buf_a, buf_b
+    log(f"copy probe: {copy_gbps:.0f} GB/s")
+
+    # First build over full keys: the plain full-key GPU radix sort (timed as a
+    # baseline) and D from its order (Sec. 4.3, first build).
+    ones = np.full(L, 0xFF, np.uint8)
+    wf = (8 * L + 63) // 64
+    ckf = torch.empty((wf, n), dtype=torch.int64, device=dev)
+    ridf = torch.empty(n, dtype=torch.int32, device=dev)
+    wsf = torch.empty(ckey.ckey_sort_workspace(wf, 8 * L, n), dtype=torch.uint8, device=dev)
+    full = None
+    reps = 0 if args.no_full_key else 2
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ckey.ckey_compress(keys, ones, out=ckf, rowids=ridf)
+        ckey.ckey_sort(ckf, 8 * L, ridf, workspace=wsf)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if r > 0:
+            full = dt if full is None else min(full, dt)
+        log(f"full-key sort rep {r}: {dt * 1e3:.1f} ms")
+    d_bitmap = ckey.ckey_distinction_bits(keys, order=ridf).cpu().numpy()
+    del ckf, wsf
+    plan = ckey.ckey_plan_query(d_bitmap)
+    nbits, w = plan["nbits"], plan["words"]
+    log(f"|D|={nbits} words={w} windows={len(plan['windows'])}")
+
+    ck = torch.empty((w, n), dtype=torch.int64, device=dev)
+    rid = torch.empty(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(ckey.ckey_sort_workspace(w, nbits, n), dtype=torch.uint8, device=dev)
+
+    def step():
+        ckey.ckey_compress(keys, d_bitmap, out=ck, rowids=rid)
+        ckey.ckey_sort(ck, nbits, rid, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # correctness spot check of the last warm-up result against the first build
+    assert torch.equal(rid, ridf), "compressed-key order differs from full-key order"
+    log("warm-up done; permutation equals the full-key order")
+
+    prof.on()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    kern = {}
+    for name in ("compress", "hist", "onesweep"):
+        t, c = prof.read(name)
+        kern[name] = {"ms_total_per_step": t / args.steps, "launches_per_step": c / args.steps,
+                      "ms_per_launch": (t / c) if c else None}
+    prof.on(False)
+    log(f"step {ms:.3f} ms; kernels {json.dumps(kern)}")
+
+    # algorithmic bytes: compress reads the key bytes that hold
+    # D bits and writes 8w+4 B; the histogram reads 8w B; each pass reads and
+    # writes 8w+4 B per key.
+    key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
+    npass = int(round(kern["onesweep"]["launches_per_step"]))
+    rec = 8 * w + 4
+    step_bytes = n * (key_bytes_read + rec + 8 * w + npass * 2 * rec)
+    pass_bytes = n * 2 * rec
+    pass_ms = kern["onesweep"]["ms_per_launch"]
+    achieved = pass_bytes / (pass_ms / 1e3) / 1e9
+    src = os.path.join(ROOT, "paper_2009_11543_amd", "csrc", "k_radix.hip")
+    traffic = traffic_for("onesweep", args.workload, src)
+
+    out = {
+        "metric": METRIC, "value": n / (ms / 1e3), "unit": "keys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n": n, "key_bytes": L,
+                   "nbits": nbits, "words": w, "method": args.method, "digit_bits": 8,
+                   "passes": npass},
+        "hbm_gbps_algorithmic": step_bytes / (ms / 1e3) / 1e9,
+        "bytes_per_key_algorithmic": step_bytes / n,
+        "roofline": {"kernel": "onesweep", "bound": "hbm", "achieved": achieved,
+                     "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
+                     "traffic": traffic, "bytes_per_launch_algorithmic": pass_bytes,
+                     "ms_per_launch": pass_ms, "copy_probe_gbps": copy_gbps},
+        "kernels": kern,
+        "full_key_gpu": None if full is None else {
+            "ms_per_step": full * 1e3, "keys_per_s": n / full,
+            "speedup_of_compressed": full * 1e3 / ms,
+            "what": "ckey_compress with an all-ones bitmap + ckey_sort over all 8L bits"},
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline on {args.cpu_sample} rows")
+        out["cpu_baseline"] = cpu_baseline(rows, min(args.cpu_sample, n))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,21 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *workspace,
                                size_t *workspace_bytes, void *stream);
 
+/* ---- Benchmark support (not part of the method) ---------------------------
+ * Per-kernel timing: while enabled, every launch of the library's main kernels
+ * ("compress", "hist", "onesweep", "refine", "dbits", "stream_copy") is
+ * bracketed by HIP events on its stream.  ckey_profile_read waits for the
+ * recorded events and returns the summed duration and launch count of the
+ * kernels named `name` (NULL: all); ckey_profile_reset drops the records. */
+ckey_status ckey_profile_enable(int on);
+ckey_status ckey_profile_read(const char *name, double *total_ms, uint64_t *launches);
+ckey_status ckey_profile_reset(void);
+
+/* A plain device-to-device copy kernel ("stream_copy") of `bytes` bytes
+ * (multiple of 16, 16-byte aligned device pointers): measures achievable HBM
+ * bandwidth and calibrates hardware byte counters. */
+ckey_status ckey_bench_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Human-readable status name. */
 const char *ckey_status_string(ckey_status s);
 

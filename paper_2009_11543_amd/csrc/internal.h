@@ -78,6 +78,10 @@ __device__ __forceinline__ uint32_t bitmap_word_bit(uint32_t p) {
     return 1u << (8 * ((p >> 3) & 3) + (7 - (p & 7)));
 }
 
+// Event timing around a launch when profiling is enabled (profiler.hip).
+int prof_begin(hipStream_t st, const char *name);
+void prof_end(hipStream_t st, int idx);
+
 // ----------------------------------------------------------------- launchers --
 // Distinction bits (k_dbits.hip).
 ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc_words,

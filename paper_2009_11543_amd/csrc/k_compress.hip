@@ -199,13 +199,25 @@ ckey_status compress_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, ui
         if (runs.empty()) plan.word_begin = 0;
         switch (mode) {
             case kLoad16:
-                hipLaunchKernelGGL(k_compress<kLoad16>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                {
+                    const int pr_ = prof_begin(st, "compress");
+                    hipLaunchKernelGGL(k_compress<kLoad16>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                    prof_end(st, pr_);
+                }
                 break;
             case kLoad4:
-                hipLaunchKernelGGL(k_compress<kLoad4>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                {
+                    const int pr_ = prof_begin(st, "compress");
+                    hipLaunchKernelGGL(k_compress<kLoad4>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                    prof_end(st, pr_);
+                }
                 break;
             default:
-                hipLaunchKernelGGL(k_compress<kLoadBytes>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                {
+                    const int pr_ = prof_begin(st, "compress");
+                    hipLaunchKernelGGL(k_compress<kLoadBytes>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                    prof_end(st, pr_);
+                }
                 break;
         }
         CKEY_TRY(launch_status());

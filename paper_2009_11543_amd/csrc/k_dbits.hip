@@ -98,12 +98,20 @@ ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc, 
     const size_t lds = nw * sizeof(uint32_t);
     switch (load_mode(k)) {
         case kLoadBytes:
-            hipLaunchKernelGGL(k_dbits<kLoadBytes>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
-                               order, acc, flags);
+            {
+                const int pr_ = prof_begin(st, "dbits");
+                hipLaunchKernelGGL(k_dbits<kLoadBytes>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
+                                   order, acc, flags);
+                prof_end(st, pr_);
+            }
             break;
         default:
-            hipLaunchKernelGGL(k_dbits<kLoad4>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
-                               order, acc, flags);
+            {
+                const int pr_ = prof_begin(st, "dbits");
+                hipLaunchKernelGGL(k_dbits<kLoad4>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
+                                   order, acc, flags);
+                prof_end(st, pr_);
+            }
             break;
     }
     return launch_status();

@@ -320,8 +320,12 @@ ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *r
             ++ha.npass;
             ++p;
         }
-        hipLaunchKernelGGL(k_hist, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, ck + uint64_t(wk) * n,
-                           n, ha, hist);
+        {
+            const int pr_ = prof_begin(st, "hist");
+            hipLaunchKernelGGL(k_hist, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, ck + uint64_t(wk) * n,
+                               n, ha, hist);
+            prof_end(st, pr_);
+        }
         CKEY_TRY(launch_status());
         p0 = p;
     }
@@ -334,8 +338,12 @@ ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *r
     uint32_t *dr = alt_rid;
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
-        hipLaunchKernelGGL(k_onesweep, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, s, sr, dk, dr, n,
-                           words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+        {
+            const int pr_ = prof_begin(st, "onesweep");
+            hipLaunchKernelGGL(k_onesweep, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, s, sr, dk, dr, n,
+                               words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+            prof_end(st, pr_);
+        }
         CKEY_TRY(launch_status());
         // swap
         const uint64_t *ns = dk;

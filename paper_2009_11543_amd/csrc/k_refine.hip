@@ -84,8 +84,12 @@ ckey_status refine_launch(const uint64_t *ck, uint32_t words, uint64_t n, const 
     const size_t lds = nw * sizeof(uint32_t) + ((nbits + 1) / 2) * sizeof(uint32_t);
     uint64_t blocks = (n - 1 + kWG - 1) / kWG;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_refine, dim3(uint32_t(blocks)), dim3(kWG), lds, st, ck, words, n, bm, L,
-                       nbits, acc, pair_pos);
+    {
+        const int pr_ = prof_begin(st, "refine");
+        hipLaunchKernelGGL(k_refine, dim3(uint32_t(blocks)), dim3(kWG), lds, st, ck, words, n, bm, L,
+                           nbits, acc, pair_pos);
+        prof_end(st, pr_);
+    }
     return launch_status();
 }
 
