@@ -51,7 +51,7 @@ typedef enum {
 #define CKEY_FLAG_DESCENDING   0x1u /* ckey_distinction_bits: an adjacent pair descends     */
 #define CKEY_FLAG_KEY_TOO_LONG 0x2u /* a variable-length key is longer than key_bytes       */
 #define CKEY_FLAG_SPIN_LIMIT   0x4u /* a sort pass gave up waiting on a predecessor tile    */
-#define CKEY_FLAG_BUCKET_OVERFLOW 0x8u /* learned sort: some bucket went to the radix fallback */
+#define CKEY_FLAG_BUCKET_OVERFLOW 0x8u /* bucketing sort: a bucket was finished by the radix sort */
 
 /* Limits of this build. */
 #define CKEY_MAX_KEY_BYTES 2048u          /* key_bytes                       */
@@ -105,23 +105,25 @@ typedef enum {
     CKEY_SORT_SPLITTER = 2 /* the same bucketing with a binary search of the thresholds */
 } ckey_sort_method;
 
-typedef struct ckey_cdf_model ckey_cdf_model; /* opaque, see ckey_cdf_* below */
-
 typedef struct {
-    uint32_t method;      /* ckey_sort_method                                         */
-    uint32_t digit_bits;  /* radix digit width, 1..8; 0 = 8                          */
-    uint32_t bucket_log2; /* learned/splitter bucket count = 2^bucket_log2; 0 = model's */
+    uint32_t method;      /* ckey_sort_method                                          */
+    uint32_t digit_bits;  /* radix digit width, 1..8; 0 = 8                           */
+    uint32_t bucket_log2; /* learned/splitter: log2 of the model's bucket count, 8..16 */
     uint32_t reserved;
-    const ckey_cdf_model *model; /* learned/splitter: trained model (thresholds + net)  */
-    uint32_t *flags;      /* device flags word or NULL                                */
+    const void *model;    /* learned/splitter: device model memory (ckey_cdf_*)        */
+    uint32_t *flags;      /* device flags word or NULL                                 */
 } ckey_sort_opts;
 
 /* Sort (compressed key, row id) pairs (Sec. 3.2 compressed key sort; Sec. 5,
  * step 3) in place: afterwards ckeys (device, word-major, words x n) are in
  * ascending order of their top nbits and rowids (device uint32[n]) moved with
- * them.  The sort is stable, so with rowids = 0..n-1 (as ckey_compress
- * writes them) ties are broken by row id, as in the paper's sort key.
- * opts may be NULL (radix, 8-bit digits).  Needs a workspace. */
+ * them.  Ties go to the smaller row id, as in the paper's sort key (row id
+ * inside the sort key): the radix method is stable (so this holds when the
+ * row ids arrive ascending, as ckey_compress writes them); the bucketing
+ * methods compare row ids explicitly.  opts may be NULL (radix, 8-bit
+ * digits).  The bucketing methods synchronize `stream` once to learn whether
+ * a bucket overflowed the in-LDS sort (those buckets are finished by the radix
+ * sort and raise CKEY_FLAG_BUCKET_OVERFLOW).  Needs a workspace. */
 ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
                       uint64_t n, const ckey_sort_opts *opts, void *workspace,
                       size_t *workspace_bytes, void *stream);
@@ -147,6 +149,54 @@ typedef struct {
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *workspace,
                                size_t *workspace_bytes, void *stream);
+
+/* ---- CDF model for learned bucketing (an extension; not in the paper) -------
+ * Model memory is device memory owned by the caller, ckey_cdf_model_bytes()
+ * long, 256-byte aligned: a 4 -> 64 -> 1 ReLU MLP (385 fp32 parameters, plus
+ * Adam moments) and a table T of 2^bucket_log2 sorted 64-bit thresholds.
+ * bucket(x) = the b with T[b] <= x < T[b+1] for the key's first compressed
+ * word x; it is non-decreasing in key order.  The network predicts b from x's
+ * four 16-bit chunks (each / 65536); an exponential-then-binary search from
+ * the prediction makes it exact, so results never depend on the network. */
+size_t ckey_cdf_model_bytes(uint32_t bucket_log2);
+
+/* Initialise the parameters deterministically from `seed`, zero the moments. */
+ckey_status ckey_cdf_model_init(void *model, uint32_t bucket_log2, uint64_t seed, void *stream);
+
+typedef struct {
+    uint32_t steps;   /* Adam steps                                  */
+    uint32_t batch;   /* samples per step, 1..2^20                   */
+    float lr, beta1, beta2, eps;
+    uint64_t seed;    /* minibatch sampling: sample j of step s is row
+                         SplitMix64(seed + phi*((s << 32) + j + 1)) mod m */
+} ckey_cdf_train_opts;
+
+/* Fit a model to the sorted first compressed words of a training set
+ * (device uint64[m], ascending): T[b] = sorted_prefix[b*m / 2^bucket_log2]
+ * (T[0] = 0), then `steps` Adam steps on the mean squared error between the
+ * network output and the normalised rank (r + 0.5)/m of sampled rows.
+ * loss_trace: device float[steps] (or NULL) receives each step's loss.
+ * Needs a workspace. */
+ckey_status ckey_cdf_fit(void *model, uint32_t bucket_log2, const uint64_t *sorted_prefix,
+                         uint64_t m, const ckey_cdf_train_opts *opts, float *loss_trace,
+                         void *workspace, size_t *workspace_bytes, void *stream);
+
+/* Loss and gradient of the network on an explicit batch: prefix (device
+ * uint64[m]) and target (device float[m]); grad: device float[385] in the
+ * parameter order W1[k][j] (k<64, j<4), b1[k], w2[k], b2; loss: device
+ * float.  Reductions run in a fixed order (deterministic).  Needs a workspace. */
+ckey_status ckey_cdf_grad(const void *model, const uint64_t *prefix, const float *target,
+                          uint64_t m, float *grad, float *loss, void *workspace,
+                          size_t *workspace_bytes, void *stream);
+
+/* Exact bucket of n prefixes (device uint64[n]) into bucket (device
+ * uint32[n]) with method CKEY_SORT_LEARNED or CKEY_SORT_SPLITTER; predicted
+ * (device uint32[n] or NULL, learned only) gets the network's raw guess;
+ * stats (device uint64[2] or NULL, accumulated) gets the number of threshold
+ * probes read from global memory and the summed |bucket - guess|. */
+ckey_status ckey_cdf_bucket(const void *model, uint32_t bucket_log2, uint32_t method,
+                            const uint64_t *prefix, uint64_t n, uint32_t *bucket,
+                            uint32_t *predicted, uint64_t *stats, void *stream);
 
 /* ---- Benchmark support (not part of the method) ---------------------------
  * Per-kernel timing: while enabled, every launch of the library's main kernels

@@ -18,7 +18,7 @@ _lib = None
 
 def build():
     """Compile oracle.c into liboracle.so (gcc -O2)."""
-    subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC])
+    subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC, "-lm"])
 
 
 def _load():
@@ -42,13 +42,12 @@ def _load():
         lib.oracle_csort.argtypes = [P, U32, U64, P]
         lib.oracle_refine.argtypes = [P, U32, U64, P, P, U32, P, P]
         lib.oracle_variant.argtypes = keys + [U64, P]
-        if hasattr(lib, "oracle_mlp_loss_grad"):
-            lib.oracle_mlp_loss_grad.argtypes = [P, P, P, U64, P]
-            lib.oracle_mlp_loss_grad.restype = ctypes.c_double
-            lib.oracle_mlp_forward.argtypes = [P, P, U64, P]
-            lib.oracle_adam.argtypes = [P, P, P, P, U32, ctypes.c_double, ctypes.c_double,
-                                        ctypes.c_double, ctypes.c_double, U32]
-            lib.oracle_bucket.argtypes = [P, U64, P, U32, P]
+        lib.oracle_mlp_loss_grad.argtypes = [P, P, P, U64, P]
+        lib.oracle_mlp_loss_grad.restype = ctypes.c_double
+        lib.oracle_mlp_forward.argtypes = [P, P, U64, P]
+        D = ctypes.c_double
+        lib.oracle_adam.argtypes = [P, P, P, P, U32, D, D, D, D, U32]
+        lib.oracle_bucket.argtypes = [P, U64, P, U32, P]
         _lib = lib
     return _lib
 
@@ -183,4 +182,48 @@ def refine(ck, perm, bitmap_in):
 def variant(k, ref_row=0):
     out = np.zeros(k.L, np.uint8)
     _load().oracle_variant(*k.args(), ref_row, _ptr(out))
+    return out
+
+
+# ------------------------------------------------------------ CDF model --
+MLP_H = 64
+MLP_P = 6 * MLP_H + 1
+
+
+def mlp_features(prefix):
+    """(n, 4) float64 features: four 16-bit chunks of each 64-bit prefix, /65536."""
+    x = np.asarray(prefix, np.uint64)
+    cols = [((x >> np.uint64(48 - 16 * j)) & np.uint64(0xFFFF)).astype(np.float64) / 65536.0
+            for j in range(4)]
+    return np.ascontiguousarray(np.stack(cols, 1))
+
+
+def mlp_forward(p, X):
+    p = np.ascontiguousarray(p, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    y = np.zeros(len(X), np.float64)
+    _load().oracle_mlp_forward(_ptr(p), _ptr(X), len(X), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(p, X, t):
+    p = np.ascontiguousarray(p, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.zeros(MLP_P, np.float64)
+    loss = _load().oracle_mlp_loss_grad(_ptr(p), _ptr(X), _ptr(t), len(X), _ptr(g))
+    return loss, g
+
+
+def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays p, m, v."""
+    g = np.ascontiguousarray(g, np.float64)
+    _load().oracle_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), len(p), lr, b1, b2, eps, t)
+
+
+def bucket(prefix, T):
+    x = np.ascontiguousarray(prefix, np.uint64)
+    T = np.ascontiguousarray(T, np.uint64)
+    out = np.zeros(len(x), np.uint32)
+    _load().oracle_bucket(_ptr(x), len(x), _ptr(T), len(T), _ptr(out))
     return out

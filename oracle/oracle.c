@@ -19,6 +19,14 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
+
+static double pow_u(double b, uint32_t e)
+{
+    double r = 1;
+    while (e--) r *= b;
+    return r;
+}
 
 /* ------------------------------------------------------------------------- */
 /* Key access                                                                 */
@@ -318,4 +326,86 @@ int oracle_variant(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
     for (uint64_t i = 0; i < n; ++i)
         for (uint32_t j = 0; j < L; ++j) variant[j] |= key_byte(&k, i, j) ^ key_byte(&k, ref_row, j);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* CDF model for learned bucketing (not in the paper; the model of the       */
+/* learned bucketing extension).  fp64 reference of a 4 -> H -> 1 ReLU MLP.  */
+/* Parameter vector p (length 6H + 1):                                        */
+/*   W1[k][j] = p[4k + j] (k < H, j < 4), b1[k] = p[4H + k], w2[k] = p[5H + k],*/
+/*   b2 = p[6H].                                                              */
+/* Features of a 64-bit key prefix x: f_j = ((x >> (48 - 16 j)) & 0xFFFF)/65536. */
+/* ------------------------------------------------------------------------- */
+
+#define MLP_H 64
+#define MLP_P (6 * MLP_H + 1)
+
+static double mlp_forward_one(const double *p, const double *x, double *h)
+{
+    double y = p[6 * MLP_H];
+    for (int k = 0; k < MLP_H; ++k) {
+        double a = p[4 * MLP_H + k];
+        for (int j = 0; j < 4; ++j) a += p[4 * k + j] * x[j];
+        h[k] = a > 0 ? a : 0;
+        y += p[5 * MLP_H + k] * h[k];
+    }
+    return y;
+}
+
+/* y[i] = MLP(X[i]) for M rows of 4 features. */
+void oracle_mlp_forward(const double *p, const double *X, uint64_t M, double *y)
+{
+    double h[MLP_H];
+    for (uint64_t i = 0; i < M; ++i) y[i] = mlp_forward_one(p, X + 4 * i, h);
+}
+
+/* Mean squared error over M rows and its gradient with respect to p. */
+double oracle_mlp_loss_grad(const double *p, const double *X, const double *t, uint64_t M,
+                            double *grad)
+{
+    double h[MLP_H], loss = 0;
+    memset(grad, 0, sizeof(double) * MLP_P);
+    for (uint64_t i = 0; i < M; ++i) {
+        const double *x = X + 4 * i;
+        double e = mlp_forward_one(p, x, h) - t[i];
+        loss += e * e;
+        double dy = 2.0 * e / (double)M;        /* d(mean e^2)/dy */
+        grad[6 * MLP_H] += dy;                  /* b2 */
+        for (int k = 0; k < MLP_H; ++k) {
+            grad[5 * MLP_H + k] += dy * h[k];   /* w2 */
+            if (h[k] > 0) {
+                double g = dy * p[5 * MLP_H + k];
+                grad[4 * MLP_H + k] += g;       /* b1 */
+                for (int j = 0; j < 4; ++j) grad[4 * k + j] += g * x[j];
+            }
+        }
+    }
+    return loss / (double)M;
+}
+
+/* One Adam step (Kingma & Ba) on n parameters at step t (1-based). */
+void oracle_adam(double *p, const double *g, double *m, double *v, uint32_t n, double lr,
+                 double b1, double b2, double eps, uint32_t t)
+{
+    for (uint32_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1 - b1) * g[i];
+        v[i] = b2 * v[i] + (1 - b2) * g[i] * g[i];
+        double mh = m[i] / (1 - pow_u(b1, t));
+        double vh = v[i] / (1 - pow_u(b2, t));
+        p[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* bucket[i] = the b with T[b] <= x[i] < T[b+1] (T[B] taken as +infinity),
+ * for a non-decreasing threshold table T of B entries with T[0] = 0. */
+void oracle_bucket(const uint64_t *x, uint64_t n, const uint64_t *T, uint32_t B, uint32_t *bucket)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t lo = 0, hi = B; /* invariant: T[lo] <= x < T[hi] */
+        while (hi - lo > 1) {
+            uint32_t mid = lo + (hi - lo) / 2;
+            if (T[mid] <= x[i]) lo = mid; else hi = mid;
+        }
+        bucket[i] = lo;
+    }
 }

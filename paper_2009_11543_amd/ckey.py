@@ -178,7 +178,9 @@ def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, s
     return ck, rid
 
 
-def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=0, model=None, flags=None):
+def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=None, model=None, flags=None):
+    if bucket_log2 is None:
+        bucket_log2 = model.bucket_log2 if model is not None else 0
     return ckey_sort_opts(method, digit_bits, bucket_log2, 0,
                           None if model is None else model.handle,
                           None if flags is None else flags.data_ptr())
@@ -251,3 +253,99 @@ def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
 def as_u64(t):
     """Device int64 tensor of word bit patterns -> host numpy uint64 array."""
     return t.cpu().numpy().view(np.uint64)
+
+
+# ----------------------------------------------------- learned bucketing --
+
+class ckey_cdf_train_opts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib.ckey_cdf_model_bytes.argtypes = [ctypes.c_uint32]
+_lib.ckey_cdf_model_bytes.restype = ctypes.c_size_t
+_lib.ckey_cdf_model_init.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+_lib.ckey_cdf_fit.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                              ctypes.POINTER(ckey_cdf_train_opts), ctypes.c_void_p, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
+_lib.ckey_cdf_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
+_lib.ckey_cdf_bucket.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p]
+for _fn in ("ckey_cdf_model_init", "ckey_cdf_fit", "ckey_cdf_grad", "ckey_cdf_bucket"):
+    getattr(_lib, _fn).restype = ctypes.c_int
+
+MODEL_PARAMS = 385
+_OFF_T = 8192
+
+
+class CdfModel:
+    """Device memory of a CDF model (thresholds + MLP), owned by torch."""
+
+    def __init__(self, bucket_log2=14, seed=0, device="cuda", stream=None):
+        nbytes = _lib.ckey_cdf_model_bytes(bucket_log2)
+        if nbytes == 0:
+            raise CkeyError("ckey_cdf_model_bytes", CKEY_ERR_INVALID)
+        self.bucket_log2 = bucket_log2
+        self.mem = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+        _check("ckey_cdf_model_init", _lib.ckey_cdf_model_init(self.handle, bucket_log2, seed,
+                                                               _stream(stream)))
+
+    @property
+    def handle(self):
+        return self.mem.data_ptr()
+
+    def params(self):
+        return self.mem[: 4 * MODEL_PARAMS].view(torch.float32)
+
+    def thresholds(self):
+        return self.mem[_OFF_T:].view(torch.int64)
+
+
+def ckey_cdf_fit(model, sorted_prefix, steps=500, batch=1 << 14, lr=3e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, seed=1, stream=None):
+    """Fit thresholds and train the network; returns the per-step loss (device)."""
+    o = ckey_cdf_train_opts(steps, batch, lr, beta1, beta2, eps, seed)
+    need = ctypes.c_size_t(0)
+    _check("ckey_cdf_fit", _lib.ckey_cdf_fit(None, model.bucket_log2, None, 0, ctypes.byref(o), None,
+                                             None, ctypes.byref(need), None))
+    dev = model.mem.device
+    ws = _workspace(need.value, dev)
+    trace = torch.zeros(max(steps, 1), dtype=torch.float32, device=dev)
+    need = ctypes.c_size_t(ws.numel())
+    _check("ckey_cdf_fit", _lib.ckey_cdf_fit(model.handle, model.bucket_log2, _ptr(sorted_prefix),
+                                             sorted_prefix.numel(), ctypes.byref(o), _ptr(trace),
+                                             _ptr(ws), ctypes.byref(need), _stream(stream)))
+    return trace[:steps]
+
+
+def ckey_cdf_grad(model, prefix, target, stream=None):
+    """(grad float32[385], loss float32[1]) of the network on an explicit batch."""
+    need = ctypes.c_size_t(0)
+    _check("ckey_cdf_grad", _lib.ckey_cdf_grad(None, None, None, prefix.numel(), None, None, None,
+                                               ctypes.byref(need), None))
+    dev = model.mem.device
+    ws = _workspace(need.value, dev)
+    grad = torch.zeros(MODEL_PARAMS, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    need = ctypes.c_size_t(ws.numel())
+    _check("ckey_cdf_grad", _lib.ckey_cdf_grad(model.handle, _ptr(prefix), _ptr(target), prefix.numel(),
+                                               _ptr(grad), _ptr(loss), _ptr(ws), ctypes.byref(need),
+                                               _stream(stream)))
+    return grad, loss
+
+
+def ckey_cdf_bucket(model, prefix, method=CKEY_SORT_LEARNED, stream=None):
+    """(exact bucket int32[n], network guess int32[n] or None, stats int64[2])."""
+    dev = model.mem.device
+    n = prefix.numel()
+    bucket = torch.empty(n, dtype=torch.int32, device=dev)
+    pred = torch.empty(n, dtype=torch.int32, device=dev) if method == CKEY_SORT_LEARNED else None
+    stats = torch.zeros(2, dtype=torch.int64, device=dev)
+    _check("ckey_cdf_bucket", _lib.ckey_cdf_bucket(model.handle, model.bucket_log2, method,
+                                                   _ptr(prefix), n, _ptr(bucket), _ptr(pred),
+                                                   _ptr(stats), _stream(stream)))
+    return bucket, pred, stats

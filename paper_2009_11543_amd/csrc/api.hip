@@ -52,6 +52,34 @@ uint32_t digit_bits_of(const ckey_sort_opts *o) {
     return d == 0 ? 8 : d;
 }
 
+uint32_t method_of(const ckey_sort_opts *o) { return o ? o->method : uint32_t(CKEY_SORT_RADIX); }
+
+ckey_status check_sort_opts(const ckey_sort_opts *o, bool need_model) {
+    const uint32_t m = method_of(o);
+    if (m == CKEY_SORT_RADIX) {
+        const uint32_t d = digit_bits_of(o);
+        return (d >= 1 && d <= 8) ? CKEY_OK : CKEY_ERR_INVALID;
+    }
+    if (m != CKEY_SORT_LEARNED && m != CKEY_SORT_SPLITTER) return CKEY_ERR_INVALID;
+    if (!learned_b_ok(o->bucket_log2)) return CKEY_ERR_INVALID;
+    if (need_model && !o->model) return CKEY_ERR_INVALID;
+    return CKEY_OK;
+}
+
+size_t sort_workspace(const ckey_sort_opts *o, uint32_t words, uint32_t nbits, uint64_t n) {
+    if (method_of(o) == CKEY_SORT_RADIX) return radix_workspace(words, nbits, n, digit_bits_of(o));
+    return learned_workspace(words, nbits, n, o->bucket_log2);
+}
+
+ckey_status sort_dispatch(const ckey_sort_opts *o, uint64_t *ck, uint32_t words, uint32_t nbits,
+                          uint32_t *rid, uint64_t n, uint32_t *flags, void *ws, hipStream_t st) {
+    const uint32_t m = method_of(o);
+    if (m == CKEY_SORT_RADIX)
+        return radix_sort(ck, n, words, nbits, rid, n, digit_bits_of(o), 0, flags, ws, st);
+    return learned_sort(ck, words, nbits, rid, n, m == CKEY_SORT_LEARNED ? 1 : 0, o->model,
+                        o->bucket_log2, flags, ws, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -121,25 +149,20 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
                       const ckey_sort_opts *opts, void *ws, size_t *ws_bytes, void *stream) {
     if (n > CKEY_MAX_ROWS) return CKEY_ERR_UNSUPPORTED;
     if (words == 0 || nbits > 64ull * words) return CKEY_ERR_INVALID;
-    const uint32_t method = opts ? opts->method : CKEY_SORT_RADIX;
-    const uint32_t d = digit_bits_of(opts);
-    if (d < 1 || d > 8) return CKEY_ERR_INVALID;
-    if (method != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    CKEY_TRY(check_sort_opts(opts, ws != nullptr));
     bool query;
-    CKEY_TRY(ws_check(ws, ws_bytes, radix_workspace(words, nbits, n, d), query));
+    CKEY_TRY(ws_check(ws, ws_bytes, sort_workspace(opts, words, nbits, n), query));
     if (query) return CKEY_OK;
     if (n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
-    return radix_sort(ckeys, words, nbits, rowids, n, d, opts ? opts->flags : nullptr, ws,
-                      as_stream(stream));
+    return sort_dispatch(opts, ckeys, words, nbits, rowids, n, opts ? opts->flags : nullptr, ws,
+                         as_stream(stream));
 }
 
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *ws, size_t *ws_bytes,
                                void *stream) {
     if (!idx || count == 0) return CKEY_ERR_INVALID;
-    const uint32_t d = digit_bits_of(opts);
-    if (d < 1 || d > 8) return CKEY_ERR_INVALID;
-    if (opts && opts->method != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    CKEY_TRY(check_sort_opts(opts, ws != nullptr));
     // Per-index plan and workspace; indexes run one after another and share it.
     size_t need = 0;
     std::vector<std::vector<uint8_t>> bms(count);
@@ -155,7 +178,7 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
         const uint64_t n = D.keys.n;
         size_t s = align256((L + 3) / 4 * 4);
         if (!D.ckeys) s += align256(size_t(w) * n * 8);
-        s += radix_workspace(w, nb, n, d);
+        s += sort_workspace(opts, w, nb, n);
         if (s > need) need = s;
     }
     bool query;
@@ -179,7 +202,7 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
         }
         uint32_t *flags = D.flags ? D.flags : (opts ? opts->flags : nullptr);
         CKEY_TRY(compress_launch(key_src(&D.keys), bm, ck, w, D.perm, flags, st));
-        CKEY_TRY(radix_sort(ck, w, nb, D.perm, n, d, flags, p, st));
+        CKEY_TRY(sort_dispatch(opts, ck, w, nb, D.perm, n, flags, p, st));
         if (D.bitmap_out || D.pair_pos) {
             CKEY_TRY(fill_u32(acc, (L + 3) / 4, 0, st));
             CKEY_TRY(refine_launch(ck, w, n, bm, L, acc, D.pair_pos, flags, st));
@@ -187,6 +210,52 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
         }
     }
     return CKEY_OK;
+}
+
+size_t ckey_cdf_model_bytes(uint32_t b_log2) { return learned_b_ok(b_log2) ? model_bytes(b_log2) : 0; }
+
+ckey_status ckey_cdf_model_init(void *model, uint32_t b_log2, uint64_t seed, void *stream) {
+    if (!model || reinterpret_cast<uintptr_t>(model) % 256) return CKEY_ERR_INVALID;
+    if (!learned_b_ok(b_log2)) return CKEY_ERR_INVALID;
+    return model_init(model, seed, as_stream(stream));
+}
+
+ckey_status ckey_cdf_fit(void *model, uint32_t b_log2, const uint64_t *sorted_prefix, uint64_t m,
+                         const ckey_cdf_train_opts *o, float *loss_trace, void *ws,
+                         size_t *ws_bytes, void *stream) {
+    if (!o || !learned_b_ok(b_log2)) return CKEY_ERR_INVALID;
+    if (o->batch == 0 || o->batch > (1u << 20)) return CKEY_ERR_INVALID;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, grad_workspace(o->batch), query));
+    if (query) return CKEY_OK;
+    if (!model || !sorted_prefix || m == 0) return CKEY_ERR_INVALID;
+    hipStream_t st = as_stream(stream);
+    CKEY_TRY(model_thresholds(model, b_log2, sorted_prefix, m, st));
+    return model_train(model, sorted_prefix, m, o->steps, o->batch, o->lr, o->beta1, o->beta2,
+                       o->eps, o->seed, loss_trace, ws, st);
+}
+
+ckey_status ckey_cdf_grad(const void *model, const uint64_t *prefix, const float *target,
+                          uint64_t m, float *grad, float *loss, void *ws, size_t *ws_bytes,
+                          void *stream) {
+    if (m == 0 || m > (1u << 20)) return CKEY_ERR_INVALID;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, grad_workspace(uint32_t(m)), query));
+    if (query) return CKEY_OK;
+    if (!model || !prefix || !target || (!grad && !loss)) return CKEY_ERR_INVALID;
+    return model_grad(model, prefix, target, m, uint32_t(m), 0, 0, grad, loss, ws, as_stream(stream));
+}
+
+ckey_status ckey_cdf_bucket(const void *model, uint32_t b_log2, uint32_t method,
+                            const uint64_t *prefix, uint64_t n, uint32_t *bucket,
+                            uint32_t *predicted, uint64_t *stats, void *stream) {
+    if (!learned_b_ok(b_log2)) return CKEY_ERR_INVALID;
+    if (method != CKEY_SORT_LEARNED && method != CKEY_SORT_SPLITTER) return CKEY_ERR_INVALID;
+    if (n > 0 && (!model || !prefix || !bucket)) return CKEY_ERR_INVALID;
+    if (n > CKEY_MAX_ROWS) return CKEY_ERR_UNSUPPORTED;
+    return model_bucket(model, b_log2, method == CKEY_SORT_LEARNED ? 1 : 0, prefix, n, bucket,
+                        method == CKEY_SORT_LEARNED ? predicted : nullptr,
+                        reinterpret_cast<unsigned long long *>(stats), as_stream(stream));
 }
 
 }  // extern "C"

@@ -101,11 +101,40 @@ ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
                           const uint8_t *bitmap_in_host, uint32_t L, uint32_t *acc_words,
                           uint32_t *pair_pos, uint32_t *flags, hipStream_t st);
 
-// Radix sort (k_radix.hip).
-size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits);
-ckey_status radix_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
-                       uint64_t n, uint32_t digit_bits, uint32_t *flags, void *ws,
+// Radix sort (k_radix.hip): stable LSD sort of rows [0, n) of word-major keys
+// (word k of row i at ckeys[k*ld + i]) by their top nbits, moving rowids
+// along.  rid_bits > 0 first sorts by the low rid_bits bits of the row ids,
+// so that ties end up in row-id order whatever the input order.
+size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits,
+                       uint32_t rid_bits = 0);
+ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nbits,
+                       uint32_t *rowids, uint64_t n, uint32_t digit_bits, uint32_t rid_bits,
+                       uint32_t *flags, void *ws, hipStream_t st);
+
+// OR a value into a device flags word (a kernel, so it is stream-ordered).
+ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st);
+
+// Learned bucketing (k_learned.hip).  mode 1 = learned (MLP + correction),
+// mode 0 = splitter search.
+bool learned_b_ok(uint32_t b_log2);
+size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2);
+ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
+                         int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
+                         hipStream_t st);
+size_t model_bytes(uint32_t b_log2);
+ckey_status model_init(void *model, uint64_t seed, hipStream_t st);
+ckey_status model_thresholds(void *model, uint32_t b_log2, const uint64_t *sorted, uint64_t m,
+                             hipStream_t st);
+size_t grad_workspace(uint32_t M);
+ckey_status model_grad(const void *model, const uint64_t *prefix, const float *target, uint64_t m,
+                       uint32_t M, uint64_t seed, uint32_t step, float *grad, float *loss, void *ws,
                        hipStream_t st);
+ckey_status model_train(void *model, const uint64_t *prefix, uint64_t m, uint32_t steps, uint32_t M,
+                        float lr, float b1, float b2, float eps, uint64_t seed, float *loss_trace,
+                        void *ws, hipStream_t st);
+ckey_status model_bucket(const void *model, uint32_t b_log2, int mode, const uint64_t *prefix,
+                         uint64_t n, uint32_t *bucket, uint32_t *pred, unsigned long long *stats,
+                         hipStream_t st);
 
 }  // namespace ckey
 

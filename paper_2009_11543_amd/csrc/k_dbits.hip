@@ -75,6 +75,13 @@ __global__ void k_bitmap_finalize(const uint32_t *acc, uint8_t *bitmap, uint32_t
         bitmap[j] = uint8_t(acc[j >> 2] >> (8 * (j & 3)));
 }
 
+__global__ void k_flag_or(uint32_t *f, uint32_t v) { atomicOr(f, v); }
+
+ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_flag_or, dim3(1), dim3(1), 0, st, flags, v);
+    return launch_status();
+}
+
 ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
     if (n == 0) return CKEY_OK;
     uint64_t blocks = (n + kWG - 1) / kWG;

@@ -1,0 +1,702 @@
+// Learned bucketing sort of compressed keys (an extension of the paper's
+// compressed key sort; the paper itself sorts by comparison, Appendix A).
+//
+// Model (device memory owned by the caller, layout below): a threshold table
+// T[0..B) of 64-bit key prefixes (T[0] = 0; T[b] = the prefix of rank b*m/B
+// in a sorted training set) and a 4 -> 64 -> 1 ReLU MLP predicting the
+// normalised rank of a prefix from its four 16-bit chunks.
+//
+// bucket(x) = the b with T[b] <= prefix(x) < T[b+1].  It is non-decreasing in
+// key order, so concatenating the buckets, each sorted, sorts everything.
+// The MLP only predicts where to start looking: an exponential-then-binary
+// search from the prediction always lands on the exact bucket, so exactness
+// never depends on the network (the splitter method instead searches a
+// 1-in-S sample of T held in LDS, then T itself).
+//
+// Sort: assign buckets (+ histogram) -> scan -> scatter records to their
+// bucket ranges (one atomic cursor per bucket) -> one workgroup per bucket
+// sorts it in LDS by the 32 prefix bits below the bucket's common prefix
+// (stable 8-bit LSD passes with wave ballots, skipping constant digits), then
+// orders runs of equal 32-bit keys by the full record (words, then row id).
+// Buckets larger than the LDS capacity, or with a run of equal 32-bit keys
+// longer than kRunCap, are copied through unsorted and finished by the radix
+// sort (row-id digits first, so ties still end in row-id order).
+#include <math.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace ckey {
+
+namespace {
+
+constexpr int kH = 64;
+constexpr int kNP = 6 * kH + 1;  // parameters
+constexpr int kNPad = 392;       // parameters + loss slot, padded
+constexpr int kLoss = kNP;       // index of the loss in a partial-sum row
+constexpr size_t kOffParams = 0, kOffM = 2048, kOffV = 4096, kOffT = 8192;
+constexpr int kCap = 5120;       // max bucket size sorted in LDS
+constexpr int kRunCap = 32;      // max run of equal 32-bit local keys
+constexpr int kAssignWG = 1024;
+constexpr uint32_t kKeysPerAssignWG = 65535;  // keeps the packed 16-bit LDS counters exact
+
+inline float *params_of(void *model) { return reinterpret_cast<float *>(static_cast<uint8_t *>(model) + kOffParams); }
+inline const float *params_of(const void *model) {
+    return reinterpret_cast<const float *>(static_cast<const uint8_t *>(model) + kOffParams);
+}
+inline const uint64_t *thresholds_of(const void *model) {
+    return reinterpret_cast<const uint64_t *>(static_cast<const uint8_t *>(model) + kOffT);
+}
+
+__device__ __forceinline__ void features(uint64_t x, float f[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f[j] = float(uint32_t(x >> (48 - 16 * j)) & 0xFFFFu) * (1.0f / 65536.0f);
+}
+
+__device__ __forceinline__ float mlp_eval(const float *__restrict__ p, const float f[4]) {
+    float y = p[6 * kH];
+#pragma unroll 16
+    for (int k = 0; k < kH; ++k) {
+        float a = p[4 * kH + k];
+        a = fmaf(p[4 * k + 0], f[0], a);
+        a = fmaf(p[4 * k + 1], f[1], a);
+        a = fmaf(p[4 * k + 2], f[2], a);
+        a = fmaf(p[4 * k + 3], f[3], a);
+        y = fmaf(p[5 * kH + k], fmaxf(a, 0.0f), y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ uint32_t predict_bucket(const float *__restrict__ p, uint64_t x, uint32_t B) {
+    float f[4];
+    features(x, f);
+    const float y = mlp_eval(p, f) * float(B);
+    if (!(y > 0.0f)) return 0;  // also maps NaN to 0
+    if (y >= float(B)) return B - 1;
+    return uint32_t(y);
+}
+
+// Exact bucket from a start guess: exponential search outward, then binary.
+__device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ T, uint32_t B,
+                                                   uint64_t x, uint32_t pb, uint32_t &probes) {
+    uint32_t lo, hi;  // T[lo] <= x and (hi == B or T[hi] > x)
+    ++probes;
+    if (T[pb] <= x) {
+        lo = pb;
+        hi = B;
+        for (uint32_t step = 1;; step <<= 1) {
+            const uint32_t j = lo + step;
+            if (j >= B) break;
+            ++probes;
+            if (T[j] > x) { hi = j; break; }
+            lo = j;
+        }
+    } else {
+        hi = pb;
+        lo = 0;  // T[0] = 0 <= x
+        for (uint32_t step = 1;; step <<= 1) {
+            if (hi <= step) break;
+            const uint32_t j = hi - step;
+            ++probes;
+            if (T[j] <= x) { lo = j; break; }
+            hi = j;
+        }
+    }
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        ++probes;
+        if (T[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // SplitMix64 finaliser (Steele, Lea, Flood 2014).
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------ model --
+
+__global__ void k_model_init(float *p, float *m, float *v, uint64_t seed) {
+    const int t = threadIdx.x;
+    if (t >= kNPad) return;
+    const float noise = float(int64_t(mix64(seed + 0x9E3779B97F4A7C15ull * (t + 1)) >> 40) - (1 << 23)) *
+                        (1.0f / float(1 << 23)) * 1e-3f;
+    float val = 0.0f;
+    if (t < 4 * kH) {
+        val = (t % 4 == 0) ? 1.0f + noise : noise;   // W1: unit k watches the top chunk
+    } else if (t < 5 * kH) {
+        val = -float(t - 4 * kH) / float(kH);        // b1: kinks spread over [0, 1)
+    } else if (t < 6 * kH) {
+        val = (t == 5 * kH ? 1.0f : 0.0f) + noise;   // w2: start from the uniform CDF
+    }
+    p[t] = t < kNP ? val : 0.0f;
+    m[t] = 0.0f;
+    v[t] = 0.0f;
+}
+
+__global__ void k_thresholds(const uint64_t *__restrict__ sorted, uint64_t m, uint64_t *__restrict__ T,
+                             uint32_t B) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    T[b] = b == 0 ? 0ull : sorted[(uint64_t(b) * m) / B];
+}
+
+// Forward + backward on M samples; per-block partial sums (fixed order).
+// target == nullptr: sample i = hash(seed, step, j) mod m, target (i+0.5)/m.
+__global__ __launch_bounds__(kWG) void k_mlp_grad(const float *__restrict__ p,
+                                                  const uint64_t *__restrict__ prefix,
+                                                  const float *__restrict__ target, uint64_t m,
+                                                  uint32_t M, uint64_t seed, uint32_t step,
+                                                  float *__restrict__ partial) {
+    __shared__ float s_acc[kWG / 64][kNPad];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int t = tid; t < (kWG / 64) * kNPad; t += kWG) (&s_acc[0][0])[t] = 0.0f;
+    __syncthreads();
+    const float invM = 1.0f / float(M);
+    for (uint64_t base = uint64_t(blockIdx.x) * kWG + wave * 64; base < M;
+         base += uint64_t(gridDim.x) * kWG) {
+        const uint64_t j = base + lane;
+        const bool valid = j < M;
+        uint64_t i = j;
+        if (!target)
+            i = mix64(seed + 0x9E3779B97F4A7C15ull * ((uint64_t(step) << 32) + j + 1)) % m;
+        const uint64_t x = valid ? prefix[i] : 0ull;
+        const float t = valid ? (target ? target[i] : (float(i) + 0.5f) / float(m)) : 0.0f;
+        float f[4];
+        features(x, f);
+        float h[kH];
+        float y = p[6 * kH];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+            float a = p[4 * kH + k];
+            a = fmaf(p[4 * k + 0], f[0], a);
+            a = fmaf(p[4 * k + 1], f[1], a);
+            a = fmaf(p[4 * k + 2], f[2], a);
+            a = fmaf(p[4 * k + 3], f[3], a);
+            h[k] = fmaxf(a, 0.0f);
+            y = fmaf(p[5 * kH + k], h[k], y);
+        }
+        const float e = valid ? y - t : 0.0f;
+        const float dy = 2.0f * e * invM;
+        const float db2 = wave_sum(dy);
+        const float ls = wave_sum(e * e * invM);
+        if (lane == 0) {
+            s_acc[wave][6 * kH] += db2;
+            s_acc[wave][kLoss] += ls;
+        }
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+            const float g = h[k] > 0.0f ? dy * p[5 * kH + k] : 0.0f;
+            const float c_w2 = wave_sum(dy * h[k]);
+            const float c_b1 = wave_sum(g);
+            const float c0 = wave_sum(g * f[0]);
+            const float c1 = wave_sum(g * f[1]);
+            const float c2 = wave_sum(g * f[2]);
+            const float c3 = wave_sum(g * f[3]);
+            if (lane == 0) {
+                s_acc[wave][5 * kH + k] += c_w2;
+                s_acc[wave][4 * kH + k] += c_b1;
+                s_acc[wave][4 * k + 0] += c0;
+                s_acc[wave][4 * k + 1] += c1;
+                s_acc[wave][4 * k + 2] += c2;
+                s_acc[wave][4 * k + 3] += c3;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < kNPad; t += kWG) {
+        float s = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kWG / 64; ++w) s += s_acc[w][t];
+        partial[uint64_t(blockIdx.x) * kNPad + t] = s;
+    }
+}
+
+// Sum G partial rows in order; then either write grad/loss or take an Adam step.
+__global__ __launch_bounds__(512) void k_mlp_reduce(const float *__restrict__ partial, uint32_t G,
+                                                    float *__restrict__ grad_out,
+                                                    float *__restrict__ loss_out, float *p, float *m,
+                                                    float *v, float lr, float b1, float b2, float eps,
+                                                    uint32_t t) {
+    const int i = threadIdx.x;
+    if (i > kLoss) return;
+    float s = 0.0f;
+    for (uint32_t g = 0; g < G; ++g) s += partial[uint64_t(g) * kNPad + i];
+    if (i == kLoss) {
+        if (loss_out) *loss_out = s;
+        return;
+    }
+    if (grad_out) grad_out[i] = s;
+    if (p) {  // Adam (Kingma & Ba), bias-corrected
+        const float mi = b1 * m[i] + (1.0f - b1) * s;
+        const float vi = b2 * v[i] + (1.0f - b2) * s * s;
+        m[i] = mi;
+        v[i] = vi;
+        const float mh = mi / (1.0f - powf(b1, float(t)));
+        const float vh = vi / (1.0f - powf(b2, float(t)));
+        p[i] -= lr * mh / (sqrtf(vh) + eps);
+    }
+}
+
+// ------------------------------------------------------- bucket assignment --
+
+// MODE 0: splitter search (LDS sample of T, then T); MODE 1: MLP prediction + correction.
+template <int MODE>
+__global__ __launch_bounds__(kAssignWG) void k_bucket_assign(
+    const uint64_t *__restrict__ w0, uint64_t n, const float *__restrict__ p,
+    const uint64_t *__restrict__ T, uint32_t B, uint32_t S, uint16_t *__restrict__ bid,
+    uint32_t *__restrict__ bid32, uint32_t *__restrict__ pred, uint32_t *__restrict__ hist,
+    unsigned long long *__restrict__ stats) {
+    extern __shared__ uint32_t s_dyn[];
+    uint32_t *s_h = s_dyn;                                       // B/2 packed 16-bit counters
+    uint64_t *s_ts = reinterpret_cast<uint64_t *>(s_dyn + B / 2); // B/S sampled thresholds
+    const int tid = threadIdx.x;
+    if (hist)
+        for (uint32_t t = tid; t < B / 2; t += kAssignWG) s_h[t] = 0;
+    if (MODE == 0)
+        for (uint32_t t = tid; t < B / S; t += kAssignWG) s_ts[t] = T[uint64_t(t) * S];
+    __syncthreads();
+    const uint64_t i0 = uint64_t(blockIdx.x) * kKeysPerAssignWG;
+    const uint64_t i1 = min<uint64_t>(n, i0 + kKeysPerAssignWG);
+    uint32_t probes = 0, err = 0;
+    for (uint64_t i = i0 + tid; i < i1; i += kAssignWG) {
+        const uint64_t x = w0[i];
+        uint32_t b;
+        if (MODE == 1) {
+            const uint32_t pb = predict_bucket(p, x, B);
+            b = correct_bucket(T, B, x, pb, probes);
+            err += b > pb ? b - pb : pb - b;
+            if (pred) pred[i] = pb;
+        } else {
+            uint32_t lo = 0, hi = B / S;  // s_ts[lo] <= x < s_ts[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_ts[mid] <= x) lo = mid; else hi = mid;
+            }
+            uint32_t l2 = lo * S, h2 = min(B, (lo + 1) * S);
+            while (h2 - l2 > 1) {
+                const uint32_t mid = (l2 + h2) >> 1;
+                ++probes;
+                if (T[mid] <= x) l2 = mid; else h2 = mid;
+            }
+            b = l2;
+        }
+        if (bid) bid[i] = uint16_t(b);
+        if (bid32) bid32[i] = b;
+        if (hist) atomicAdd(&s_h[b >> 1], 1u << (16 * (b & 1)));
+    }
+    if (hist) {
+        __syncthreads();
+        for (uint32_t t = tid; t < B / 2; t += kAssignWG) {
+            const uint32_t v = s_h[t];
+            if (v & 0xFFFFu) atomicAdd(&hist[2 * t], v & 0xFFFFu);
+            if (v >> 16) atomicAdd(&hist[2 * t + 1], v >> 16);
+        }
+    }
+    if (stats) {
+        unsigned long long a = probes, e = err;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            a += __shfl_xor(a, off, 64);
+            e += __shfl_xor(e, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&stats[0], a);
+            atomicAdd(&stats[1], e);
+        }
+    }
+}
+
+// Exclusive scan of B counters by one 1024-thread workgroup -> starts[0..B], cursors.
+__global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict__ hist, uint32_t B,
+                                                      uint32_t *__restrict__ starts,
+                                                      uint32_t *__restrict__ cursor) {
+    __shared__ uint32_t s_w[16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint32_t per = (B + 1023) / 1024;
+    const uint32_t b0 = tid * per;
+    uint32_t sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (b0 + q < B) sum += hist[b0 + q];
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        off += w < wave ? s_w[w] : 0u;
+        tot += s_w[w];
+    }
+    uint32_t run = off + incl - sum;
+    for (uint32_t q = 0; q < per; ++q)
+        if (b0 + q < B) {
+            starts[b0 + q] = run;
+            cursor[b0 + q] = run;
+            run += hist[b0 + q];
+        }
+    if (tid == 0) starts[B] = tot;
+}
+
+struct Bufs {
+    const uint64_t *src;
+    const uint32_t *src_rid;
+    uint64_t *dst;
+    uint32_t *dst_rid;
+};
+
+template <int WC>
+__global__ __launch_bounds__(kWG) void k_bucket_scatter(Bufs bf, uint64_t n, uint32_t words_rt,
+                                                        const uint16_t *__restrict__ bid,
+                                                        uint32_t *__restrict__ cursor) {
+    const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
+    const uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t pos = atomicAdd(&cursor[bid[i]], 1u);
+    if (pos >= n) return;  // cannot happen when the histogram matches bid
+    for (uint32_t k = 0; k < words; ++k) bf.dst[uint64_t(k) * n + pos] = bf.src[uint64_t(k) * n + i];
+    bf.dst_rid[pos] = bf.src_rid[i];
+}
+
+// Full-record order of two rows of the bucket (words, then row id).
+template <int WC>
+__device__ __forceinline__ bool rec_less(const Bufs &bf, uint64_t n, uint32_t words, uint64_t a,
+                                         uint64_t b) {
+    for (uint32_t k = 0; k < words; ++k) {
+        const uint64_t x = bf.src[uint64_t(k) * n + a], y = bf.src[uint64_t(k) * n + b];
+        if (x != y) return x < y;
+    }
+    return bf.src_rid[a] < bf.src_rid[b];
+}
+
+template <int WC>
+__global__ __launch_bounds__(kWG) void k_bucket_sort(Bufs bf, uint64_t n, uint32_t words_rt,
+                                                     const uint32_t *__restrict__ starts,
+                                                     const uint64_t *__restrict__ T, uint32_t B,
+                                                     uint32_t *__restrict__ ovf) {
+    __shared__ uint32_t s_key[2][kCap];
+    __shared__ uint16_t s_idx[2][kCap];
+    __shared__ uint16_t s_rank[kCap];
+    __shared__ uint32_t s_wc[kWG / 64][256];
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_and, s_or, s_fail;
+    const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const uint32_t b = blockIdx.x;
+    const uint32_t start = starts[b];
+    const uint32_t cnt = starts[b + 1] - start;
+    if (cnt == 0) return;
+
+    bool fallback = cnt > uint32_t(kCap);
+    if (!fallback) {
+        const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
+        const uint32_t cp = lo == hi ? 64u : uint32_t(__clzll(lo ^ hi));
+        if (tid == 0) {
+            s_and = ~0u;
+            s_or = 0u;
+            s_fail = 0u;
+        }
+        __syncthreads();
+        uint32_t a_and = ~0u, a_or = 0u;
+        for (uint32_t j = tid; j < cnt; j += kWG) {
+            const uint64_t x = bf.src[start + j];
+            const uint32_t k32 = cp < 64 ? uint32_t((x << cp) >> 32) : 0u;
+            s_key[0][j] = k32;
+            s_idx[0][j] = uint16_t(j);
+            a_and &= k32;
+            a_or |= k32;
+        }
+        atomicAnd(&s_and, a_and);
+        atomicOr(&s_or, a_or);
+        __syncthreads();
+        const uint32_t varying = s_and ^ s_or;
+        int cur = 0;
+        // Each wave owns a contiguous slice of Q elements (Q a multiple of 64), in order.
+        const uint32_t Q = ((cnt + 4 * 64 - 1) / (4 * 64)) * 64;
+        const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
+        const uint64_t lane_lt = (1ull << lane) - 1ull;
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t shift = 8 * d;
+            if (((varying >> shift) & 0xFFu) == 0) continue;
+            for (int t = tid; t < (kWG / 64) * 256; t += kWG) (&s_wc[0][0])[t] = 0;
+            __syncthreads();
+            for (uint32_t r = e0; r < e0 + Q; r += 64) {
+                const uint32_t e = r + lane;
+                const bool valid = e < e1;
+                const uint32_t dig = valid ? (s_key[cur][e] >> shift) & 0xFFu : 0u;
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool on = (dig >> bit) & 1u;
+                    const uint64_t bal = __ballot(on);
+                    peers &= on ? bal : ~bal;
+                }
+                const uint32_t below = __popcll(peers & lane_lt);
+                uint32_t old = 0;
+                if (valid) old = s_wc[wave][dig];
+                if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
+                if (valid) s_rank[e] = uint16_t(old + below);
+            }
+            __syncthreads();
+            {
+                const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
+                uint32_t all;
+                const uint32_t ds = block_excl_scan(c0 + c1 + c2 + c3, s_tmp, all);
+                s_wc[0][tid] = ds;
+                s_wc[1][tid] = ds + c0;
+                s_wc[2][tid] = ds + c0 + c1;
+                s_wc[3][tid] = ds + c0 + c1 + c2;
+            }
+            __syncthreads();
+            for (uint32_t e = e0 + lane; e < e1; e += 64) {
+                const uint32_t k32 = s_key[cur][e];
+                const uint32_t pos = s_wc[wave][(k32 >> shift) & 0xFFu] + s_rank[e];
+                s_key[cur ^ 1][pos] = k32;
+                s_idx[cur ^ 1][pos] = s_idx[cur][e];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        // Runs of equal 32-bit keys: order by the full record.
+        const Bufs rb{bf.src + start, bf.src_rid + start, nullptr, nullptr};
+        for (uint32_t j = tid; j < cnt; j += kWG) {
+            const uint32_t k32 = s_key[cur][j];
+            if (j > 0 && s_key[cur][j - 1] == k32) continue;
+            uint32_t r = 1;
+            while (j + r < cnt && s_key[cur][j + r] == k32 && r <= uint32_t(kRunCap)) ++r;
+            if (r > uint32_t(kRunCap)) {
+                s_fail = 1u;
+                continue;
+            }
+            for (uint32_t a = 1; a < r; ++a) {  // insertion sort of s_idx[cur][j..j+r)
+                const uint16_t v = s_idx[cur][j + a];
+                uint32_t c = a;
+                while (c > 0 && rec_less<WC>(rb, n, words, v, s_idx[cur][j + c - 1])) {
+                    s_idx[cur][j + c] = s_idx[cur][j + c - 1];
+                    --c;
+                }
+                s_idx[cur][j + c] = v;
+            }
+        }
+        __syncthreads();
+        if (!s_fail) {
+            for (uint32_t j = tid; j < cnt; j += kWG) {
+                const uint64_t src = start + s_idx[cur][j];
+                for (uint32_t k = 0; k < words; ++k)
+                    bf.dst[uint64_t(k) * n + start + j] = bf.src[uint64_t(k) * n + src];
+                bf.dst_rid[start + j] = bf.src_rid[src];
+            }
+            return;
+        }
+        fallback = true;
+    }
+    // Hand the bucket to the radix fallback: copy it through, record its range.
+    for (uint32_t j = tid; j < cnt; j += kWG) {
+        for (uint32_t k = 0; k < words; ++k)
+            bf.dst[uint64_t(k) * n + start + j] = bf.src[uint64_t(k) * n + start + j];
+        bf.dst_rid[start + j] = bf.src_rid[start + j];
+    }
+    if (tid == 0) {
+        const uint32_t slot = atomicAdd(&ovf[0], 1u);
+        ovf[1 + 2 * slot] = start;
+        ovf[2 + 2 * slot] = cnt;
+    }
+}
+
+struct LLayout {
+    size_t alt_keys, alt_rid, bid, hist, starts, cursor, ovf, stats, total;
+};
+
+LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
+    LLayout l{};
+    size_t off = 0;
+    l.alt_keys = off; off += align256(size_t(words) * n * 8);
+    l.alt_rid = off;  off += align256(size_t(n) * 4);
+    l.bid = off;      off += align256(size_t(n) * 2);
+    l.hist = off;     off += align256(size_t(B) * 4);
+    l.starts = off;   off += align256(size_t(B + 1) * 4);
+    l.cursor = off;   off += align256(size_t(B) * 4);
+    l.ovf = off;      off += align256(size_t(2 * B + 1) * 4);
+    l.stats = off;    off += align256(2 * 8);
+    l.total = off;
+    return l;
+}
+
+uint32_t splitter_stride(uint32_t B) { return B / 16 > 2048 ? B / 2048 : 16; }
+
+size_t assign_lds(uint32_t B, int mode) {
+    return size_t(B / 2) * 4 + (mode == 0 ? size_t(B / splitter_stride(B)) * 8 : 0);
+}
+
+ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const void *model, uint32_t B,
+                          uint16_t *bid, uint32_t *bid32, uint32_t *pred, uint32_t *hist,
+                          unsigned long long *stats, hipStream_t st) {
+    if (n == 0) return CKEY_OK;
+    const uint32_t S = splitter_stride(B);
+    const size_t lds = assign_lds(B, mode) + 16;
+    const uint64_t blocks = (n + kKeysPerAssignWG - 1) / kKeysPerAssignWG;
+    const float *p = params_of(model);
+    const uint64_t *T = thresholds_of(model);
+    static bool attr_set = false;
+    if (!attr_set) {  // dynamic LDS above 64 KB (B = 2^16)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_assign<0>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_assign<1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    const int pr = prof_begin(st, mode ? "assign_learned" : "assign_splitter");
+    if (mode)
+        hipLaunchKernelGGL(k_bucket_assign<1>, dim3(uint32_t(blocks)), dim3(kAssignWG), lds, st, w0, n,
+                           p, T, B, S, bid, bid32, pred, hist, stats);
+    else
+        hipLaunchKernelGGL(k_bucket_assign<0>, dim3(uint32_t(blocks)), dim3(kAssignWG), lds, st, w0, n,
+                           p, T, B, S, bid, bid32, pred, hist, stats);
+    prof_end(st, pr);
+    return launch_status();
+}
+
+}  // namespace
+
+bool learned_b_ok(uint32_t b_log2) { return b_log2 >= 8 && b_log2 <= 16; }
+
+size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2) {
+    const size_t a = llayout(words, n, 1u << b_log2).total;
+    const size_t r = radix_workspace(words, nbits, n, 8, 32);
+    return a > r ? a : r;
+}
+
+ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
+                         int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
+                         hipStream_t st) {
+    if (n < 2) return CKEY_OK;
+    const uint32_t B = 1u << b_log2;
+    const LLayout l = llayout(words, n, B);
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
+    uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
+    uint16_t *bid = reinterpret_cast<uint16_t *>(w8 + l.bid);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w8 + l.hist);
+    uint32_t *starts = reinterpret_cast<uint32_t *>(w8 + l.starts);
+    uint32_t *cursor = reinterpret_cast<uint32_t *>(w8 + l.cursor);
+    uint32_t *ovf = reinterpret_cast<uint32_t *>(w8 + l.ovf);
+
+    CKEY_TRY(fill_u32(hist, B, 0, st));
+    CKEY_TRY(fill_u32(ovf, 1, 0, st));
+    CKEY_TRY(assign_launch(mode, ck, n, model, B, bid, nullptr, nullptr, hist, nullptr, st));
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, hist, B, starts, cursor);
+    CKEY_TRY(launch_status());
+    const uint32_t blocks = uint32_t((n + kWG - 1) / kWG);
+    const Bufs to_alt{ck, rid, alt, alt_rid};
+    const Bufs to_out{alt, alt_rid, ck, rid};
+    const uint64_t *T = thresholds_of(model);
+    {
+        const int pr = prof_begin(st, "bucket_scatter");
+        auto ks = words == 1 ? k_bucket_scatter<1> : words == 2 ? k_bucket_scatter<2>
+                : words == 3 ? k_bucket_scatter<3> : k_bucket_scatter<0>;
+        hipLaunchKernelGGL(ks, dim3(blocks), dim3(kWG), 0, st, to_alt, n, words, bid, cursor);
+        prof_end(st, pr);
+    }
+    CKEY_TRY(launch_status());
+    {
+        const int pr = prof_begin(st, "bucket_sort");
+        auto kb = words == 1 ? k_bucket_sort<1> : words == 2 ? k_bucket_sort<2>
+                : words == 3 ? k_bucket_sort<3> : k_bucket_sort<0>;
+        hipLaunchKernelGGL(kb, dim3(B), dim3(kWG), 0, st, to_out, n, words, starts, T, B, ovf);
+        prof_end(st, pr);
+    }
+    CKEY_TRY(launch_status());
+    // Overflowing buckets: read their ranges back and finish them with the radix sort.
+    uint32_t novf = 0;
+    CKEY_HIP_TRY(hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st));
+    CKEY_HIP_TRY(hipStreamSynchronize(st));
+    if (novf == 0) return CKEY_OK;
+    std::vector<uint32_t> ranges(2 * size_t(novf));
+    CKEY_HIP_TRY(hipMemcpyAsync(ranges.data(), ovf + 1, ranges.size() * 4, hipMemcpyDeviceToHost, st));
+    CKEY_HIP_TRY(hipStreamSynchronize(st));
+    for (uint32_t q = 0; q < novf; ++q) {
+        const uint32_t s0 = ranges[2 * q], c = ranges[2 * q + 1];
+        CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
+    }
+    if (flags) CKEY_TRY(fill_flag_or(flags, CKEY_FLAG_BUCKET_OVERFLOW, st));
+    return CKEY_OK;
+}
+
+// ------------------------------------------------------------- model API --
+
+size_t model_bytes(uint32_t b_log2) { return kOffT + (size_t(1) << b_log2) * 8; }
+
+ckey_status model_init(void *model, uint64_t seed, hipStream_t st) {
+    uint8_t *m8 = static_cast<uint8_t *>(model);
+    hipLaunchKernelGGL(k_model_init, dim3(1), dim3(512), 0, st, reinterpret_cast<float *>(m8 + kOffParams),
+                       reinterpret_cast<float *>(m8 + kOffM), reinterpret_cast<float *>(m8 + kOffV), seed);
+    return launch_status();
+}
+
+ckey_status model_thresholds(void *model, uint32_t b_log2, const uint64_t *sorted, uint64_t m,
+                             hipStream_t st) {
+    const uint32_t B = 1u << b_log2;
+    uint64_t *T = reinterpret_cast<uint64_t *>(static_cast<uint8_t *>(model) + kOffT);
+    hipLaunchKernelGGL(k_thresholds, dim3((B + 255) / 256), dim3(256), 0, st, sorted, m, T, B);
+    return launch_status();
+}
+
+uint32_t grad_blocks(uint32_t M) {
+    uint32_t g = (M + kWG - 1) / kWG;
+    return g > 1024 ? 1024 : (g == 0 ? 1 : g);
+}
+
+size_t grad_workspace(uint32_t M) { return align256(size_t(grad_blocks(M)) * kNPad * 4); }
+
+ckey_status model_grad(const void *model, const uint64_t *prefix, const float *target, uint64_t m,
+                       uint32_t M, uint64_t seed, uint32_t step, float *grad, float *loss, void *ws,
+                       hipStream_t st) {
+    const uint32_t G = grad_blocks(M);
+    float *partial = static_cast<float *>(ws);
+    const int pr = prof_begin(st, "mlp_grad");
+    hipLaunchKernelGGL(k_mlp_grad, dim3(G), dim3(kWG), 0, st, params_of(model), prefix, target, m, M,
+                       seed, step, partial);
+    prof_end(st, pr);
+    CKEY_TRY(launch_status());
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(512), 0, st, partial, G, grad, loss, nullptr,
+                       nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0u);
+    return launch_status();
+}
+
+ckey_status model_train(void *model, const uint64_t *prefix, uint64_t m, uint32_t steps, uint32_t M,
+                        float lr, float b1, float b2, float eps, uint64_t seed, float *loss_trace,
+                        void *ws, hipStream_t st) {
+    const uint32_t G = grad_blocks(M);
+    float *partial = static_cast<float *>(ws);
+    uint8_t *m8 = static_cast<uint8_t *>(model);
+    float *p = reinterpret_cast<float *>(m8 + kOffParams);
+    float *mm = reinterpret_cast<float *>(m8 + kOffM);
+    float *vv = reinterpret_cast<float *>(m8 + kOffV);
+    for (uint32_t s = 1; s <= steps; ++s) {
+        const int pr = prof_begin(st, "mlp_grad");
+        hipLaunchKernelGGL(k_mlp_grad, dim3(G), dim3(kWG), 0, st, p, prefix, nullptr, m, M, seed, s,
+                           partial);
+        prof_end(st, pr);
+        CKEY_TRY(launch_status());
+        hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(512), 0, st, partial, G, nullptr,
+                           loss_trace ? loss_trace + (s - 1) : nullptr, p, mm, vv, lr, b1, b2, eps, s);
+        CKEY_TRY(launch_status());
+    }
+    return CKEY_OK;
+}
+
+ckey_status model_bucket(const void *model, uint32_t b_log2, int mode, const uint64_t *prefix,
+                         uint64_t n, uint32_t *bucket, uint32_t *pred, unsigned long long *stats,
+                         hipStream_t st) {
+    return assign_launch(mode, prefix, n, model, 1u << b_log2, nullptr, bucket, pred, nullptr, stats, st);
+}
+
+}  // namespace ckey

@@ -35,8 +35,19 @@ constexpr uint32_t kFlagInc = 2u << 30;   // inclusive prefix published
 constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
+constexpr uint32_t kRidWord = 0xFFFFu;  // Pass::word for a digit of the row id
+
 struct Pass {
-    uint32_t word, shift, bits;
+    uint32_t word, shift, bits;  // digit = (word[i] >> shift) & (2^bits - 1)
+};
+
+// Buffers of one pass: word k of row i at base + k*ld + i.
+struct Bufs {
+    const uint64_t *src;
+    const uint32_t *src_rid;
+    uint64_t *dst;
+    uint32_t *dst_rid;
+    uint64_t src_ld, dst_ld;
 };
 
 struct HistArgs {
@@ -46,8 +57,9 @@ struct HistArgs {
     uint32_t out[8];  // pass index of each digit
 };
 
-__global__ __launch_bounds__(kWG) void k_hist(const uint64_t *__restrict__ word, uint64_t n,
-                                              HistArgs ha, uint32_t *__restrict__ hist) {
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_hist(const T *__restrict__ word, uint64_t n, HistArgs ha,
+                                              uint32_t *__restrict__ hist) {
     __shared__ uint32_t s_h[8][kRadixMax];
     for (int t = threadIdx.x; t < 8 * kRadixMax; t += kWG) (&s_h[0][0])[t] = 0;
     __syncthreads();
@@ -76,10 +88,10 @@ __global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist) {
     h[threadIdx.x] = e;
 }
 
+// WC: the word count when it is small enough to unroll (1..4), else 0 (runtime `words`).
+template <int WC>
 __global__ __launch_bounds__(kWG) void k_onesweep(
-    const uint64_t *__restrict__ src, const uint32_t *__restrict__ src_rid,
-    uint64_t *__restrict__ dst, uint32_t *__restrict__ dst_rid, uint64_t n, uint32_t words,
-    Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback, uint32_t *tile_counter,
+    Bufs bf, uint64_t n, uint32_t words_rt, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback, uint32_t *tile_counter,
     uint32_t *flags) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_wc[kWaves][kRadixMax];  // per-wave bucket counts, then offsets
@@ -88,6 +100,12 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     __shared__ uint32_t s_tmp[4];
     __shared__ uint64_t s_buf[kTile];
 
+    const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
+    const uint64_t *__restrict__ src = bf.src;
+    const uint32_t *__restrict__ src_rid = bf.src_rid;
+    uint64_t *__restrict__ dst = bf.dst;
+    uint32_t *__restrict__ dst_rid = bf.dst_rid;
+    const bool rid_pass = ps.word == kRidWord;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int t = tid; t < kWaves * kRadixMax; t += kWG) (&s_wc[0][0])[t] = 0;
@@ -96,7 +114,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     const uint64_t base = uint64_t(tile) * kTile;
     const uint32_t cnt = uint32_t(min<uint64_t>(kTile, n - base));
     const uint32_t dmask = (1u << ps.bits) - 1u;
-    const uint64_t *dsrc = src + uint64_t(ps.word) * n + base;
+    const uint64_t *dsrc = src + uint64_t(rid_pass ? 0 : ps.word) * bf.src_ld + base;
     const uint64_t lane_lt = (1ull << lane) - 1ull;
 
     uint64_t xv[kKPT];
@@ -105,7 +123,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 #pragma unroll
     for (int m = 0; m < kKPT; ++m) {
         const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
-        xv[m] = li < cnt ? dsrc[li] : 0ull;
+        xv[m] = li < cnt ? (rid_pass ? uint64_t(src_rid[base + li]) : dsrc[li]) : 0ull;
         dig[m] = uint32_t(xv[m] >> ps.shift) & dmask;
     }
 
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
         if (li < cnt) s_buf[lpos[m]] = xv[m];
     }
     __syncthreads();
-    uint64_t *ddst = dst + uint64_t(ps.word) * n;
+    uint64_t *ddst = dst + uint64_t(rid_pass ? 0 : ps.word) * bf.dst_ld;
 #pragma unroll
     for (int m = 0; m < kKPT; ++m) {
         const uint32_t j = m * kWG + tid;
@@ -189,12 +207,15 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
             const uint64_t v = s_buf[j];
             gdst[m] = s_gbase[uint32_t(v >> ps.shift) & dmask] + j;
             // every index is < n unless a look-back gave up (CKEY_FLAG_SPIN_LIMIT)
-            if (gdst[m] < n) ddst[gdst[m]] = v;
+            if (gdst[m] < n) {
+                if (rid_pass) dst_rid[gdst[m]] = uint32_t(v);
+                else ddst[gdst[m]] = v;
+            }
         }
     }
     for (uint32_t k = 0; k < words; ++k) {
         if (k == ps.word) continue;
-        const uint64_t *ksrc = src + uint64_t(k) * n + base;
+        const uint64_t *ksrc = src + uint64_t(k) * bf.src_ld + base;
         uint64_t vv[kKPT];
 #pragma unroll
         for (int m = 0; m < kKPT; ++m) {
@@ -208,14 +229,14 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
             if (li < cnt) s_buf[lpos[m]] = vv[m];
         }
         __syncthreads();
-        uint64_t *kdst = dst + uint64_t(k) * n;
+        uint64_t *kdst = dst + uint64_t(k) * bf.dst_ld;
 #pragma unroll
         for (int m = 0; m < kKPT; ++m) {
             const uint32_t j = m * kWG + tid;
             if (j < cnt && gdst[m] < n) kdst[gdst[m]] = s_buf[j];
         }
     }
-    {
+    if (!rid_pass) {
         uint32_t rv[kKPT];
 #pragma unroll
         for (int m = 0; m < kKPT; ++m) {
@@ -238,18 +259,23 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     }
 }
 
-__global__ void k_copy_back(const uint64_t *__restrict__ src, const uint32_t *__restrict__ src_rid,
-                            uint64_t *__restrict__ dst, uint32_t *__restrict__ dst_rid, uint64_t n,
-                            uint32_t words) {
+__global__ void k_copy_back(Bufs bf, uint64_t n, uint32_t words) {
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
-        for (uint32_t k = 0; k < words; ++k) dst[uint64_t(k) * n + i] = src[uint64_t(k) * n + i];
-        dst_rid[i] = src_rid[i];
+        for (uint32_t k = 0; k < words; ++k)
+            bf.dst[uint64_t(k) * bf.dst_ld + i] = bf.src[uint64_t(k) * bf.src_ld + i];
+        bf.dst_rid[i] = bf.src_rid[i];
     }
 }
 
-void make_passes(uint32_t words, uint32_t nbits, uint32_t d, std::vector<Pass> &ps) {
+void make_passes(uint32_t words, uint32_t nbits, uint32_t d, uint32_t rid_bits,
+                 std::vector<Pass> &ps) {
     ps.clear();
+    for (uint32_t s = 0; s < rid_bits;) {  // row-id digits are the least significant
+        const uint32_t b = std::min<uint32_t>(d, rid_bits - s);
+        ps.push_back({kRidWord, s, b});
+        s += b;
+    }
     for (int k = int(words) - 1; k >= 0; --k) {
         const int64_t have = int64_t(nbits) - 64 * int64_t(k);
         if (have <= 0) continue;
@@ -269,9 +295,9 @@ struct Layout {
     uint32_t npass;
 };
 
-Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d) {
+Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
     std::vector<Pass> ps;
-    make_passes(words, nbits, d, ps);
+    make_passes(words, nbits, d, rid_bits, ps);
     Layout l{};
     l.npass = uint32_t(ps.size());
     l.tiles = (n + kTile - 1) / kTile;
@@ -287,16 +313,17 @@ Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d) {
 
 }  // namespace
 
-size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d) {
-    return layout(words, nbits, n, d).total;
+size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
+    return layout(words, nbits, n, d, rid_bits).total;
 }
 
-ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
-                       uint32_t d, uint32_t *flags, void *ws, hipStream_t st) {
-    if (n < 2 || nbits == 0) return CKEY_OK;
+ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits, uint32_t *rid,
+                       uint64_t n, uint32_t d, uint32_t rid_bits, uint32_t *flags, void *ws,
+                       hipStream_t st) {
+    if (n < 2 || (nbits == 0 && rid_bits == 0)) return CKEY_OK;
     std::vector<Pass> ps;
-    make_passes(words, nbits, d, ps);
-    const Layout l = layout(words, nbits, n, d);
+    make_passes(words, nbits, d, rid_bits, ps);
+    const Layout l = layout(words, nbits, n, d, rid_bits);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
     uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
@@ -306,7 +333,7 @@ ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *r
 
     CKEY_TRY(fill_u32(hist, size_t(l.npass) * kRadixMax, 0, st));
     CKEY_TRY(fill_u32(counters, l.npass, 0, st));
-    // Upfront histograms, grouped by word, at most 8 digits per launch.
+    // Upfront histograms, grouped by source array, at most 8 digits per launch.
     uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
     if (hblocks > 2048) hblocks = 2048;
     for (size_t p0 = 0; p0 < ps.size();) {
@@ -322,8 +349,12 @@ ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *r
         }
         {
             const int pr_ = prof_begin(st, "hist");
-            hipLaunchKernelGGL(k_hist, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, ck + uint64_t(wk) * n,
-                               n, ha, hist);
+            if (wk == kRidWord)
+                hipLaunchKernelGGL(k_hist<uint32_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, rid,
+                                   n, ha, hist);
+            else
+                hipLaunchKernelGGL(k_hist<uint64_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st,
+                                   ck + uint64_t(wk) * ld, n, ha, hist);
             prof_end(st, pr_);
         }
         CKEY_TRY(launch_status());
@@ -332,32 +363,27 @@ ckey_status radix_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *r
     hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist);
     CKEY_TRY(launch_status());
 
-    const uint64_t *s = ck;
-    const uint32_t *sr = rid;
-    uint64_t *dk = alt;
-    uint32_t *dr = alt_rid;
+    // Ping-pong between the caller's arrays (leading dimension ld) and the
+    // workspace copy (leading dimension n).
+    Bufs cur{ck, rid, alt, alt_rid, ld, n};
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
             const int pr_ = prof_begin(st, "onesweep");
-            hipLaunchKernelGGL(k_onesweep, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, s, sr, dk, dr, n,
-                               words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+            auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
+                      : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
+            hipLaunchKernelGGL(kern, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, cur, n, words,
+                               ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
             prof_end(st, pr_);
         }
         CKEY_TRY(launch_status());
-        // swap
-        const uint64_t *ns = dk;
-        const uint32_t *nsr = dr;
-        dk = const_cast<uint64_t *>(s);
-        dr = const_cast<uint32_t *>(sr);
-        s = ns;
-        sr = nsr;
+        cur = Bufs{cur.dst, cur.dst_rid, const_cast<uint64_t *>(cur.src),
+                   const_cast<uint32_t *>(cur.src_rid), cur.dst_ld, cur.src_ld};
     }
-    if (s != ck) {
+    if (cur.src != ck) {
         uint64_t blocks = (n + kWG - 1) / kWG;
         if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_copy_back, dim3(uint32_t(blocks)), dim3(kWG), 0, st, s, sr, ck, rid, n,
-                           words);
+        hipLaunchKernelGGL(k_copy_back, dim3(uint32_t(blocks)), dim3(kWG), 0, st, cur, n, words);
         CKEY_TRY(launch_status());
     }
     return CKEY_OK;

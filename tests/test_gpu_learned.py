@@ -1,0 +1,195 @@
+"""GPU tests of the learned bucketing sort (an extension of the paper's
+compressed key sort): network gradients and an Adam step against the fp64
+oracle, exact bucket assignment against the oracle's threshold definition, and
+the final permutation against the oracle's full-key sort."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_11543_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+MASK64 = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def ck():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_11543_amd import ckey
+    return ckey
+
+
+def dna_prefixes(n, seed):
+    """First compressed words of DNA-window keys, sorted (oracle-computed)."""
+    rows = datagen.dna_window_keys(n, seed=seed, seq_len=4 * n)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    cko = O.compress(k, d)
+    return rows, k, perm, d, cko
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def splitmix_index(seed, step, j, m):
+    """The sampling rule documented for ckey_cdf_fit, in Python integers."""
+    z = (seed + 0x9E3779B97F4A7C15 * ((step << 32) + j + 1)) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    z ^= z >> 31
+    return z % m
+
+
+def test_grad_matches_oracle(ck):
+    import torch
+    model = ck.CdfModel(bucket_log2=10, seed=7)
+    rng = np.random.default_rng(1)
+    x = rng.integers(0, 2 ** 63, 3000, dtype=np.uint64) * np.uint64(2)
+    t = rng.random(3000).astype(np.float32)
+    grad, loss = ck.ckey_cdf_grad(model, to_dev(x), torch.from_numpy(t).cuda())
+    p = model.params().double().cpu().numpy()
+    loss_ref, g_ref = O.mlp_loss_grad(p, O.mlp_features(x), t.astype(np.float64))
+    g = grad.double().cpu().numpy()
+    scale = np.abs(g_ref).max()
+    np.testing.assert_allclose(g, g_ref, rtol=1e-3, atol=1e-4 * scale)
+    assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-4)
+
+
+def test_adam_step_matches_oracle(ck):
+    """One training step: sampled batch (documented SplitMix64 rule), gradient,
+    Adam update -- all compared with the fp64 oracle."""
+    import torch
+    _, _, perm, _, cko = dna_prefixes(1 << 12, 3)
+    srt = np.ascontiguousarray(cko[0, perm])
+    m = len(srt)
+    model = ck.CdfModel(bucket_log2=8, seed=5)
+    p0 = model.params().double().cpu().numpy().copy()
+    batch, seed, lr = 2048, 11, 1e-2
+    ck.ckey_cdf_fit(model, to_dev(srt), steps=1, batch=batch, lr=lr, seed=seed)
+    p1 = model.params().double().cpu().numpy()
+    idx = np.array([splitmix_index(seed, 1, j, m) for j in range(batch)])
+    X = O.mlp_features(srt[idx])
+    tgt = (idx.astype(np.float64) + 0.5) / m
+    _, g = O.mlp_loss_grad(p0, X, tgt)
+    pr, mm, vv = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    O.adam(pr, g, mm, vv, 1, lr)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    np.testing.assert_allclose((p1 - p0)[big], (pr - p0)[big], rtol=1e-3, atol=1e-6)
+    # thresholds: T[b] = sorted[b*m/B], T[0] = 0
+    T = model.thresholds().cpu().numpy().view(np.uint64)
+    B = 1 << 8
+    ref = srt[(np.arange(B) * m) // B]
+    ref[0] = 0
+    np.testing.assert_array_equal(T, ref)
+
+
+@pytest.mark.parametrize("method", ["learned", "splitter"])
+def test_bucket_exact(ck, method):
+    import torch
+    _, _, perm, _, cko = dna_prefixes(1 << 14, 4)
+    srt = np.ascontiguousarray(cko[0, perm])
+    model = ck.CdfModel(bucket_log2=12, seed=1)
+    ck.ckey_cdf_fit(model, to_dev(srt), steps=50, batch=4096)
+    T = model.thresholds().cpu().numpy().view(np.uint64)
+    rng = np.random.default_rng(2)
+    q = np.concatenate([cko[0], T, T - np.uint64(1), np.array([0, MASK64], np.uint64),
+                        rng.integers(0, 2 ** 63, 5000, dtype=np.uint64) * np.uint64(2)])
+    meth = ck.CKEY_SORT_LEARNED if method == "learned" else ck.CKEY_SORT_SPLITTER
+    b, pred, stats = ck.ckey_cdf_bucket(model, to_dev(q), meth)
+    np.testing.assert_array_equal(b.cpu().numpy().view(np.uint32), O.bucket(q, T))
+    assert int(stats[0].item()) > 0
+
+
+def trained_model(ck, d, bucket_log2, n_train, steps=400, seed=2):
+    """Model fitted to a training rebuild of a different seed, compressed with d."""
+    import torch
+    rows_t = datagen.dna_window_keys(n_train, seed=seed, seq_len=4 * n_train)
+    dk = ck.DeviceKeys.from_numpy(rows_t)
+    ckt, ridt = ck.ckey_compress(dk, d)
+    plan = ck.ckey_plan_query(d)
+    ck.ckey_sort(ckt, plan["nbits"], ridt)
+    model = ck.CdfModel(bucket_log2=bucket_log2, seed=3)
+    trace = ck.ckey_cdf_fit(model, ckt[0].contiguous(), steps=steps, batch=8192)
+    torch.cuda.synchronize()
+    return model, trace.cpu().numpy()
+
+
+@pytest.mark.parametrize("method", ["learned", "splitter"])
+@pytest.mark.parametrize("n", [1 << 15, (1 << 17) + 123])
+def test_bucket_sort_parity(ck, method, n):
+    import torch
+    rows, k, perm, d, cko = dna_prefixes(n, 1)
+    plan = ck.ckey_plan_query(d)
+    model, _ = trained_model(ck, d, 8 if n < 1 << 16 else 10, 1 << 16)
+    dk = ck.DeviceKeys.from_numpy(rows)
+    ckd, rid = ck.ckey_compress(dk, d)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    meth = ck.CKEY_SORT_LEARNED if method == "learned" else ck.CKEY_SORT_SPLITTER
+    ck.ckey_sort(ckd, plan["nbits"], rid, method=meth, model=model, flags=flags)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(ck.as_u64(ckd), cko[:, perm])
+
+
+def test_bucket_overflow_falls_back(ck):
+    """Buckets beyond the in-LDS capacity and long runs of equal prefixes go to
+    the radix fallback; the permutation stays exact and the flag is raised."""
+    import torch
+    rng = np.random.default_rng(8)
+    n = 1 << 18
+    heavy = rng.integers(0, 256, (20, 16), dtype=np.uint8)
+    rows = heavy[rng.integers(0, 20, n)]             # 90%: copies of 20 keys
+    light = rng.random(n) < 0.1
+    rows[light] = rng.integers(0, 256, (int(light.sum()), 16), dtype=np.uint8)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    plan = ck.ckey_plan_query(d)
+    srt = np.ascontiguousarray(O.compress(k, d)[0, perm])
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    ck.ckey_cdf_fit(model, to_dev(srt), steps=20, batch=1024)
+    dk = ck.DeviceKeys.from_numpy(rows)
+    for meth in (ck.CKEY_SORT_LEARNED, ck.CKEY_SORT_SPLITTER):
+        ckd, rid = ck.ckey_compress(dk, d)
+        flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ck.ckey_sort(ckd, plan["nbits"], rid, method=meth, model=model, flags=flags)
+        np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+        assert int(flags.item()) & ck.CKEY_FLAG_BUCKET_OVERFLOW
+
+
+def test_rebuild_with_learned_sort(ck):
+    rows, k, perm, d, _ = dna_prefixes(1 << 15, 6)
+    model, _ = trained_model(ck, d, 8, 1 << 15)
+    dk = ck.DeviceKeys.from_numpy(rows)
+    out = ck.ckey_rebuild_index([{"keys": dk, "bitmap": d}], method=ck.CKEY_SORT_LEARNED, model=model)[0]
+    np.testing.assert_array_equal(out["perm"].cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(out["bitmap"].cpu().numpy(), d)
+
+
+def test_trained_network_gain(ck):
+    """What the trained network gains over the method without it: global
+    threshold probes per key with the trained net vs the untrained start
+    (uniform CDF) vs the splitter search (LDS sample, then T)."""
+    import torch
+    rows, k, perm, d, cko = dna_prefixes(1 << 16, 1)
+    model, trace = trained_model(ck, d, 10, 1 << 16, steps=600)
+    assert trace[-20:].mean() < 0.5 * trace[:5].mean()
+    q = to_dev(cko[0])
+    n = cko.shape[1]
+    _, _, st_tr = ck.ckey_cdf_bucket(model, q, ck.CKEY_SORT_LEARNED)
+    untrained = ck.CdfModel(bucket_log2=10, seed=3)
+    untrained.thresholds().copy_(model.thresholds())
+    _, _, st_un = ck.ckey_cdf_bucket(untrained, q, ck.CKEY_SORT_LEARNED)
+    _, _, st_sp = ck.ckey_cdf_bucket(model, q, ck.CKEY_SORT_SPLITTER)
+    probes_tr, err_tr = st_tr.cpu().numpy() / n
+    probes_un, err_un = st_un.cpu().numpy() / n
+    probes_sp = st_sp.cpu().numpy()[0] / n
+    print(f"probes/key: trained {probes_tr:.2f} (|err| {err_tr:.1f} buckets), untrained "
+          f"{probes_un:.2f} (|err| {err_un:.1f}), splitter {probes_sp:.2f} global + LDS levels")
+    assert err_tr < 0.5 * err_un
+    assert probes_tr < probes_un

@@ -334,3 +334,61 @@ def test_varlen_matches_padded():
     bf, _ = O.dbits(kf, pf)
     np.testing.assert_array_equal(bv, bf)
     np.testing.assert_array_equal(O.compress(kv, bv), O.compress(kf, bf))
+
+
+# ------------------------------------------------- CDF model (extension) --
+
+def test_mlp_gradient_finite_differences():
+    """fp64 analytic gradient vs central differences."""
+    rng = np.random.default_rng(3)
+    p = rng.normal(0, 0.5, O.MLP_P)
+    X = rng.random((200, 4))
+    t = rng.random(200)
+    loss, g = O.mlp_loss_grad(p, X, t)
+    h = 1e-6
+    for i in list(range(0, O.MLP_P, 7)) + [O.MLP_P - 1]:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.mlp_loss_grad(pp, X, t)[0] - O.mlp_loss_grad(pm, X, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), i
+    y = O.mlp_forward(p, X)
+    assert loss == pytest.approx(np.mean((y - t) ** 2), rel=1e-12)
+
+
+def test_mlp_forward_closed_form():
+    """One active unit: y = w2 * relu(W1 x + b1) + b2."""
+    p = np.zeros(O.MLP_P)
+    p[0:4] = [2.0, -1.0, 0.5, 0.25]
+    p[4 * O.MLP_H] = -0.5
+    p[5 * O.MLP_H] = 3.0
+    p[6 * O.MLP_H] = 0.125
+    X = np.array([[0.5, 0.25, 0.0, 1.0], [0.0, 0.5, 0.0, 0.0]])
+    lin = X @ np.array([2.0, -1.0, 0.5, 0.25]) - 0.5
+    np.testing.assert_allclose(O.mlp_forward(p, X), 3.0 * np.maximum(lin, 0) + 0.125)
+
+
+def test_adam_closed_form():
+    """First Adam step moves each parameter by lr * sign(g) (bias-corrected)."""
+    p = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m, v = np.zeros(3), np.zeros(3)
+    O.adam(p, g, m, v, 1, 0.01, eps=0.0)
+    np.testing.assert_allclose(p, [0.99, -1.99, 0.49])
+
+
+def test_bucket_definition():
+    rng = np.random.default_rng(4)
+    T = np.sort(rng.integers(0, 1 << 63, 1000, dtype=np.uint64))
+    T[0] = 0
+    T[10:20] = T[10]  # repeated thresholds give empty buckets
+    x = rng.integers(0, 1 << 63, 5000, dtype=np.uint64)
+    x[:50] = T[rng.integers(0, 1000, 50)]
+    import bisect
+    ref = [bisect.bisect_right(list(T), int(v)) - 1 for v in x]
+    np.testing.assert_array_equal(O.bucket(x, T), ref)
+
+
+def test_features():
+    x = np.array([0x0001_8000_FFFF_0000], np.uint64)
+    np.testing.assert_array_equal(O.mlp_features(x)[0], [1 / 65536, 0.5, 65535 / 65536, 0.0])
