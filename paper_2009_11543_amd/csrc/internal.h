@@ -111,6 +111,13 @@ ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nb
                        uint32_t *rowids, uint64_t n, uint32_t digit_bits, uint32_t rid_bits,
                        uint32_t *flags, void *ws, hipStream_t st);
 
+// Stable sort of rows [0, n) by a 16-bit aux key of aux_bits bits (two
+// one-sweep passes; the aux array is read, not reordered), moving the words
+// and row ids; the result is back in ck/rid.
+size_t aux_sort_workspace(uint32_t words, uint64_t n);
+ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
+                     uint32_t aux_bits, uint32_t *flags, void *ws, hipStream_t st);
+
 // OR a value into a device flags word (a kernel, so it is stream-ordered).
 ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st);
 
@@ -149,6 +156,26 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
         if (lane >= d) v += t;
     }
     return v;
+}
+
+// Exclusive scan over the NT threads of a workgroup; all threads must call.
+// s_tmp: NT/64 words of LDS.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t *s_tmp, uint32_t &total) {
+    const uint32_t incl = wave_incl_scan(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) s_tmp[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        const uint32_t t = s_tmp[w];
+        off += (w < wave) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
 }
 
 // Exclusive scan over the 256 threads of a workgroup; all threads must call.

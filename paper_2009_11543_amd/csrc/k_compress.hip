@@ -100,39 +100,53 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
         p = k.bytes + i * k.stride;
     }
     uint32_t lo = 0, hi = 0, kw = plan.word_begin;
-    for (uint32_t c = 0; c < plan.n_chunks; ++c) {
-        const uint32_t cb = plan.chunk[c];
-        uint32_t x[4] = {0, 0, 0, 0};
-        if (MODE == kLoad16) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
-            x[0] = __builtin_bswap32(v.x);
-            x[1] = __builtin_bswap32(v.y);
-            x[2] = __builtin_bswap32(v.z);
-            x[3] = __builtin_bswap32(v.w);
-        } else if (MODE == kLoad4) {
+    // Chunks are taken four at a time: all loads of a group are issued before
+    // any of its output stores, so they overlap.
+    for (uint32_t c0 = 0; c0 < plan.n_chunks; c0 += 4) {
+        uint32_t x[4][4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
-                    x[q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
-        } else {
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t c = c0 + g;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
-                    x[q] = key_word_bytes(p, 4 * cb + q, len);
+            for (int q = 0; q < 4; ++q) x[g][q] = 0;
+            if (c >= plan.n_chunks) continue;
+            const uint32_t cb = plan.chunk[c];
+            if (MODE == kLoad16) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
+                x[g][0] = __builtin_bswap32(v.x);
+                x[g][1] = __builtin_bswap32(v.y);
+                x[g][2] = __builtin_bswap32(v.z);
+                x[g][3] = __builtin_bswap32(v.w);
+            } else if (MODE == kLoad4) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
+                        x[g][q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
+                        x[g][q] = key_word_bytes(p, 4 * cb + q, len);
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t r1 = plan.run_begin[4 * c + q + 1];
-            for (uint32_t r = plan.run_begin[4 * c + q]; r < r1; ++r) {
-                const uint32_t R = plan.runs[r];
-                uint32_t f = (R & kRunWhole) ? x[q]
-                                             : __builtin_amdgcn_ubfe(x[q], R & 31u, (R >> kRunLenShift) & 63u);
-                f <<= (R >> kRunDstShift) & 31u;
-                if (R & kRunHi) hi |= f; else lo |= f;
-                if (R & kRunFlush) {
-                    ck[uint64_t(kw) * k.n + i] = (uint64_t(hi) << 32) | lo;
-                    ++kw;
-                    lo = hi = 0;
+        for (int g = 0; g < 4; ++g) {
+            const uint32_t c = c0 + g;
+            if (c >= plan.n_chunks) break;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t r1 = plan.run_begin[4 * c + q + 1];
+                for (uint32_t r = plan.run_begin[4 * c + q]; r < r1; ++r) {
+                    const uint32_t R = plan.runs[r];
+                    uint32_t f = (R & kRunWhole) ? x[g][q]
+                                                 : __builtin_amdgcn_ubfe(x[g][q], R & 31u, (R >> kRunLenShift) & 63u);
+                    f <<= (R >> kRunDstShift) & 31u;
+                    if (R & kRunHi) hi |= f; else lo |= f;
+                    if (R & kRunFlush) {
+                        ck[uint64_t(kw) * k.n + i] = (uint64_t(hi) << 32) | lo;
+                        ++kw;
+                        lo = hi = 0;
+                    }
                 }
             }
         }

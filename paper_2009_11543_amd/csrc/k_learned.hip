@@ -13,14 +13,15 @@
 // never depends on the network (the splitter method instead searches a
 // 1-in-S sample of T held in LDS, then T itself).
 //
-// Sort: assign buckets (+ histogram) -> scan -> scatter records to their
-// bucket ranges (one atomic cursor per bucket) -> one workgroup per bucket
-// sorts it in LDS by the 32 prefix bits below the bucket's common prefix
-// (stable 8-bit LSD passes with wave ballots, skipping constant digits), then
-// orders runs of equal 32-bit keys by the full record (words, then row id).
-// Buckets larger than the LDS capacity, or with a run of equal 32-bit keys
-// longer than kRunCap, are copied through unsorted and finished by the radix
-// sort (row-id digits first, so ties still end in row-id order).
+// Sort: assign buckets (+ histogram) -> scan -> group rows by bucket (a
+// stable sort on the bucket id: two one-sweep passes) -> one workgroup per
+// bucket sorts it in place in LDS by the bits of the first word below the
+// bucket's common prefix (stable 8-bit LSD passes with wave ballots, skipping
+// digits constant in the bucket), then orders runs of equal first words by the
+// remaining words and the row id.  Buckets larger than the LDS capacity, or
+// with a run of equal first words longer than kRunCap, are left in place and
+// finished by the radix sort (row-id digits first, so ties still end in row-id
+// order).
 #include <math.h>
 
 #include <vector>
@@ -37,7 +38,7 @@ constexpr int kNPad = 392;       // parameters + loss slot, padded
 constexpr int kLoss = kNP;       // index of the loss in a partial-sum row
 constexpr size_t kOffParams = 0, kOffM = 2048, kOffV = 4096, kOffT = 8192;
 constexpr int kCap = 5120;       // max bucket size sorted in LDS
-constexpr int kRunCap = 32;      // max run of equal 32-bit local keys
+constexpr int kRunCap = 32;      // max run of equal first words sorted in place
 constexpr int kAssignWG = 1024;
 constexpr uint32_t kKeysPerAssignWG = 65535;  // keeps the packed 16-bit LDS counters exact
 
@@ -346,186 +347,202 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict
     if (tid == 0) starts[B] = tot;
 }
 
-struct Bufs {
-    const uint64_t *src;
-    const uint32_t *src_rid;
-    uint64_t *dst;
-    uint32_t *dst_rid;
-};
+constexpr int kSortWG = 512;  // threads per bucket-sort workgroup (8 waves)
 
-template <int WC>
-__global__ __launch_bounds__(kWG) void k_bucket_scatter(Bufs bf, uint64_t n, uint32_t words_rt,
-                                                        const uint16_t *__restrict__ bid,
-                                                        uint32_t *__restrict__ cursor) {
-    const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
-    const uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t pos = atomicAdd(&cursor[bid[i]], 1u);
-    if (pos >= n) return;  // cannot happen when the histogram matches bid
-    for (uint32_t k = 0; k < words; ++k) bf.dst[uint64_t(k) * n + pos] = bf.src[uint64_t(k) * n + i];
-    bf.dst_rid[pos] = bf.src_rid[i];
-}
-
-// Full-record order of two rows of the bucket (words, then row id).
-template <int WC>
-__device__ __forceinline__ bool rec_less(const Bufs &bf, uint64_t n, uint32_t words, uint64_t a,
-                                         uint64_t b) {
+// Full-record order of two rows (words, then row id); rows index the bucket.
+__device__ __forceinline__ bool rec_less(const uint64_t *ck, const uint32_t *rid, uint64_t n,
+                                         uint32_t words, uint64_t a, uint64_t b) {
     for (uint32_t k = 0; k < words; ++k) {
-        const uint64_t x = bf.src[uint64_t(k) * n + a], y = bf.src[uint64_t(k) * n + b];
+        const uint64_t x = ck[uint64_t(k) * n + a], y = ck[uint64_t(k) * n + b];
         if (x != y) return x < y;
     }
-    return bf.src_rid[a] < bf.src_rid[b];
+    return rid[a] < rid[b];
 }
 
+// One workgroup per bucket, in place on rows [starts[b], starts[b+1]) of ck/rid
+// (the rows are already grouped by bucket).  Every first word x in bucket b
+// lies in [T[b], T[b+1]), so all share the common prefix (cp bits) of that
+// range; the LDS sort key is x << cp, whose equal values are equal first words.
 template <int WC>
-__global__ __launch_bounds__(kWG) void k_bucket_sort(Bufs bf, uint64_t n, uint32_t words_rt,
-                                                     const uint32_t *__restrict__ starts,
-                                                     const uint64_t *__restrict__ T, uint32_t B,
-                                                     uint32_t *__restrict__ ovf) {
-    __shared__ uint32_t s_key[2][kCap];
-    __shared__ uint16_t s_idx[2][kCap];
+__global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ ck,
+                                                         uint32_t *__restrict__ rid, uint64_t n,
+                                                         uint32_t words_rt,
+                                                         const uint32_t *__restrict__ starts,
+                                                         const uint64_t *__restrict__ T, uint32_t B,
+                                                         uint32_t *__restrict__ ovf) {
+    constexpr int NW = kSortWG / 64;
+    __shared__ uint32_t s_k[2][kCap];    // [0]: high, [1]: low half of the local key;
+                                         // afterwards the staging buffer of the permute
+    __shared__ uint16_t s_idx[2][kCap];  // element order, ping-pong
     __shared__ uint16_t s_rank[kCap];
-    __shared__ uint32_t s_wc[kWG / 64][256];
-    __shared__ uint32_t s_tmp[4];
-    __shared__ uint32_t s_and, s_or, s_fail;
+    __shared__ uint32_t s_wc[NW][256];
+    __shared__ uint32_t s_tmp[NW];
+    __shared__ uint32_t s_and[2], s_or[2], s_fail;
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t b = blockIdx.x;
     const uint32_t start = starts[b];
     const uint32_t cnt = starts[b + 1] - start;
-    if (cnt == 0) return;
-
-    bool fallback = cnt > uint32_t(kCap);
-    if (!fallback) {
-        const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
-        const uint32_t cp = lo == hi ? 64u : uint32_t(__clzll(lo ^ hi));
+    if (cnt < 2) return;
+    if (cnt > uint32_t(kCap)) {
         if (tid == 0) {
-            s_and = ~0u;
-            s_or = 0u;
-            s_fail = 0u;
+            const uint32_t slot = atomicAdd(&ovf[0], 1u);
+            ovf[1 + 2 * slot] = start;
+            ovf[2 + 2 * slot] = cnt;
         }
-        __syncthreads();
-        uint32_t a_and = ~0u, a_or = 0u;
-        for (uint32_t j = tid; j < cnt; j += kWG) {
-            const uint64_t x = bf.src[start + j];
-            const uint32_t k32 = cp < 64 ? uint32_t((x << cp) >> 32) : 0u;
-            s_key[0][j] = k32;
-            s_idx[0][j] = uint16_t(j);
-            a_and &= k32;
-            a_or |= k32;
-        }
-        atomicAnd(&s_and, a_and);
-        atomicOr(&s_or, a_or);
-        __syncthreads();
-        const uint32_t varying = s_and ^ s_or;
-        int cur = 0;
-        // Each wave owns a contiguous slice of Q elements (Q a multiple of 64), in order.
-        const uint32_t Q = ((cnt + 4 * 64 - 1) / (4 * 64)) * 64;
-        const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
-        const uint64_t lane_lt = (1ull << lane) - 1ull;
-        for (int d = 0; d < 4; ++d) {
-            const uint32_t shift = 8 * d;
-            if (((varying >> shift) & 0xFFu) == 0) continue;
-            for (int t = tid; t < (kWG / 64) * 256; t += kWG) (&s_wc[0][0])[t] = 0;
-            __syncthreads();
-            for (uint32_t r = e0; r < e0 + Q; r += 64) {
-                const uint32_t e = r + lane;
-                const bool valid = e < e1;
-                const uint32_t dig = valid ? (s_key[cur][e] >> shift) & 0xFFu : 0u;
-                uint64_t peers = __ballot(valid);
-#pragma unroll
-                for (int bit = 0; bit < 8; ++bit) {
-                    const bool on = (dig >> bit) & 1u;
-                    const uint64_t bal = __ballot(on);
-                    peers &= on ? bal : ~bal;
-                }
-                const uint32_t below = __popcll(peers & lane_lt);
-                uint32_t old = 0;
-                if (valid) old = s_wc[wave][dig];
-                if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
-                if (valid) s_rank[e] = uint16_t(old + below);
-            }
-            __syncthreads();
-            {
-                const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
-                uint32_t all;
-                const uint32_t ds = block_excl_scan(c0 + c1 + c2 + c3, s_tmp, all);
-                s_wc[0][tid] = ds;
-                s_wc[1][tid] = ds + c0;
-                s_wc[2][tid] = ds + c0 + c1;
-                s_wc[3][tid] = ds + c0 + c1 + c2;
-            }
-            __syncthreads();
-            for (uint32_t e = e0 + lane; e < e1; e += 64) {
-                const uint32_t k32 = s_key[cur][e];
-                const uint32_t pos = s_wc[wave][(k32 >> shift) & 0xFFu] + s_rank[e];
-                s_key[cur ^ 1][pos] = k32;
-                s_idx[cur ^ 1][pos] = s_idx[cur][e];
-            }
-            __syncthreads();
-            cur ^= 1;
-        }
-        // Runs of equal 32-bit keys: order by the full record.
-        const Bufs rb{bf.src + start, bf.src_rid + start, nullptr, nullptr};
-        for (uint32_t j = tid; j < cnt; j += kWG) {
-            const uint32_t k32 = s_key[cur][j];
-            if (j > 0 && s_key[cur][j - 1] == k32) continue;
-            uint32_t r = 1;
-            while (j + r < cnt && s_key[cur][j + r] == k32 && r <= uint32_t(kRunCap)) ++r;
-            if (r > uint32_t(kRunCap)) {
-                s_fail = 1u;
-                continue;
-            }
-            for (uint32_t a = 1; a < r; ++a) {  // insertion sort of s_idx[cur][j..j+r)
-                const uint16_t v = s_idx[cur][j + a];
-                uint32_t c = a;
-                while (c > 0 && rec_less<WC>(rb, n, words, v, s_idx[cur][j + c - 1])) {
-                    s_idx[cur][j + c] = s_idx[cur][j + c - 1];
-                    --c;
-                }
-                s_idx[cur][j + c] = v;
-            }
-        }
-        __syncthreads();
-        if (!s_fail) {
-            for (uint32_t j = tid; j < cnt; j += kWG) {
-                const uint64_t src = start + s_idx[cur][j];
-                for (uint32_t k = 0; k < words; ++k)
-                    bf.dst[uint64_t(k) * n + start + j] = bf.src[uint64_t(k) * n + src];
-                bf.dst_rid[start + j] = bf.src_rid[src];
-            }
-            return;
-        }
-        fallback = true;
+        return;
     }
-    // Hand the bucket to the radix fallback: copy it through, record its range.
-    for (uint32_t j = tid; j < cnt; j += kWG) {
-        for (uint32_t k = 0; k < words; ++k)
-            bf.dst[uint64_t(k) * n + start + j] = bf.src[uint64_t(k) * n + start + j];
-        bf.dst_rid[start + j] = bf.src_rid[start + j];
-    }
+    const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
+    const uint32_t cp = lo == hi ? 64u : uint32_t(__clzll(lo ^ hi));
     if (tid == 0) {
-        const uint32_t slot = atomicAdd(&ovf[0], 1u);
-        ovf[1 + 2 * slot] = start;
-        ovf[2 + 2 * slot] = cnt;
+        s_and[0] = s_and[1] = ~0u;
+        s_or[0] = s_or[1] = 0u;
+        s_fail = 0u;
     }
+    __syncthreads();
+    uint32_t a_and[2] = {~0u, ~0u}, a_or[2] = {0u, 0u};
+    for (uint32_t j = tid; j < cnt; j += kSortWG) {
+        const uint64_t x = ck[start + j];
+        const uint64_t l64 = cp < 64 ? x << cp : 0ull;
+        const uint32_t h32 = uint32_t(l64 >> 32), l32 = uint32_t(l64);
+        s_k[0][j] = h32;
+        s_k[1][j] = l32;
+        s_idx[0][j] = uint16_t(j);
+        a_and[0] &= h32;
+        a_or[0] |= h32;
+        a_and[1] &= l32;
+        a_or[1] |= l32;
+    }
+    atomicAnd(&s_and[0], a_and[0]);
+    atomicOr(&s_or[0], a_or[0]);
+    atomicAnd(&s_and[1], a_and[1]);
+    atomicOr(&s_or[1], a_or[1]);
+    __syncthreads();
+    const uint32_t vary[2] = {s_and[0] ^ s_or[0], s_and[1] ^ s_or[1]};
+    int cur = 0;
+    // Each wave ranks a contiguous slice of Q elements (Q a multiple of 64) in order.
+    const uint32_t Q = ((cnt + NW * 64 - 1) / (NW * 64)) * 64;
+    const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+    for (int d = 0; d < 8; ++d) {  // LSD: low half first
+        const int half = d < 4 ? 1 : 0;
+        const uint32_t shift = 8 * (d & 3);
+        if (((vary[half] >> shift) & 0xFFu) == 0) continue;  // digit constant in the bucket
+        const uint32_t *key = s_k[half];
+        for (int t = tid; t < NW * 256; t += kSortWG) (&s_wc[0][0])[t] = 0;
+        __syncthreads();
+        for (uint32_t r = e0; r < e0 + Q; r += 64) {
+            const uint32_t e = r + lane;
+            const bool valid = e < e1;
+            const uint32_t dig = valid ? (key[s_idx[cur][e]] >> shift) & 0xFFu : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool on = (dig >> bit) & 1u;
+                const uint64_t bal = __ballot(on);
+                peers &= on ? bal : ~bal;
+            }
+            const uint32_t below = __popcll(peers & lane_lt);
+            uint32_t old = 0;
+            if (valid) old = s_wc[wave][dig];
+            if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
+            if (valid) s_rank[e] = uint16_t(old + below);
+        }
+        __syncthreads();
+        {
+            uint32_t c[NW], tot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                c[w] = tid < 256 ? s_wc[w][tid] : 0u;
+                tot += c[w];
+            }
+            uint32_t all;
+            uint32_t ds = block_excl_scan_n<kSortWG>(tot, s_tmp, all);
+            if (tid < 256) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    s_wc[w][tid] = ds;
+                    ds += c[w];
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = e0 + lane; e < e1; e += 64) {
+            const uint16_t id = s_idx[cur][e];
+            const uint32_t pos = s_wc[wave][(key[id] >> shift) & 0xFFu] + s_rank[e];
+            s_idx[cur ^ 1][pos] = id;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // Runs of equal first words: order by the remaining words, then the row id.
+    const uint64_t *bck = ck + start;
+    const uint32_t *brid = rid + start;
+    uint16_t *ord = s_idx[cur];
+    for (uint32_t j = tid; j < cnt; j += kSortWG) {
+        const uint16_t i0 = ord[j];
+        if (j > 0) {
+            const uint16_t ip = ord[j - 1];
+            if (s_k[0][ip] == s_k[0][i0] && s_k[1][ip] == s_k[1][i0]) continue;
+        }
+        uint32_t r = 1;
+        while (j + r < cnt && r <= uint32_t(kRunCap) && s_k[0][ord[j + r]] == s_k[0][i0] &&
+               s_k[1][ord[j + r]] == s_k[1][i0])
+            ++r;
+        if (r > uint32_t(kRunCap)) {
+            s_fail = 1u;
+            continue;
+        }
+        for (uint32_t a = 1; a < r; ++a) {  // insertion sort of ord[j..j+r)
+            const uint16_t v = ord[j + a];
+            uint32_t c = a;
+            while (c > 0 && rec_less(bck, brid, n, words, v, ord[j + c - 1])) {
+                ord[j + c] = ord[j + c - 1];
+                --c;
+            }
+            ord[j + c] = v;
+        }
+    }
+    __syncthreads();
+    if (s_fail) {  // leave the bucket as it is for the radix fallback
+        if (tid == 0) {
+            const uint32_t slot = atomicAdd(&ovf[0], 1u);
+            ovf[1 + 2 * slot] = start;
+            ovf[2 + 2 * slot] = cnt;
+        }
+        return;
+    }
+    // Permute in place: stage each array's bucket slice in LDS (coalesced load),
+    // then write it back in sorted order (coalesced store).
+    uint64_t *stage = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
+    for (uint32_t k = 0; k < words; ++k) {
+        uint64_t *wk = ck + uint64_t(k) * n + start;
+        for (uint32_t j = tid; j < cnt; j += kSortWG) stage[j] = wk[j];
+        __syncthreads();
+        for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stage[ord[j]];
+        __syncthreads();
+    }
+    uint32_t *stage32 = &s_k[0][0];
+    uint32_t *rk = rid + start;
+    for (uint32_t j = tid; j < cnt; j += kSortWG) stage32[j] = rk[j];
+    __syncthreads();
+    for (uint32_t j = tid; j < cnt; j += kSortWG) rk[j] = stage32[ord[j]];
 }
 
 struct LLayout {
-    size_t alt_keys, alt_rid, bid, hist, starts, cursor, ovf, stats, total;
+    size_t bid, hist, starts, cursor, ovf, stats, sortws, total;
 };
 
 LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
     LLayout l{};
     size_t off = 0;
-    l.alt_keys = off; off += align256(size_t(words) * n * 8);
-    l.alt_rid = off;  off += align256(size_t(n) * 4);
     l.bid = off;      off += align256(size_t(n) * 2);
     l.hist = off;     off += align256(size_t(B) * 4);
     l.starts = off;   off += align256(size_t(B + 1) * 4);
     l.cursor = off;   off += align256(size_t(B) * 4);
     l.ovf = off;      off += align256(size_t(2 * B + 1) * 4);
     l.stats = off;    off += align256(2 * 8);
+    l.sortws = off;   off += aux_sort_workspace(words, n);
     l.total = off;
     return l;
 }
@@ -581,8 +598,6 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     const uint32_t B = 1u << b_log2;
     const LLayout l = llayout(words, n, B);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
-    uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
-    uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
     uint16_t *bid = reinterpret_cast<uint16_t *>(w8 + l.bid);
     uint32_t *hist = reinterpret_cast<uint32_t *>(w8 + l.hist);
     uint32_t *starts = reinterpret_cast<uint32_t *>(w8 + l.starts);
@@ -594,23 +609,14 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     CKEY_TRY(assign_launch(mode, ck, n, model, B, bid, nullptr, nullptr, hist, nullptr, st));
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, hist, B, starts, cursor);
     CKEY_TRY(launch_status());
-    const uint32_t blocks = uint32_t((n + kWG - 1) / kWG);
-    const Bufs to_alt{ck, rid, alt, alt_rid};
-    const Bufs to_out{alt, alt_rid, ck, rid};
+    // Group rows by bucket: a stable sort by the bucket id (two one-sweep passes).
+    CKEY_TRY(aux_sort(ck, rid, bid, n, words, b_log2, flags, w8 + l.sortws, st));
     const uint64_t *T = thresholds_of(model);
-    {
-        const int pr = prof_begin(st, "bucket_scatter");
-        auto ks = words == 1 ? k_bucket_scatter<1> : words == 2 ? k_bucket_scatter<2>
-                : words == 3 ? k_bucket_scatter<3> : k_bucket_scatter<0>;
-        hipLaunchKernelGGL(ks, dim3(blocks), dim3(kWG), 0, st, to_alt, n, words, bid, cursor);
-        prof_end(st, pr);
-    }
-    CKEY_TRY(launch_status());
     {
         const int pr = prof_begin(st, "bucket_sort");
         auto kb = words == 1 ? k_bucket_sort<1> : words == 2 ? k_bucket_sort<2>
                 : words == 3 ? k_bucket_sort<3> : k_bucket_sort<0>;
-        hipLaunchKernelGGL(kb, dim3(B), dim3(kWG), 0, st, to_out, n, words, starts, T, B, ovf);
+        hipLaunchKernelGGL(kb, dim3(B), dim3(kSortWG), 0, st, ck, rid, n, words, starts, T, B, ovf);
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());

@@ -36,6 +36,7 @@ constexpr uint32_t kValMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
 constexpr uint32_t kRidWord = 0xFFFFu;  // Pass::word for a digit of the row id
+constexpr uint32_t kAuxWord = 0xFFFEu;  // Pass::word for a digit of the 16-bit aux key
 
 struct Pass {
     uint32_t word, shift, bits;  // digit = (word[i] >> shift) & (2^bits - 1)
@@ -48,6 +49,8 @@ struct Bufs {
     uint64_t *dst;
     uint32_t *dst_rid;
     uint64_t src_ld, dst_ld;
+    const uint16_t *src_aux;  // aux key: read by aux-digit passes,
+    uint16_t *dst_aux;        // and moved along when dst_aux != nullptr
 };
 
 struct HistArgs {
@@ -106,6 +109,8 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     uint64_t *__restrict__ dst = bf.dst;
     uint32_t *__restrict__ dst_rid = bf.dst_rid;
     const bool rid_pass = ps.word == kRidWord;
+    const bool aux_pass = ps.word == kAuxWord;
+    const bool word_pass = !rid_pass && !aux_pass;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int t = tid; t < kWaves * kRadixMax; t += kWG) (&s_wc[0][0])[t] = 0;
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     const uint64_t base = uint64_t(tile) * kTile;
     const uint32_t cnt = uint32_t(min<uint64_t>(kTile, n - base));
     const uint32_t dmask = (1u << ps.bits) - 1u;
-    const uint64_t *dsrc = src + uint64_t(rid_pass ? 0 : ps.word) * bf.src_ld + base;
+    const uint64_t *dsrc = src + uint64_t(word_pass ? ps.word : 0) * bf.src_ld + base;
     const uint64_t lane_lt = (1ull << lane) - 1ull;
 
     uint64_t xv[kKPT];
@@ -123,7 +128,9 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 #pragma unroll
     for (int m = 0; m < kKPT; ++m) {
         const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
-        xv[m] = li < cnt ? (rid_pass ? uint64_t(src_rid[base + li]) : dsrc[li]) : 0ull;
+        xv[m] = li < cnt ? (word_pass ? dsrc[li]
+                            : rid_pass ? uint64_t(src_rid[base + li]) : uint64_t(bf.src_aux[base + li]))
+                         : 0ull;
         dig[m] = uint32_t(xv[m] >> ps.shift) & dmask;
     }
 
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
         if (li < cnt) s_buf[lpos[m]] = xv[m];
     }
     __syncthreads();
-    uint64_t *ddst = dst + uint64_t(rid_pass ? 0 : ps.word) * bf.dst_ld;
+    uint64_t *ddst = dst + uint64_t(word_pass ? ps.word : 0) * bf.dst_ld;
 #pragma unroll
     for (int m = 0; m < kKPT; ++m) {
         const uint32_t j = m * kWG + tid;
@@ -208,13 +215,14 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
             gdst[m] = s_gbase[uint32_t(v >> ps.shift) & dmask] + j;
             // every index is < n unless a look-back gave up (CKEY_FLAG_SPIN_LIMIT)
             if (gdst[m] < n) {
-                if (rid_pass) dst_rid[gdst[m]] = uint32_t(v);
-                else ddst[gdst[m]] = v;
+                if (word_pass) ddst[gdst[m]] = v;
+                else if (rid_pass) dst_rid[gdst[m]] = uint32_t(v);
+                else if (bf.dst_aux) bf.dst_aux[gdst[m]] = uint16_t(v);
             }
         }
     }
     for (uint32_t k = 0; k < words; ++k) {
-        if (k == ps.word) continue;
+        if (word_pass && k == ps.word) continue;
         const uint64_t *ksrc = src + uint64_t(k) * bf.src_ld + base;
         uint64_t vv[kKPT];
 #pragma unroll
@@ -311,7 +319,85 @@ Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t r
     return l;
 }
 
+struct AuxLayout {
+    size_t alt_keys, alt_rid, alt_aux, hist, lookback, counters, total;
+    uint64_t tiles;
+};
+
+AuxLayout aux_layout(uint32_t words, uint64_t n) {
+    AuxLayout l{};
+    l.tiles = (n + kTile - 1) / kTile;
+    size_t off = 0;
+    l.alt_keys = off; off += align256(size_t(words) * n * 8);
+    l.alt_rid = off;  off += align256(size_t(n) * 4);
+    l.alt_aux = off;  off += align256(size_t(n) * 2);
+    l.hist = off;     off += align256(2 * kRadixMax * 4);
+    l.lookback = off; off += align256(size_t(l.tiles) * kRadixMax * 4);
+    l.counters = off; off += align256(2 * 4);
+    l.total = off;
+    return l;
+}
+
 }  // namespace
+
+size_t aux_sort_workspace(uint32_t words, uint64_t n) { return aux_layout(words, n).total; }
+
+ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
+                     uint32_t aux_bits, uint32_t *flags, void *ws, hipStream_t st) {
+    if (n < 2 || aux_bits == 0) return CKEY_OK;
+    const AuxLayout l = aux_layout(words, n);
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
+    uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
+    uint16_t *alt_aux = reinterpret_cast<uint16_t *>(w8 + l.alt_aux);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(w8 + l.hist);
+    uint32_t *lookback = reinterpret_cast<uint32_t *>(w8 + l.lookback);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(w8 + l.counters);
+    const uint32_t lo = aux_bits / 2, hi = aux_bits - lo;
+    std::vector<Pass> ps;
+    if (lo) ps.push_back({kAuxWord, 0, lo});
+    ps.push_back({kAuxWord, lo, hi});
+    CKEY_TRY(fill_u32(hist, 2 * kRadixMax, 0, st));
+    CKEY_TRY(fill_u32(counters, 2, 0, st));
+    HistArgs ha{};
+    for (size_t p = 0; p < ps.size(); ++p) {
+        ha.shift[p] = ps[p].shift;
+        ha.bits[p] = ps[p].bits;
+        ha.out[p] = uint32_t(p);
+    }
+    ha.npass = uint32_t(ps.size());
+    uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
+    if (hblocks > 2048) hblocks = 2048;
+    {
+        const int pr_ = prof_begin(st, "hist");
+        hipLaunchKernelGGL(k_hist<uint16_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, aux, n, ha, hist);
+        prof_end(st, pr_);
+    }
+    CKEY_TRY(launch_status());
+    hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist);
+    CKEY_TRY(launch_status());
+    // With two passes: caller -> workspace (moving aux) -> caller.
+    Bufs first{ck, rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
+    Bufs second{alt, alt_rid, ck, rid, n, n, alt_aux, nullptr};
+    auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
+              : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
+    for (size_t p = 0; p < ps.size(); ++p) {
+        CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
+        const int pr_ = prof_begin(st, "bucket_pass");
+        hipLaunchKernelGGL(kern, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, p == 0 ? first : second,
+                           n, words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+        prof_end(st, pr_);
+        CKEY_TRY(launch_status());
+    }
+    if (ps.size() == 1) {  // one pass wrote the workspace: copy back
+        Bufs back{alt, alt_rid, ck, rid, n, n, nullptr, nullptr};
+        uint64_t blocks = (n + kWG - 1) / kWG;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_copy_back, dim3(uint32_t(blocks)), dim3(kWG), 0, st, back, n, words);
+        CKEY_TRY(launch_status());
+    }
+    return CKEY_OK;
+}
 
 size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
     return layout(words, nbits, n, d, rid_bits).total;
@@ -365,7 +451,7 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
 
     // Ping-pong between the caller's arrays (leading dimension ld) and the
     // workspace copy (leading dimension n).
-    Bufs cur{ck, rid, alt, alt_rid, ld, n};
+    Bufs cur{ck, rid, alt, alt_rid, ld, n, nullptr, nullptr};
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
@@ -378,7 +464,7 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         }
         CKEY_TRY(launch_status());
         cur = Bufs{cur.dst, cur.dst_rid, const_cast<uint64_t *>(cur.src),
-                   const_cast<uint32_t *>(cur.src_rid), cur.dst_ld, cur.src_ld};
+                   const_cast<uint32_t *>(cur.src_rid), cur.dst_ld, cur.src_ld, nullptr, nullptr};
     }
     if (cur.src != ck) {
         uint64_t blocks = (n + kWG - 1) / kWG;

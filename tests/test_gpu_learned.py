@@ -193,3 +193,32 @@ def test_trained_network_gain(ck):
           f"{probes_un:.2f} (|err| {err_un:.1f}), splitter {probes_sp:.2f} global + LDS levels")
     assert err_tr < 0.5 * err_un
     assert probes_tr < probes_un
+
+
+def test_bucket_spanning_a_gap_sorts_in_place(ck):
+    """A bucket whose threshold range spans the gap between two clusters has no
+    common prefix; its keys still differ below the 32 bits each cluster shares,
+    so the in-LDS sort must finish it without the radix fallback."""
+    import torch
+    rng = np.random.default_rng(12)
+    n = 1 << 17
+    rows = rng.integers(0, 256, (n, 16), dtype=np.uint8)
+    hi = rng.random(n) < 0.5
+    rows[:, 0] = np.where(hi, 0x80, 0x00)
+    rows[:, 1:5] = np.where(hi[:, None], 0xFF, 0x00)   # 32 bits shared within a cluster
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    plan = ck.ckey_plan_query(d)
+    srt = np.ascontiguousarray(O.compress(k, d)[0, perm])
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    ck.ckey_cdf_fit(model, to_dev(srt[::7].copy()), steps=20, batch=1024)
+    T = model.thresholds().cpu().numpy().view(np.uint64)
+    gap = [b for b in range(255) if (T[b] >> np.uint64(63)) != (T[b + 1] >> np.uint64(63))]
+    assert gap, "expected a bucket spanning both clusters"
+    dk = ck.DeviceKeys.from_numpy(rows)
+    ckd, rid = ck.ckey_compress(dk, d)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, plan["nbits"], rid, method=ck.CKEY_SORT_SPLITTER, model=model, flags=flags)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    assert int(flags.item()) & ck.CKEY_FLAG_BUCKET_OVERFLOW == 0
