@@ -2,13 +2,15 @@
 //
 // The paper cuts the D-bitmap into 8-byte masks and applies x86 PEXT to each
 // 8-byte slice of the key, joining the pieces with shift and OR.  gfx950 has
-// no PEXT, but the masks are the same for every key, so the host turns them
-// into a wave-uniform program once per call: every maximal run of 1-bits of
-// the bitmap, cut at 32-bit source-word and 32-bit destination-half
-// boundaries, becomes one (bit-field extract, shift, OR) step.  The program
-// lives in the kernel argument segment and is read with scalar loads; each key
-// costs one 128-bit load per 16 key bytes that hold D bits, one v_bfe_u32 and
-// one shift-or per run, and one coalesced 64-bit store per output word.
+// no PEXT.  The masks are the same for every key, so the host prepares, for
+// each 32-bit big-endian source word that holds D bits, its mask m, the five
+// "move" masks of the log-step compress of Hacker's Delight (Warren, 2nd ed.,
+// Sec. 7-4: after x &= m, step i moves the selected bits right by 2^i), the
+// number of selected bits and their offset in the compressed string.  Each key
+// then costs, per such word, one AND plus five (AND, XOR, shift-OR) steps and
+// a 64-bit shift-OR into the output word -- a fixed cost, independent of how
+// fragmented the mask is, with all per-word constants in scalar registers.
+// Source words are fetched with 128-bit loads, four 16-byte chunks at a time.
 #include <algorithm>
 #include <vector>
 
@@ -18,66 +20,46 @@ namespace ckey {
 
 namespace {
 
-constexpr int kMaxRuns = 512;
-constexpr int kMaxChunks = 64;
+constexpr int kMaxChunks = 24;  // 16-byte chunks per launch (longer keys take several launches)
 
-// Run encoding (one u32 per run).
-constexpr uint32_t kRunLenShift = 5;     // bits 5..10: length 1..32
-constexpr uint32_t kRunDstShift = 11;    // bits 11..15: destination shift inside the 32-bit half
-constexpr uint32_t kRunHi = 1u << 16;    // destination is the high half of the 64-bit word
-constexpr uint32_t kRunFlush = 1u << 17; // this run completes the output word
-constexpr uint32_t kRunWhole = 1u << 18; // the run is the whole 32-bit source word
+// One 32-bit source word (slot q of chunk c).  m == 0: the word holds no D bit.
+struct WordOp {
+    uint32_t m;       // D bits of the word (big-endian word of the bitmap)
+    uint32_t mv[5];   // bits moved right by 1, 2, 4, 8, 16
+    uint32_t pc;      // popcount(m)
+    uint32_t off;     // offset of the word's first selected bit in the compressed string
+};
 
 struct CompressPlan {
     uint32_t n_chunks;
-    uint32_t word_begin;     // first output word this launch writes
-    uint32_t zero_end;       // after the runs, zero-fill output words up to this one
+    uint32_t word_begin;     // this launch writes output words [word_begin, word_end)
+    uint32_t word_end;
+    uint32_t zero_end;       // and zero-fills [word_end, zero_end)
+    uint32_t kw_init;        // output word of the first source word's first bit
     uint32_t write_rowids;
-    uint16_t chunk[kMaxChunks];             // 16-byte source chunk index
-    uint16_t run_begin[kMaxChunks * 4 + 1]; // runs of chunk c, word q: [run_begin[4c+q], run_begin[4c+q+1])
-    uint32_t runs[kMaxRuns];
+    uint32_t chunk[kMaxChunks];    // 16-byte chunk index in the key
+    WordOp op[kMaxChunks * 4];
 };
 
-struct Run {
-    uint32_t src_word;  // 32-bit source word index
-    uint32_t code;
-    uint32_t out_word;  // 64-bit output word index
-};
-
-// Decompose the bitmap into runs in output order.
-void bitmap_runs(const uint8_t *bm, uint32_t L, std::vector<Run> &runs, uint32_t &nbits) {
-    runs.clear();
-    uint32_t c = 0;  // output bit index
-    const uint32_t nw = (L + 3) / 4;
-    for (uint32_t j = 0; j < nw; ++j) {
-        uint32_t m = 0;
-        for (uint32_t t = 0; t < 4; ++t) m = (m << 8) | (4 * j + t < L ? bm[4 * j + t] : 0u);
-        uint32_t a = 0;  // MSB-based index inside the source word
-        while (a < 32) {
-            if (!((m >> (31 - a)) & 1u)) { ++a; continue; }
-            uint32_t len = 0;
-            while (a + len < 32 && ((m >> (31 - a - len)) & 1u)) ++len;
-            // source bits [a, a+len) -> output bits [c, c+len), split at 32-bit output halves
-            uint32_t done = 0;
-            while (done < len) {
-                uint32_t o = (c + done) & 63;
-                uint32_t room = 32 - (o & 31);
-                uint32_t part = std::min(len - done, room);
-                uint32_t rshift = 32 - (a + done) - part;
-                uint32_t dshift = 32 - (o & 31) - part;
-                uint32_t code = rshift | (part << kRunLenShift) | (dshift << kRunDstShift) |
-                                (o < 32 ? kRunHi : 0u) | (part == 32 ? kRunWhole : 0u);
-                if (((c + done + part) & 63) == 0) code |= kRunFlush;
-                runs.push_back({j, code, (c + done) >> 6});
-                done += part;
-            }
-            c += len;
-            a += len;
-        }
+// Move masks of the log-step compress for mask m (Hacker's Delight Sec. 7-4).
+void compress_masks(uint32_t m, uint32_t mv[5]) {
+    uint32_t mk = ~m << 1;  // counts the zeros to the right of each bit
+    for (int i = 0; i < 5; ++i) {
+        uint32_t mp = mk ^ (mk << 1);  // parallel suffix (prefix XOR from the right)
+        mp ^= mp << 2;
+        mp ^= mp << 4;
+        mp ^= mp << 8;
+        mp ^= mp << 16;
+        const uint32_t v = mp & m;     // bits to move in this step
+        mv[i] = v;
+        m = (m ^ v) | (v >> (1u << i));
+        mk &= ~mp;
     }
-    nbits = c;
-    if (!runs.empty()) runs.back().code |= kRunFlush;  // the last (possibly partial) word
 }
+
+struct SrcWord {
+    uint32_t j, m, off;
+};
 
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
@@ -99,9 +81,12 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
     } else {
         p = k.bytes + i * k.stride;
     }
-    uint32_t lo = 0, hi = 0, kw = plan.word_begin;
-    // Chunks are taken four at a time: all loads of a group are issued before
-    // any of its output stores, so they overlap.
+    uint64_t acc = 0;
+    uint32_t kw = plan.kw_init;
+    // Stores outside [word_begin, word_end) belong to a neighbouring launch.
+    auto store = [&](uint32_t kk, uint64_t val) {
+        if (kk >= plan.word_begin && kk < plan.word_end) ck[uint64_t(kk) * k.n + i] = val;
+    };
     for (uint32_t c0 = 0; c0 < plan.n_chunks; c0 += 4) {
         uint32_t x[4][4];
 #pragma unroll
@@ -120,13 +105,12 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
             } else if (MODE == kLoad4) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
+                    if (plan.op[4 * c + q].m)
                         x[g][q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (plan.run_begin[4 * c + q] != plan.run_begin[4 * c + q + 1])
-                        x[g][q] = key_word_bytes(p, 4 * cb + q, len);
+                    if (plan.op[4 * c + q].m) x[g][q] = key_word_bytes(p, 4 * cb + q, len);
             }
         }
 #pragma unroll
@@ -135,23 +119,35 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
             if (c >= plan.n_chunks) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t r1 = plan.run_begin[4 * c + q + 1];
-                for (uint32_t r = plan.run_begin[4 * c + q]; r < r1; ++r) {
-                    const uint32_t R = plan.runs[r];
-                    uint32_t f = (R & kRunWhole) ? x[g][q]
-                                                 : __builtin_amdgcn_ubfe(x[g][q], R & 31u, (R >> kRunLenShift) & 63u);
-                    f <<= (R >> kRunDstShift) & 31u;
-                    if (R & kRunHi) hi |= f; else lo |= f;
-                    if (R & kRunFlush) {
-                        ck[uint64_t(kw) * k.n + i] = (uint64_t(hi) << 32) | lo;
-                        ++kw;
-                        lo = hi = 0;
+                const WordOp &op = plan.op[4 * c + q];
+                if (op.m == 0) continue;
+                uint32_t v = x[g][q] & op.m;
+                if (op.m != 0xFFFFFFFFu) {
+#pragma unroll
+                    for (int s = 0; s < 5; ++s) {
+                        const uint32_t t = v & op.mv[s];
+                        v = (v ^ t) | (t >> (1u << s));
                     }
+                }
+                // append the op.pc low bits of v at bit op.off of the compressed string
+                const uint32_t o = op.off & 63u, end = o + op.pc;
+                if ((op.off >> 6) != kw) {  // the previous output word is complete
+                    store(kw, acc);
+                    acc = 0;
+                    kw = op.off >> 6;
+                }
+                if (end <= 64) {
+                    acc |= uint64_t(v) << (64 - end);
+                } else {  // straddles two output words
+                    store(kw, acc | (uint64_t(v) >> (end - 64)));
+                    ++kw;
+                    acc = uint64_t(v) << (128 - end);
                 }
             }
         }
     }
-    for (; kw < plan.zero_end; ++kw) ck[uint64_t(kw) * k.n + i] = 0;
+    store(kw, acc);
+    for (uint32_t kk = plan.word_end; kk < plan.zero_end; ++kk) ck[uint64_t(kk) * k.n + i] = 0;
     if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
 }
 
@@ -159,85 +155,92 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
 
 ckey_status compress_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
                             uint32_t *rowids, uint32_t *flags, hipStream_t st) {
-    std::vector<Run> runs;
+    // Source words with D bits, in key order, with their offsets in the compressed string.
+    std::vector<SrcWord> src;
     uint32_t nbits = 0;
-    bitmap_runs(bm, k.L, runs, nbits);
+    for (uint32_t j = 0; j < (k.L + 3) / 4; ++j) {
+        uint32_t m = 0;
+        for (uint32_t t = 0; t < 4; ++t) m = (m << 8) | (4 * j + t < k.L ? bm[4 * j + t] : 0u);
+        if (!m) continue;
+        src.push_back({j, m, nbits});
+        nbits += __builtin_popcount(m);
+    }
     const uint32_t w = nbits ? (nbits + 63) / 64 : 1;
     if (words < w) return CKEY_ERR_INVALID;
     if (k.n == 0) return CKEY_OK;
     const int mode = load_mode(k);
     const uint32_t blocks = uint32_t((k.n + kWG - 1) / kWG);
 
-    // Greedily pack whole output words into launches that fit the argument block.
-    size_t r0 = 0;
+    // Each launch owns a range of output words [wb, we) and takes every source
+    // word with a bit in it (at most kMaxChunks chunks); a source word that
+    // straddles a range boundary is processed by both launches, each storing
+    // only its own words.
+    auto overlapping = [&](uint32_t wb, uint32_t we, size_t &a0, size_t &a1) {
+        a0 = 0;
+        while (a0 < src.size() && src[a0].off + __builtin_popcount(src[a0].m) <= 64 * wb) ++a0;
+        a1 = a0;
+        while (a1 < src.size() && src[a1].off < 64 * we) ++a1;
+    };
+    auto chunks_of = [&](size_t a0, size_t a1) {
+        uint32_t nc = 0, lc = UINT32_MAX;
+        for (size_t r = a0; r < a1; ++r)
+            if (src[r].j / 4 != lc) { ++nc; lc = src[r].j / 4; }
+        return nc;
+    };
+    uint32_t wb = 0;
     bool first = true;
     do {
+        uint32_t we = wb + 1;
+        size_t a0, a1;
+        overlapping(wb, we, a0, a1);
+        if (chunks_of(a0, a1) > uint32_t(kMaxChunks)) return CKEY_ERR_UNSUPPORTED;
+        while (we < w) {
+            size_t b0, b1;
+            overlapping(wb, we + 1, b0, b1);
+            if (chunks_of(b0, b1) > uint32_t(kMaxChunks)) break;
+            ++we;
+            a0 = b0;
+            a1 = b1;
+        }
         CompressPlan plan{};
         plan.write_rowids = first ? 1u : 0u;
-        plan.word_begin = runs.empty() ? 0u : runs[r0].out_word;
-        size_t r1 = r0;
-        // extend by whole output words while the limits hold
-        while (r1 < runs.size()) {
-            size_t e = r1;
-            const uint32_t ow = runs[r1].out_word;
-            while (e < runs.size() && runs[e].out_word == ow) ++e;
-            // count chunks for [r0, e)
-            uint32_t chunks = 0, last = UINT32_MAX;
-            for (size_t r = r0; r < e; ++r) {
-                uint32_t cb = runs[r].src_word / 4;
-                if (cb != last) { ++chunks; last = cb; }
+        plan.word_begin = wb;
+        plan.word_end = we;
+        plan.zero_end = we == w ? words : 0u;
+        plan.kw_init = a0 < a1 ? src[a0].off >> 6 : wb;
+        uint32_t cidx = 0, lc = UINT32_MAX;
+        for (size_t r = a0; r < a1; ++r) {
+            const uint32_t cb = src[r].j / 4, q = src[r].j % 4;
+            if (cb != lc) {
+                plan.chunk[cidx++] = cb;
+                lc = cb;
             }
-            if ((e - r0) > size_t(kMaxRuns) || chunks > uint32_t(kMaxChunks)) {
-                if (r1 == r0) return CKEY_ERR_UNSUPPORTED;  // one output word too large
-                break;
-            }
-            r1 = e;
+            WordOp &op = plan.op[4 * (cidx - 1) + q];
+            op.m = src[r].m;
+            compress_masks(src[r].m, op.mv);
+            op.pc = __builtin_popcount(src[r].m);
+            op.off = src[r].off;
         }
-        // fill the plan with runs [r0, r1)
-        uint32_t nc = 0, last = UINT32_MAX;
-        for (size_t r = r0; r < r1; ++r) {
-            const uint32_t cb = runs[r].src_word / 4, q = runs[r].src_word % 4;
-            if (cb != last) {
-                plan.chunk[nc] = uint16_t(cb);
-                for (int t = 0; t <= 4; ++t) plan.run_begin[4 * nc + t] = uint16_t(r - r0);
-                ++nc;
-                last = cb;
-            }
-            plan.runs[r - r0] = runs[r].code;
-            // run r belongs to (chunk nc-1, word q): bump the ends of words q..3 of this chunk
-            for (uint32_t t = q + 1; t <= 4; ++t) plan.run_begin[4 * (nc - 1) + t] = uint16_t(r - r0 + 1);
-        }
-        plan.n_chunks = nc;
-        const bool last_launch = (r1 == runs.size());
-        plan.zero_end = last_launch ? words : 0u;
-        if (runs.empty()) plan.word_begin = 0;
-        switch (mode) {
-            case kLoad16:
-                {
-                    const int pr_ = prof_begin(st, "compress");
+        plan.n_chunks = cidx;
+        {
+            const int pr_ = prof_begin(st, "compress");
+            switch (mode) {
+                case kLoad16:
                     hipLaunchKernelGGL(k_compress<kLoad16>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
-                    prof_end(st, pr_);
-                }
-                break;
-            case kLoad4:
-                {
-                    const int pr_ = prof_begin(st, "compress");
+                    break;
+                case kLoad4:
                     hipLaunchKernelGGL(k_compress<kLoad4>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
-                    prof_end(st, pr_);
-                }
-                break;
-            default:
-                {
-                    const int pr_ = prof_begin(st, "compress");
+                    break;
+                default:
                     hipLaunchKernelGGL(k_compress<kLoadBytes>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
-                    prof_end(st, pr_);
-                }
-                break;
+                    break;
+            }
+            prof_end(st, pr_);
         }
         CKEY_TRY(launch_status());
         first = false;
-        r0 = r1;
-    } while (r0 < runs.size());
+        wb = we;
+    } while (wb < w);
     return CKEY_OK;
 }
 
