@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "compress+sort keys/s & HBM GB/s at 2^26 keys vs plain GPU full-key sort"
 KERNEL_BYTES = ("compress", "hist", "onesweep", "assign_learned", "assign_splitter",
-                "bucket_scatter", "bucket_sort")
+                "bucket_pass", "bucket_sort")
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -249,14 +249,14 @@ def main():
     key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
     rec = 8 * w + 4
     per_key = {"compress": key_bytes_read + rec, "hist": 8 * w, "onesweep": 2 * rec,
-               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_scatter": 2 + 2 * rec,
+               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_pass": 2 * rec + 3,
                "bucket_sort": 8 + 2 * rec}
     step_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     dom_bytes = per_key[dom] * n
     achieved = dom_bytes / (kern[dom]["ms_per_launch"] / 1e3) / 1e9
     src = os.path.join(ROOT, "paper_2009_11543_amd", "csrc",
-                       "k_radix.hip" if dom in ("onesweep", "hist") else
+                       "k_radix.hip" if dom in ("onesweep", "hist", "bucket_pass") else
                        "k_compress.hip" if dom == "compress" else "k_learned.hip")
     traffic = traffic_for(dom, args.workload, src)
 

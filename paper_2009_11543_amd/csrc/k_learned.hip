@@ -37,7 +37,8 @@ constexpr int kNP = 6 * kH + 1;  // parameters
 constexpr int kNPad = 392;       // parameters + loss slot, padded
 constexpr int kLoss = kNP;       // index of the loss in a partial-sum row
 constexpr size_t kOffParams = 0, kOffM = 2048, kOffV = 4096, kOffT = 8192;
-constexpr int kCap = 5120;       // max bucket size sorted in LDS
+constexpr int kCapLarge = 5120;  // max bucket size sorted in LDS (large-bucket kernel)
+constexpr int kCapSmall = 2560;  // (small-bucket kernel, for <= 1600 rows per bucket on average)
 constexpr int kRunCap = 32;      // max run of equal first words sorted in place
 constexpr int kAssignWG = 1024;
 constexpr uint32_t kKeysPerAssignWG = 65535;  // keeps the packed 16-bit LDS counters exact
@@ -347,24 +348,13 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict
     if (tid == 0) starts[B] = tot;
 }
 
-constexpr int kSortWG = 512;  // threads per bucket-sort workgroup (8 waves)
-
-// Full-record order of two rows (words, then row id); rows index the bucket.
-__device__ __forceinline__ bool rec_less(const uint64_t *ck, const uint32_t *rid, uint64_t n,
-                                         uint32_t words, uint64_t a, uint64_t b) {
-    for (uint32_t k = 0; k < words; ++k) {
-        const uint64_t x = ck[uint64_t(k) * n + a], y = ck[uint64_t(k) * n + b];
-        if (x != y) return x < y;
-    }
-    return rid[a] < rid[b];
-}
 
 // One workgroup per bucket, in place on rows [starts[b], starts[b+1]) of ck/rid
 // (the rows are already grouped by bucket).  Every first word x in bucket b
 // lies in [T[b], T[b+1]), so all share the common prefix (cp bits) of that
 // range; the LDS sort key is x << cp, whose equal values are equal first words.
-template <int WC>
-__global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ ck,
+template <int WC, int kCap, int kSortWG>
+__global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict__ ck,
                                                          uint32_t *__restrict__ rid, uint64_t n,
                                                          uint32_t words_rt,
                                                          const uint32_t *__restrict__ starts,
@@ -374,10 +364,9 @@ __global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ 
     __shared__ uint32_t s_k[2][kCap];    // [0]: high, [1]: low half of the local key;
                                          // afterwards the staging buffer of the permute
     __shared__ uint16_t s_idx[2][kCap];  // element order, ping-pong
-    __shared__ uint16_t s_rank[kCap];
     __shared__ uint32_t s_wc[NW][256];
     __shared__ uint32_t s_tmp[NW];
-    __shared__ uint32_t s_and[2], s_or[2], s_fail;
+    __shared__ uint32_t s_and[2], s_or[2], s_fail, s_redo;
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t b = blockIdx.x;
@@ -398,20 +387,33 @@ __global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ 
         s_and[0] = s_and[1] = ~0u;
         s_or[0] = s_or[1] = 0u;
         s_fail = 0u;
+        s_redo = 0u;
     }
     __syncthreads();
     uint32_t a_and[2] = {~0u, ~0u}, a_or[2] = {0u, 0u};
-    for (uint32_t j = tid; j < cnt; j += kSortWG) {
-        const uint64_t x = ck[start + j];
-        const uint64_t l64 = cp < 64 ? x << cp : 0ull;
-        const uint32_t h32 = uint32_t(l64 >> 32), l32 = uint32_t(l64);
-        s_k[0][j] = h32;
-        s_k[1][j] = l32;
-        s_idx[0][j] = uint16_t(j);
-        a_and[0] &= h32;
-        a_or[0] |= h32;
-        a_and[1] &= l32;
-        a_or[1] |= l32;
+    {
+        constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
+        uint64_t xs[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {  // all loads first: PER in flight per thread
+            const uint32_t j = tid + u * kSortWG;
+            xs[u] = j < cnt ? ck[start + j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            if (j < cnt) {
+                const uint64_t l64 = cp < 64 ? xs[u] << cp : 0ull;
+                const uint32_t h32 = uint32_t(l64 >> 32), l32 = uint32_t(l64);
+                s_k[0][j] = h32;
+                s_k[1][j] = l32;
+                s_idx[0][j] = uint16_t(j);
+                a_and[0] &= h32;
+                a_or[0] |= h32;
+                a_and[1] &= l32;
+                a_or[1] |= l32;
+            }
+        }
     }
     atomicAnd(&s_and[0], a_and[0]);
     atomicOr(&s_or[0], a_or[0]);
@@ -419,89 +421,139 @@ __global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ 
     atomicOr(&s_or[1], a_or[1]);
     __syncthreads();
     const uint32_t vary[2] = {s_and[0] ^ s_or[0], s_and[1] ^ s_or[1]};
+    // Digits of the 64-bit local key, 0 = least significant; d < 4 is in the low half.
+    auto digit_varies = [&](int d) { return ((vary[d < 4 ? 1 : 0] >> (8 * (d & 3))) & 0xFFu) != 0; };
+    // First attempt: only the three most significant varying digits, then an
+    // insertion pass over runs of equal top digits.  If some run is long, redo
+    // with every varying digit.
+    int dmin = 8, nvar = 0, nall = 0;
+    for (int d = 7; d >= 0; --d)
+        if (digit_varies(d)) {
+            ++nall;
+            if (nvar < 3) { dmin = d; ++nvar; }
+        }
     int cur = 0;
-    // Each wave ranks a contiguous slice of Q elements (Q a multiple of 64) in order.
+    // Each wave ranks a contiguous slice of Q elements (Q a multiple of 64) in
+    // order, at most kRounds rounds of 64.
+    constexpr int kRounds = (kCap + kSortWG - 1) / kSortWG;
     const uint32_t Q = ((cnt + NW * 64 - 1) / (NW * 64)) * 64;
     const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
     const uint64_t lane_lt = (1ull << lane) - 1ull;
-    for (int d = 0; d < 8; ++d) {  // LSD: low half first
-        const int half = d < 4 ? 1 : 0;
-        const uint32_t shift = 8 * (d & 3);
-        if (((vary[half] >> shift) & 0xFFu) == 0) continue;  // digit constant in the bucket
-        const uint32_t *key = s_k[half];
-        for (int t = tid; t < NW * 256; t += kSortWG) (&s_wc[0][0])[t] = 0;
-        __syncthreads();
-        for (uint32_t r = e0; r < e0 + Q; r += 64) {
-            const uint32_t e = r + lane;
-            const bool valid = e < e1;
-            const uint32_t dig = valid ? (key[s_idx[cur][e]] >> shift) & 0xFFu : 0u;
-            uint64_t peers = __ballot(valid);
-#pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
-                const bool on = (dig >> bit) & 1u;
-                const uint64_t bal = __ballot(on);
-                peers &= on ? bal : ~bal;
-            }
-            const uint32_t below = __popcll(peers & lane_lt);
-            uint32_t old = 0;
-            if (valid) old = s_wc[wave][dig];
-            if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
-            if (valid) s_rank[e] = uint16_t(old + below);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const int dlo = attempt == 0 ? dmin : 0;
+        if (attempt == 1) {
+            for (uint32_t j = tid; j < cnt; j += kSortWG) s_idx[0][j] = uint16_t(j);
+            cur = 0;
+            __syncthreads();
         }
-        __syncthreads();
-        {
-            uint32_t c[NW], tot = 0;
+        for (int d = dlo; d < 8; ++d) {  // LSD over the chosen digits
+            if (!digit_varies(d)) continue;
+            const int half = d < 4 ? 1 : 0;
+            const uint32_t shift = 8 * (d & 3);
+            const uint32_t *key = s_k[half];
+            for (int t = tid; t < NW * 256; t += kSortWG) (&s_wc[0][0])[t] = 0;
+            __syncthreads();
+            uint32_t rank[kRounds], dg[kRounds];
+            uint16_t ids[kRounds];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                c[w] = tid < 256 ? s_wc[w][tid] : 0u;
-                tot += c[w];
+            for (int u = 0; u < kRounds; ++u) {
+                const uint32_t e = e0 + 64 * u + lane;
+                const bool valid = e < e1;
+                ids[u] = valid ? s_idx[cur][e] : uint16_t(0);
+                const uint32_t dig = valid ? (key[ids[u]] >> shift) & 0xFFu : 0u;
+                dg[u] = dig;
+                uint64_t peers = __ballot(valid);
+#pragma unroll
+                for (int bit = 0; bit < 8; ++bit) {
+                    const bool on = (dig >> bit) & 1u;
+                    const uint64_t bal = __ballot(on);
+                    peers &= on ? bal : ~bal;
+                }
+                const uint32_t below = __popcll(peers & lane_lt);
+                uint32_t old = 0;
+                if (valid) old = s_wc[wave][dig];
+                if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
+                rank[u] = old + below;
             }
-            uint32_t all;
-            uint32_t ds = block_excl_scan_n<kSortWG>(tot, s_tmp, all);
-            if (tid < 256) {
+            __syncthreads();
+            {
+                uint32_t c[NW], tot = 0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
-                    s_wc[w][tid] = ds;
-                    ds += c[w];
+                    c[w] = tid < 256 ? s_wc[w][tid] : 0u;
+                    tot += c[w];
+                }
+                uint32_t all;
+                uint32_t ds = block_excl_scan_n<kSortWG>(tot, s_tmp, all);
+                if (tid < 256) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        s_wc[w][tid] = ds;
+                        ds += c[w];
+                    }
                 }
             }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kRounds; ++u) {
+                const uint32_t e = e0 + 64 * u + lane;
+                if (e < e1) s_idx[cur ^ 1][s_wc[wave][dg[u]] + rank[u]] = ids[u];
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        if (attempt == 1 || nall <= 3) break;  // every varying digit is sorted
+        // Runs of equal top digits: insertion sort by the whole local key (LDS).
+        const uint32_t sh = 8 * uint32_t(dmin);  // bits below the sorted digits
+        uint16_t *ordr = s_idx[cur];
+        auto top = [&](uint16_t id) { return ((uint64_t(s_k[0][id]) << 32) | s_k[1][id]) >> sh; };
+        for (uint32_t j = tid; j < cnt; j += kSortWG) {
+            const uint64_t t0 = top(ordr[j]);
+            if (j > 0 && top(ordr[j - 1]) == t0) continue;
+            uint32_t r = 1;
+            while (j + r < cnt && r <= 16u && top(ordr[j + r]) == t0) ++r;
+            if (r > 16u) {
+                s_redo = 1u;
+                continue;
+            }
+            for (uint32_t a = 1; a < r; ++a) {
+                const uint16_t v = ordr[j + a];
+                const uint64_t kv = (uint64_t(s_k[0][v]) << 32) | s_k[1][v];
+                uint32_t c = a;
+                while (c > 0) {
+                    const uint16_t u = ordr[j + c - 1];
+                    const uint64_t ku = (uint64_t(s_k[0][u]) << 32) | s_k[1][u];
+                    if (ku <= kv) break;  // stable: equal local keys keep their order
+                    ordr[j + c] = u;
+                    --c;
+                }
+                ordr[j + c] = v;
+            }
         }
         __syncthreads();
-        for (uint32_t e = e0 + lane; e < e1; e += 64) {
-            const uint16_t id = s_idx[cur][e];
-            const uint32_t pos = s_wc[wave][(key[id] >> shift) & 0xFFu] + s_rank[e];
-            s_idx[cur ^ 1][pos] = id;
-        }
-        __syncthreads();
-        cur ^= 1;
+        if (!s_redo) break;
     }
-    // Runs of equal first words: order by the remaining words, then the row id.
-    const uint64_t *bck = ck + start;
-    const uint32_t *brid = rid + start;
+    // Runs of equal first words (equal local keys) must be ordered by the
+    // remaining words, then the row id.  Record each run's length at its start
+    // in the free ping-pong buffer, then -- with the local keys no longer
+    // needed -- stage the row ids and then each remaining word (least
+    // significant first) in LDS and insertion-sort every run by it, stably:
+    // an LSD sort within the runs, with no global reads on the critical path.
     uint16_t *ord = s_idx[cur];
+    uint16_t *runlen = s_idx[cur ^ 1];
     for (uint32_t j = tid; j < cnt; j += kSortWG) {
         const uint16_t i0 = ord[j];
-        if (j > 0) {
-            const uint16_t ip = ord[j - 1];
-            if (s_k[0][ip] == s_k[0][i0] && s_k[1][ip] == s_k[1][i0]) continue;
+        uint32_t r = 0;
+        const bool starts = j == 0 || s_k[0][ord[j - 1]] != s_k[0][i0] || s_k[1][ord[j - 1]] != s_k[1][i0];
+        if (starts) {
+            r = 1;
+            while (j + r < cnt && r <= uint32_t(kRunCap) && s_k[0][ord[j + r]] == s_k[0][i0] &&
+                   s_k[1][ord[j + r]] == s_k[1][i0])
+                ++r;
+            if (r > uint32_t(kRunCap)) s_fail = 1u;
+            if (r > 1) s_redo = 2u;  // reused: "some run needs ordering"
         }
-        uint32_t r = 1;
-        while (j + r < cnt && r <= uint32_t(kRunCap) && s_k[0][ord[j + r]] == s_k[0][i0] &&
-               s_k[1][ord[j + r]] == s_k[1][i0])
-            ++r;
-        if (r > uint32_t(kRunCap)) {
-            s_fail = 1u;
-            continue;
-        }
-        for (uint32_t a = 1; a < r; ++a) {  // insertion sort of ord[j..j+r)
-            const uint16_t v = ord[j + a];
-            uint32_t c = a;
-            while (c > 0 && rec_less(bck, brid, n, words, v, ord[j + c - 1])) {
-                ord[j + c] = ord[j + c - 1];
-                --c;
-            }
-            ord[j + c] = v;
-        }
+        runlen[j] = uint16_t(r);
     }
     __syncthreads();
     if (s_fail) {  // leave the bucket as it is for the radix fallback
@@ -512,19 +564,76 @@ __global__ __launch_bounds__(kSortWG) void k_bucket_sort(uint64_t *__restrict__ 
         }
         return;
     }
-    // Permute in place: stage each array's bucket slice in LDS (coalesced load),
-    // then write it back in sorted order (coalesced store).
+    constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
+    if (s_redo == 2u) {
+        uint64_t *stg = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
+        for (int k = -1; k < int(words); ++k) {
+            if (k == 0) continue;  // first words are equal within a run
+            const int a = k < 0 ? -1 : int(words) - k;  // -1: row ids, then words w-1 .. 1
+            uint64_t v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                v[u] = j >= cnt ? 0ull : a < 0 ? uint64_t(rid[start + j]) : ck[uint64_t(a) * n + start + j];
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                if (j < cnt) stg[j] = v[u];
+            }
+            __syncthreads();
+            for (uint32_t j = tid; j < cnt; j += kSortWG) {
+                const uint32_t r = runlen[j];
+                for (uint32_t q = 1; q < r; ++q) {  // stable insertion sort of ord[j..j+r)
+                    const uint16_t id = ord[j + q];
+                    const uint64_t key = stg[id];
+                    uint32_t c = q;
+                    while (c > 0 && stg[ord[j + c - 1]] > key) {
+                        ord[j + c] = ord[j + c - 1];
+                        --c;
+                    }
+                    ord[j + c] = id;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // Permute in place: stage each array's bucket slice in LDS (coalesced load,
+    // all of a thread's loads in flight at once), then write it back in sorted
+    // order (coalesced store).
     uint64_t *stage = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
     for (uint32_t k = 0; k < words; ++k) {
         uint64_t *wk = ck + uint64_t(k) * n + start;
-        for (uint32_t j = tid; j < cnt; j += kSortWG) stage[j] = wk[j];
+        uint64_t v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            v[u] = j < cnt ? wk[j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            if (j < cnt) stage[j] = v[u];
+        }
         __syncthreads();
         for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stage[ord[j]];
         __syncthreads();
     }
     uint32_t *stage32 = &s_k[0][0];
     uint32_t *rk = rid + start;
-    for (uint32_t j = tid; j < cnt; j += kSortWG) stage32[j] = rk[j];
+    {
+        uint32_t v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            v[u] = j < cnt ? rk[j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            if (j < cnt) stage32[j] = v[u];
+        }
+    }
     __syncthreads();
     for (uint32_t j = tid; j < cnt; j += kSortWG) rk[j] = stage32[ord[j]];
 }
@@ -614,9 +723,15 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     const uint64_t *T = thresholds_of(model);
     {
         const int pr = prof_begin(st, "bucket_sort");
-        auto kb = words == 1 ? k_bucket_sort<1> : words == 2 ? k_bucket_sort<2>
-                : words == 3 ? k_bucket_sort<3> : k_bucket_sort<0>;
-        hipLaunchKernelGGL(kb, dim3(B), dim3(kSortWG), 0, st, ck, rid, n, words, starts, T, B, ovf);
+        if (n / B <= 1600) {  // small buckets: 2560-row capacity, 512 threads, 4 per CU
+            auto kb = words == 1 ? k_bucket_sort<1, kCapSmall, 512> : words == 2 ? k_bucket_sort<2, kCapSmall, 512>
+                    : words == 3 ? k_bucket_sort<3, kCapSmall, 512> : k_bucket_sort<0, kCapSmall, 512>;
+            hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, starts, T, B, ovf);
+        } else {
+            auto kb = words == 1 ? k_bucket_sort<1, kCapLarge, 1024> : words == 2 ? k_bucket_sort<2, kCapLarge, 1024>
+                    : words == 3 ? k_bucket_sort<3, kCapLarge, 1024> : k_bucket_sort<0, kCapLarge, 1024>;
+            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, starts, T, B, ovf);
+        }
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());

@@ -32,10 +32,22 @@ hipEvent_t take_event() {
     return e;
 }
 
-__global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, uint64_t n16) {
-    const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += step)
-        dst[i] = src[i];
+// Each thread moves four 16-byte vectors per iteration, all loads issued
+// before the stores; loads and stores are non-temporal (streamed once).
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src,
+                                                     v4u *__restrict__ dst, uint64_t n16) {
+    const uint64_t step = uint64_t(gridDim.x) * blockDim.x * 4;
+    uint64_t i = uint64_t(blockIdx.x) * blockDim.x * 4 + threadIdx.x;
+    for (; i + 3 * blockDim.x < n16; i += step) {
+        v4u v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(src + i + u * blockDim.x);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], dst + i + u * blockDim.x);
+    }
+    for (; i < n16; i += blockDim.x) dst[i] = src[i];
 }
 
 }  // namespace
@@ -102,12 +114,12 @@ ckey_status ckey_bench_copy(void *dst, const void *src, size_t bytes, void *stre
         reinterpret_cast<uintptr_t>(src) % 16)
         return CKEY_ERR_INVALID;
     const uint64_t n16 = bytes / 16;
-    uint64_t blocks = (n16 + kWG - 1) / kWG;
-    if (blocks > 8192) blocks = 8192;
+    uint64_t blocks = (n16 + 4 * kWG - 1) / (4 * kWG);
+    if (blocks > 4096) blocks = 4096;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int p = prof_begin(st, "stream_copy");
     hipLaunchKernelGGL(k_stream_copy, dim3(uint32_t(blocks)), dim3(kWG), 0, st,
-                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+                       static_cast<const v4u *>(src), static_cast<v4u *>(dst), n16);
     prof_end(st, p);
     return launch_status();
 }

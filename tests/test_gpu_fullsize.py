@@ -1,0 +1,107 @@
+"""Full-size GPU checks (2^26 DNA-window keys, 64 bytes, the benchmark's
+workload and launch configuration).  The oracle cannot sort 2^26 keys in test
+time, so these check what holds at any size and sample what the oracle can
+compute row by row:
+  * the permutation is a permutation, and adjacent rows in its order are in
+    non-decreasing full-key order with ascending row ids among equal keys --
+    which together determine it uniquely;
+  * compressed words of sampled rows equal the oracle's bit-by-bit compression;
+  * the D-bitmap equals the union of the adjacent pairs' D positions, computed
+    on the host from the permuted keys (Theorem 1's definition);
+  * all sort methods give the same permutation.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_11543_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 26
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_11543_amd import ckey
+    rows = datagen.dna_window_keys(N, seed=1)
+    keys = ckey.DeviceKeys(torch.from_numpy(rows).cuda())
+    first = ckey.ckey_rebuild_index([{"keys": keys, "bitmap": None}])[0]
+    d = first["bitmap"].cpu().numpy()
+    perm = first["perm"].cpu().numpy().view(np.uint32)
+    return ckey, rows, keys, d, perm
+
+
+def check_sorted_permutation(rows, perm):
+    assert perm.shape == (N,)
+    seen = np.zeros(N, np.bool_)
+    seen[perm] = True
+    assert seen.all()
+    words = rows.view(">u8")  # (N, 8) big-endian words: lexicographic = byte order
+    for a in range(0, N - 1, 1 << 24):  # chunks keep host memory bounded
+        b = min(N, a + (1 << 24) + 1)
+        w = words[perm[a:b]].astype(np.uint64)
+        lt = np.zeros(b - a - 1, np.bool_)
+        eq = np.ones(b - a - 1, np.bool_)
+        for j in range(8):
+            x, y = w[:-1, j], w[1:, j]
+            lt |= eq & (x < y)
+            eq &= x == y
+        ridok = perm[a:b - 1] < perm[a + 1:b]
+        assert np.all(lt | (eq & ridok))
+
+
+def test_first_build_is_sorted(setup):
+    ck, rows, keys, d, perm = setup
+    check_sorted_permutation(rows, perm)
+
+
+def test_dbitmap_matches_definition(setup):
+    ck, rows, keys, d, perm = setup
+    words = rows.view(">u8")
+    union = np.zeros(64 * 8, np.bool_)
+    for a in range(0, N - 1, 1 << 24):
+        b = min(N, a + (1 << 24) + 1)
+        w = words[perm[a:b]].astype(np.uint64)
+        x = w[:-1] ^ w[1:]
+        nz = x != 0
+        first = np.argmax(nz, axis=1)
+        has = nz.any(axis=1)
+        xv = x[np.arange(len(x)), first][has]
+        lead = 63 - np.floor(np.log2(xv.astype(np.float64))).astype(np.int64)
+        # float log2 can round up for values just below a power of two: fix exactly
+        lead = np.where((xv >> (63 - lead).astype(np.uint64)) == 0, lead + 1, lead)
+        union[64 * first[has] + lead] = True
+    ref = np.packbits(union)
+    np.testing.assert_array_equal(d, ref)
+    assert int(np.unpackbits(d).sum()) == 192
+
+
+@pytest.mark.parametrize("method", ["radix", "splitter", "learned"])
+def test_compress_and_sort_full_size(setup, method):
+    import torch
+    ck, rows, keys, d, perm = setup
+    plan = ck.ckey_plan_query(d)
+    ckd, rid = ck.ckey_compress(keys, d)
+    rng = np.random.default_rng(5)
+    sample = np.sort(rng.choice(N, 4096, replace=False))
+    ref = O.compress(O.Keys(np.ascontiguousarray(rows[sample])), d)
+    np.testing.assert_array_equal(ck.as_u64(ckd[:, torch.from_numpy(sample).cuda()]), ref)
+    opts = {}
+    if method != "radix":
+        train = datagen.dna_window_keys(1 << 22, seed=2)
+        kt = ck.DeviceKeys(torch.from_numpy(train).cuda())
+        ckt, ridt = ck.ckey_compress(kt, d)
+        ck.ckey_sort(ckt, plan["nbits"], ridt)
+        model = ck.CdfModel(bucket_log2=14, seed=3)
+        ck.ckey_cdf_fit(model, ckt[0].contiguous(), steps=300, batch=1 << 16)
+        opts = dict(method=ck.CKEY_SORT_SPLITTER if method == "splitter" else ck.CKEY_SORT_LEARNED,
+                    model=model)
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, plan["nbits"], rid, flags=flags, **opts)
+    got = rid.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got, perm)
+    assert int(flags.item()) & ck.CKEY_FLAG_SPIN_LIMIT == 0

@@ -222,3 +222,32 @@ def test_bucket_spanning_a_gap_sorts_in_place(ck):
     ck.ckey_sort(ckd, plan["nbits"], rid, method=ck.CKEY_SORT_SPLITTER, model=model, flags=flags)
     np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
     assert int(flags.item()) & ck.CKEY_FLAG_BUCKET_OVERFLOW == 0
+
+
+@pytest.mark.parametrize("pattern", ["dup_runs", "few_digits", "all_equal_first_word"])
+def test_bucket_sort_patterns(ck, pattern):
+    """Buckets whose local keys vary in few digits, carry long runs of equal top
+    digits (forcing the all-digit redo), or share one first word."""
+    import torch
+    rng = np.random.default_rng(hash(pattern) % 1000)
+    n = 1 << 16
+    rows = rng.integers(0, 256, (n, 24), dtype=np.uint8)
+    if pattern == "dup_runs":        # 24 top bits shared by groups of ~40 keys
+        rows[:, 0:3] = rng.integers(0, 1600, n).astype(">u4").view(np.uint8).reshape(n, 4)[:, 1:]
+    elif pattern == "few_digits":    # only bits of two bytes vary in the first word
+        rows[:, 0:6] = 7
+        rows[:, 6:8] = rng.integers(0, 256, (n, 2))
+    else:                            # first 8 bytes equal for runs of 20 keys
+        rows[:, 0:8] = np.repeat(rng.integers(0, 256, (n // 20 + 1, 8)), 20, axis=0)[:n]
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    plan = ck.ckey_plan_query(d)
+    srt = np.ascontiguousarray(O.compress(k, d)[0, perm])
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    ck.ckey_cdf_fit(model, to_dev(srt), steps=20, batch=1024)
+    dk = ck.DeviceKeys.from_numpy(rows)
+    ckd, rid = ck.ckey_compress(dk, d)
+    ck.ckey_sort(ckd, plan["nbits"], rid, method=ck.CKEY_SORT_SPLITTER, model=model)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, d)[:, perm])
