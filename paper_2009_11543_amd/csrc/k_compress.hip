@@ -61,32 +61,19 @@ struct SrcWord {
     uint32_t j, m, off;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
-                                                  uint64_t *__restrict__ ck,
-                                                  uint32_t *__restrict__ rowids,
-                                                  uint32_t *__restrict__ flags) {
-    const uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x;
-    if (i >= k.n) return;
-    const uint8_t *p;
-    uint32_t len = k.L;
-    if (MODE == kLoadBytes && k.offsets) {
-        const uint64_t o0 = k.offsets[i], o1 = k.offsets[i + 1];
-        p = k.bytes + o0;
-        if (o1 - o0 > k.L) {
-            if (flags) atomicOr(flags, CKEY_FLAG_KEY_TOO_LONG);
-        } else {
-            len = uint32_t(o1 - o0);
-        }
-    } else {
-        p = k.bytes + i * k.stride;
-    }
+// Gather of one key's D bits into its output words, for a loader that
+// fills the four big-endian words of a 16-byte chunk.
+template <typename Loader>
+__device__ __forceinline__ void compress_key(const CompressPlan &plan, const Loader &ld,
+                                             uint64_t *__restrict__ ck, uint64_t n, uint64_t i) {
     uint64_t acc = 0;
     uint32_t kw = plan.kw_init;
     // Stores outside [word_begin, word_end) belong to a neighbouring launch.
     auto store = [&](uint32_t kk, uint64_t val) {
-        if (kk >= plan.word_begin && kk < plan.word_end) ck[uint64_t(kk) * k.n + i] = val;
+        if (kk >= plan.word_begin && kk < plan.word_end) ck[uint64_t(kk) * n + i] = val;
     };
+    // Chunks are taken four at a time: all loads of a group are issued before
+    // any of its output stores, so they overlap.
     for (uint32_t c0 = 0; c0 < plan.n_chunks; c0 += 4) {
         uint32_t x[4][4];
 #pragma unroll
@@ -94,24 +81,7 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
             const uint32_t c = c0 + g;
 #pragma unroll
             for (int q = 0; q < 4; ++q) x[g][q] = 0;
-            if (c >= plan.n_chunks) continue;
-            const uint32_t cb = plan.chunk[c];
-            if (MODE == kLoad16) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
-                x[g][0] = __builtin_bswap32(v.x);
-                x[g][1] = __builtin_bswap32(v.y);
-                x[g][2] = __builtin_bswap32(v.z);
-                x[g][3] = __builtin_bswap32(v.w);
-            } else if (MODE == kLoad4) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (plan.op[4 * c + q].m)
-                        x[g][q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (plan.op[4 * c + q].m) x[g][q] = key_word_bytes(p, 4 * cb + q, len);
-            }
+            if (c < plan.n_chunks) ld(plan, c, x[g]);
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -147,7 +117,136 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
         }
     }
     store(kw, acc);
-    for (uint32_t kk = plan.word_end; kk < plan.zero_end; ++kk) ck[uint64_t(kk) * k.n + i] = 0;
+    for (uint32_t kk = plan.word_end; kk < plan.zero_end; ++kk) ck[uint64_t(kk) * n + i] = 0;
+}
+
+template <int MODE>
+struct GlobalLoader {
+    const uint8_t *p;
+    uint32_t len;
+    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, uint32_t *x) const {
+        const uint32_t cb = plan.chunk[c];
+        if (MODE == kLoad16) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
+            x[0] = __builtin_bswap32(v.x);
+            x[1] = __builtin_bswap32(v.y);
+            x[2] = __builtin_bswap32(v.z);
+            x[3] = __builtin_bswap32(v.w);
+        } else if (MODE == kLoad4) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (plan.op[4 * c + q].m)
+                    x[q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (plan.op[4 * c + q].m) x[q] = key_word_bytes(p, 4 * cb + q, len);
+        }
+    }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
+                                                  uint64_t *__restrict__ ck,
+                                                  uint32_t *__restrict__ rowids,
+                                                  uint32_t *__restrict__ flags) {
+    const uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x;
+    if (i >= k.n) return;
+    GlobalLoader<MODE> ld{nullptr, k.L};
+    if (MODE == kLoadBytes && k.offsets) {
+        const uint64_t o0 = k.offsets[i], o1 = k.offsets[i + 1];
+        ld.p = k.bytes + o0;
+        if (o1 - o0 > k.L) {
+            if (flags) atomicOr(flags, CKEY_FLAG_KEY_TOO_LONG);
+        } else {
+            ld.len = uint32_t(o1 - o0);
+        }
+    } else {
+        ld.p = k.bytes + i * k.stride;
+    }
+    compress_key(plan, ld, ck, k.n, i);
+    if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
+}
+
+// Variable-length keys: the workgroup's 256 keys occupy one contiguous byte
+// range, which is copied to LDS with 16-byte loads; each thread then reads its
+// key's words from LDS (byte-aligned, zero past the key's length).
+constexpr uint32_t kVarTileBytes = 256 * 128;  // keys up to 128 bytes on average per tile
+
+struct LdsLoader {
+    const uint32_t *s;  // LDS tile, little-endian words
+    uint32_t o;         // key's first byte in the tile
+    uint32_t len;
+    __device__ __forceinline__ uint32_t word(uint32_t j) const {
+        const int32_t have = int32_t(len) - int32_t(4 * j);  // key bytes in this word
+        if (have <= 0) return 0u;
+        const uint32_t b = o + 4 * j;  // byte offset of the word in the tile (< o + len)
+        const uint32_t lo = s[b >> 2], hi = s[(b >> 2) + 1];
+        const uint32_t sh = 8 * (b & 3);
+        const uint32_t le = sh ? (lo >> sh) | (hi << (32 - sh)) : lo;  // bytes b..b+3, little-endian
+        uint32_t v = __builtin_bswap32(le);
+        if (have < 4) v &= ~(0xFFFFFFFFu >> (8 * have));
+        return v;
+    }
+    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, uint32_t *x) const {
+        const uint32_t cb = plan.chunk[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (plan.op[4 * c + q].m) x[q] = word(4 * cb + q);
+    }
+};
+
+__global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan plan,
+                                                      uint64_t *__restrict__ ck,
+                                                      uint32_t *__restrict__ rowids,
+                                                      uint32_t *__restrict__ flags) {
+    // tile bytes + 16 for alignment + 8 zero bytes past the end for the word reads
+    __shared__ uint32_t s_tile[(kVarTileBytes + 32) / 4];
+    const uint64_t t0 = uint64_t(blockIdx.x) * kWG;
+    const uint64_t t1 = min<uint64_t>(k.n, t0 + kWG);
+    const uint64_t b0 = k.offsets[t0], b1 = k.offsets[t1];
+    const uintptr_t base = reinterpret_cast<uintptr_t>(k.bytes);
+    const uintptr_t a0 = (base + b0) & ~uintptr_t(15);  // aligned start (may precede b0)
+    const uint64_t span = (base + b1) - a0;
+    const bool fits = span <= kVarTileBytes;  // uniform
+    if (fits) {
+        // 16-byte chunks fully inside [base + b0 - pad, base + b1) are loaded as
+        // vectors when they lie inside the key buffer; edge chunks byte by byte.
+        const uint64_t nch = (span + 15) / 16;
+        for (uint64_t c = threadIdx.x; c < nch; c += kWG) {
+            const uintptr_t addr = a0 + 16 * c;
+            uint4 v;
+            if (addr >= base + b0 && addr + 16 <= base + b1) {
+                v = *reinterpret_cast<const uint4 *>(addr);
+            } else {
+                uint32_t w[4] = {0, 0, 0, 0};
+                for (int t = 0; t < 16; ++t) {
+                    const uintptr_t bt = addr + t;
+                    if (bt >= base + b0 && bt < base + b1)
+                        w[t >> 2] |= uint32_t(*reinterpret_cast<const uint8_t *>(bt)) << (8 * (t & 3));
+                }
+                v = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+            s_tile[4 * c + 0] = v.x;
+            s_tile[4 * c + 1] = v.y;
+            s_tile[4 * c + 2] = v.z;
+            s_tile[4 * c + 3] = v.w;
+        }
+        for (uint64_t c = 4 * nch + threadIdx.x; c < 4 * nch + 8; c += kWG) s_tile[c] = 0;
+    }
+    __syncthreads();
+    const uint64_t i = t0 + threadIdx.x;
+    if (i >= t1) return;
+    const uint64_t o0 = k.offsets[i], o1 = k.offsets[i + 1];
+    uint32_t len = uint32_t(min<uint64_t>(o1 - o0, k.L));
+    if (o1 - o0 > k.L && flags) atomicOr(flags, CKEY_FLAG_KEY_TOO_LONG);
+    if (fits) {
+        LdsLoader ld{s_tile, uint32_t(base + o0 - a0), len};
+        compress_key(plan, ld, ck, k.n, i);
+    } else {
+        GlobalLoader<kLoadBytes> ld{k.bytes + o0, len};
+        compress_key(plan, ld, ck, k.n, i);
+    }
     if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
 }
 
@@ -232,7 +331,10 @@ ckey_status compress_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, ui
                     hipLaunchKernelGGL(k_compress<kLoad4>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
                     break;
                 default:
-                    hipLaunchKernelGGL(k_compress<kLoadBytes>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                    if (k.offsets)
+                        hipLaunchKernelGGL(k_compress_var, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
+                    else
+                        hipLaunchKernelGGL(k_compress<kLoadBytes>, dim3(blocks), dim3(kWG), 0, st, k, plan, ck, rowids, flags);
                     break;
             }
             prof_end(st, pr_);
