@@ -140,15 +140,40 @@ typedef struct {
                                  0xFFFFFFFF where the keys are equal                   */
     uint64_t *ckeys;          /* device uint64[w*n] out or NULL: the sorted compressed keys */
     uint32_t *flags;          /* device flags word or NULL                              */
+    const ckey_sort_opts *opts; /* sort options of this index, or NULL for the call's  */
 } ckey_index_desc;
 
-/* Rebuild `count` indexes: compress each with its bitmap, sort, and refresh its
- * D-bitmap from adjacent sorted compressed keys.  opts as for ckey_sort
- * (NULL = radix).  count > 1 enqueues all indexes' work as one batch.  Needs a
+/* Rebuild `count` indexes of a table: compress each with its bitmap, sort, and
+ * refresh its D-bitmap from adjacent sorted compressed keys (Sec. 4.3, Sec. 5).
+ * opts as for ckey_sort (NULL = radix), per index overridable.  With count > 1
+ * each index gets its own part of the workspace and its own stream forked from
+ * `stream` (and joined back), so the indexes' kernels overlap.  Needs a
  * workspace. */
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *workspace,
                                size_t *workspace_bytes, void *stream);
+
+/* A table rebuild captured once into a HIP graph and replayed with one launch.
+ * ckey_graph_create records what ckey_rebuild_index(idx, count, opts, ...)
+ * enqueues (the descriptors' pointers, bitmaps and sizes are fixed at
+ * creation; the workspace must stay valid while the graph exists) and
+ * instantiates it; only the radix method can be captured (the bucketing
+ * methods read an overflow count back to the host).  ckey_graph_launch
+ * replays it on `stream`. */
+typedef struct ckey_graph ckey_graph;
+ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
+                              void *workspace, size_t workspace_bytes, ckey_graph **graph);
+ckey_status ckey_graph_launch(ckey_graph *graph, void *stream);
+ckey_status ckey_graph_destroy(ckey_graph *graph);
+
+/* Autotuning: rebuild index `idx` once per candidate option set (after one
+ * warm-up each) timing it with HIP events on `stream`; *best receives the
+ * index of the fastest candidate and times_ms (host float[ncand], or NULL)
+ * each candidate's time.  Synchronizes `stream`.  The workspace must fit every
+ * candidate (ckey_rebuild_index's query with each). */
+ckey_status ckey_tune_index(const ckey_index_desc *idx, const ckey_sort_opts *candidates,
+                            uint32_t ncand, void *workspace, size_t workspace_bytes,
+                            void *stream, uint32_t *best, float *times_ms);
 
 /* ---- CDF model for learned bucketing (an extension; not in the paper) -------
  * Model memory is device memory owned by the caller, ckey_cdf_model_bytes()

@@ -43,7 +43,8 @@ class ckey_sort_opts(ctypes.Structure):
 class ckey_index_desc(ctypes.Structure):
     _fields_ = [("keys", ckey_keys), ("bitmap_in", ctypes.c_void_p), ("perm", ctypes.c_void_p),
                 ("bitmap_out", ctypes.c_void_p), ("pair_pos", ctypes.c_void_p),
-                ("ckeys", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+                ("ckeys", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("opts", ctypes.POINTER(ckey_sort_opts))]
 
 
 def _load():
@@ -59,8 +60,17 @@ def _load():
     lib.ckey_sort.argtypes = [P, U32, U32, P, U64, ctypes.POINTER(ckey_sort_opts), P, SZP, P]
     lib.ckey_rebuild_index.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
                                        ctypes.POINTER(ckey_sort_opts), P, SZP, P]
+    lib.ckey_graph_create.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
+                                      ctypes.POINTER(ckey_sort_opts), P, ctypes.c_size_t,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.ckey_graph_launch.argtypes = [P, P]
+    lib.ckey_graph_destroy.argtypes = [P]
+    lib.ckey_tune_index.argtypes = [ctypes.POINTER(ckey_index_desc), ctypes.POINTER(ckey_sort_opts),
+                                    U32, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_float)]
     for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
-               "ckey_rebuild_index"):
+               "ckey_rebuild_index", "ckey_graph_create", "ckey_graph_launch", "ckey_graph_destroy",
+               "ckey_tune_index"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -206,14 +216,8 @@ def ckey_sort(ck, nbits, rowids, workspace=None, stream=None, **opts):
     return ck, rowids
 
 
-def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
-    """Rebuild one or more indexes.
-
-    ``indexes``: list of dicts with keys ``keys`` (DeviceKeys), ``bitmap``
-    (host uint8 array or None for a first build) and optional booleans
-    ``want_pair_pos`` / ``want_ckeys``.  Returns a list of dicts with
-    ``perm``, ``bitmap`` (device) and optionally ``pair_pos`` / ``ckeys``.
-    """
+def _build_descs(indexes):
+    """ctypes descriptors + output tensors for a list of index specs."""
     descs = (ckey_index_desc * len(indexes))()
     outs, hold = [], []
     for x, spec in enumerate(indexes):
@@ -233,11 +237,38 @@ def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
             o["pair_pos"] = torch.empty(max(k.n - 1, 0), dtype=torch.int32, device=dev)
         if spec.get("want_ckeys"):
             o["ckeys"] = torch.empty((words, k.n), dtype=torch.int64, device=dev)
+        iopts = None
+        if spec.get("opts") is not None:
+            iopts = _opts(**spec["opts"])
+            hold.append(iopts)
         descs[x] = ckey_index_desc(k.c_struct(), bp, o["perm"].data_ptr() if k.n else None,
                                    o["bitmap"].data_ptr(),
                                    o["pair_pos"].data_ptr() if "pair_pos" in o and k.n > 1 else None,
-                                   o["ckeys"].data_ptr() if "ckeys" in o and k.n else None, None)
+                                   o["ckeys"].data_ptr() if "ckeys" in o and k.n else None, None,
+                                   None if iopts is None else ctypes.pointer(iopts))
         outs.append(o)
+    return descs, outs, hold
+
+
+def ckey_rebuild_index_workspace(indexes, **opts):
+    descs, _, _hold = _build_descs(indexes)
+    so = _opts(**opts)
+    need = ctypes.c_size_t(0)
+    _check("ckey_rebuild_index", _lib.ckey_rebuild_index(descs, len(indexes), ctypes.byref(so),
+                                                         None, ctypes.byref(need), None))
+    return need.value
+
+
+def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
+    """Rebuild one or more indexes.
+
+    ``indexes``: list of dicts with keys ``keys`` (DeviceKeys), ``bitmap``
+    (host uint8 array or None for a first build), optional ``opts`` (dict of
+    sort options for this index) and optional booleans ``want_pair_pos`` /
+    ``want_ckeys``.  Returns a list of dicts with ``perm``, ``bitmap``
+    (device) and optionally ``pair_pos`` / ``ckeys``.
+    """
+    descs, outs, _hold = _build_descs(indexes)
     so = _opts(**opts)
     need = ctypes.c_size_t(0)
     _check("ckey_rebuild_index", _lib.ckey_rebuild_index(descs, len(indexes), ctypes.byref(so),
@@ -248,6 +279,57 @@ def ckey_rebuild_index(indexes, workspace=None, stream=None, **opts):
                                                          _ptr(ws), ctypes.byref(need),
                                                          _stream(stream)))
     return outs
+
+
+class RebuildGraph:
+    """A table rebuild (radix method) captured once into a HIP graph.
+
+    ``launch()`` replays it on the current stream; outputs are the tensors in
+    ``outs`` (overwritten by every replay)."""
+
+    def __init__(self, indexes, **opts):
+        self._descs, self.outs, self._hold = _build_descs(indexes)
+        self._so = _opts(**opts)
+        need = ctypes.c_size_t(0)
+        _check("ckey_rebuild_index", _lib.ckey_rebuild_index(self._descs, len(indexes),
+                                                             ctypes.byref(self._so), None,
+                                                             ctypes.byref(need), None))
+        self.workspace = _workspace(need.value, indexes[0]["keys"].data.device)
+        self._keys = [spec["keys"] for spec in indexes]  # keep inputs alive
+        g = ctypes.c_void_p()
+        _check("ckey_graph_create", _lib.ckey_graph_create(self._descs, len(indexes),
+                                                           ctypes.byref(self._so), _ptr(self.workspace),
+                                                           self.workspace.numel(), ctypes.byref(g)))
+        self._g = g
+
+    def launch(self, stream=None):
+        _check("ckey_graph_launch", _lib.ckey_graph_launch(self._g, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_g", None):
+            _lib.ckey_graph_destroy(self._g)
+            self._g = None
+
+
+def ckey_tune_index(spec, candidates, stream=None):
+    """Time one rebuild of index ``spec`` per candidate option dict on the
+    device; returns (index of the fastest, list of times in ms)."""
+    descs, _outs, hold = _build_descs([spec])
+    copts = (ckey_sort_opts * len(candidates))(*[_opts(**c) for c in candidates])
+    need = 0
+    for c in candidates:
+        d1, _, _h = _build_descs([dict(spec, opts=c)])
+        so = _opts()
+        n1 = ctypes.c_size_t(0)
+        _check("ckey_rebuild_index", _lib.ckey_rebuild_index(d1, 1, ctypes.byref(so), None,
+                                                             ctypes.byref(n1), None))
+        need = max(need, n1.value)
+    ws = _workspace(need, spec["keys"].data.device)
+    best = ctypes.c_uint32(0)
+    times = (ctypes.c_float * len(candidates))()
+    _check("ckey_tune_index", _lib.ckey_tune_index(descs, copts, len(candidates), _ptr(ws), ws.numel(),
+                                                   _stream(stream), ctypes.byref(best), times))
+    return best.value, list(times)
 
 
 def as_u64(t):

@@ -2,6 +2,7 @@
 // layout on the host; all per-key work is enqueued as HIP kernels.
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -78,6 +79,109 @@ ckey_status sort_dispatch(const ckey_sort_opts *o, uint64_t *ck, uint32_t words,
         return radix_sort(ck, n, words, nbits, rid, n, digit_bits_of(o), 0, flags, ws, st);
     return learned_sort(ck, words, nbits, rid, n, m == CKEY_SORT_LEARNED ? 1 : 0, o->model,
                         o->bucket_log2, flags, ws, st);
+}
+
+struct IndexPlan {
+    std::vector<uint8_t> bm;  // bitmap used (all ones for a first build)
+    uint32_t nbits, words;
+    size_t off, bytes;        // this index's workspace part
+};
+
+struct RebuildPlan {
+    std::vector<IndexPlan> ix;
+    size_t total = 0;
+};
+
+ckey_status plan_rebuild(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
+                         bool real_call, RebuildPlan &plan) {
+    if (!idx || count == 0) return CKEY_ERR_INVALID;
+    plan.ix.resize(count);
+    plan.total = 0;
+    for (uint32_t x = 0; x < count; ++x) {
+        const ckey_index_desc &D = idx[x];
+        const ckey_sort_opts *o = D.opts ? D.opts : opts;
+        CKEY_TRY(check_sort_opts(o, real_call));
+        CKEY_TRY(check_keys(&D.keys));
+        if (real_call && D.keys.n > 0 && !D.perm) return CKEY_ERR_INVALID;
+        IndexPlan &P = plan.ix[x];
+        const uint32_t L = D.keys.key_bytes;
+        P.bm.assign(L, 0xFF);  // first build: every position (Sec. 4.3)
+        if (D.bitmap_in) memcpy(P.bm.data(), D.bitmap_in, L);
+        P.nbits = popcount_bitmap(P.bm.data(), L);
+        P.words = words_for(P.nbits);
+        const uint64_t n = D.keys.n;
+        size_t s = align256((L + 3) / 4 * 4);
+        if (!D.ckeys) s += align256(size_t(P.words) * n * 8);
+        s += sort_workspace(o, P.words, P.nbits, n);
+        P.bytes = s;
+        // one index: the parts share offset 0; several: each its own part
+        P.off = count == 1 ? 0 : plan.total;
+        plan.total = count == 1 ? s : plan.total + align256(s);
+    }
+    return CKEY_OK;
+}
+
+ckey_status enqueue_one(const ckey_index_desc &D, const ckey_sort_opts *o, const IndexPlan &P,
+                        uint8_t *ws, hipStream_t st) {
+    const uint32_t L = D.keys.key_bytes;
+    const uint64_t n = D.keys.n;
+    uint8_t *p = ws + P.off;
+    uint32_t *acc = reinterpret_cast<uint32_t *>(p);
+    p += align256((L + 3) / 4 * 4);
+    uint64_t *ck = D.ckeys;
+    if (!ck) {
+        ck = reinterpret_cast<uint64_t *>(p);
+        p += align256(size_t(P.words) * n * 8);
+    }
+    uint32_t *flags = D.flags ? D.flags : (o ? o->flags : nullptr);
+    CKEY_TRY(compress_launch(key_src(&D.keys), P.bm.data(), ck, P.words, D.perm, flags, st));
+    CKEY_TRY(sort_dispatch(o, ck, P.words, P.nbits, D.perm, n, flags, p, st));
+    if (D.bitmap_out || D.pair_pos) {
+        CKEY_TRY(fill_u32(acc, (L + 3) / 4, 0, st));
+        CKEY_TRY(refine_launch(ck, P.words, n, P.bm.data(), L, acc, D.pair_pos, flags, st));
+        if (D.bitmap_out) CKEY_TRY(bitmap_finalize(acc, D.bitmap_out, L, st));
+    }
+    return CKEY_OK;
+}
+
+// Streams and events for fanning a table's indexes out from the caller's
+// stream (created once, default priority, kept for the process lifetime).
+constexpr int kForkStreams = 8;
+std::mutex g_fork_mu;
+hipStream_t g_fork[kForkStreams];
+hipEvent_t g_fork_ev[kForkStreams + 1];
+int g_fork_dev = -1;
+
+ckey_status fork_resources() {
+    int dev = 0;
+    CKEY_HIP_TRY(hipGetDevice(&dev));
+    if (g_fork_dev == dev) return CKEY_OK;
+    if (g_fork_dev >= 0) return CKEY_ERR_UNSUPPORTED;  // one device per process
+    for (int i = 0; i < kForkStreams; ++i)
+        CKEY_HIP_TRY(hipStreamCreateWithFlags(&g_fork[i], hipStreamNonBlocking));
+    for (int i = 0; i <= kForkStreams; ++i)
+        CKEY_HIP_TRY(hipEventCreateWithFlags(&g_fork_ev[i], hipEventDisableTiming));
+    g_fork_dev = dev;
+    return CKEY_OK;
+}
+
+ckey_status enqueue_rebuild(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
+                            const RebuildPlan &plan, void *ws, hipStream_t st) {
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    if (count == 1) return enqueue_one(idx[0], idx[0].opts ? idx[0].opts : opts, plan.ix[0], w8, st);
+    std::lock_guard<std::mutex> g(g_fork_mu);
+    CKEY_TRY(fork_resources());
+    CKEY_HIP_TRY(hipEventRecord(g_fork_ev[kForkStreams], st));
+    const int ns = int(count < uint32_t(kForkStreams) ? count : kForkStreams);
+    for (int i = 0; i < ns; ++i) CKEY_HIP_TRY(hipStreamWaitEvent(g_fork[i], g_fork_ev[kForkStreams], 0));
+    for (uint32_t x = 0; x < count; ++x)
+        CKEY_TRY(enqueue_one(idx[x], idx[x].opts ? idx[x].opts : opts, plan.ix[x], w8,
+                             g_fork[x % kForkStreams]));
+    for (int i = 0; i < ns; ++i) {
+        CKEY_HIP_TRY(hipEventRecord(g_fork_ev[i], g_fork[i]));
+        CKEY_HIP_TRY(hipStreamWaitEvent(st, g_fork_ev[i], 0));
+    }
+    return CKEY_OK;
 }
 
 }  // namespace
@@ -161,55 +265,106 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *ws, size_t *ws_bytes,
                                void *stream) {
-    if (!idx || count == 0) return CKEY_ERR_INVALID;
-    CKEY_TRY(check_sort_opts(opts, ws != nullptr));
-    // Per-index plan and workspace; indexes run one after another and share it.
-    size_t need = 0;
-    std::vector<std::vector<uint8_t>> bms(count);
-    for (uint32_t x = 0; x < count; ++x) {
-        const ckey_index_desc &D = idx[x];
-        CKEY_TRY(check_keys(&D.keys));
-        if (ws && D.keys.n > 0 && !D.perm) return CKEY_ERR_INVALID;
-        const uint32_t L = D.keys.key_bytes;
-        bms[x].assign(L, 0xFF);  // first build: every position (Sec. 4.3)
-        if (D.bitmap_in) memcpy(bms[x].data(), D.bitmap_in, L);
-        const uint32_t nb = popcount_bitmap(bms[x].data(), L);
-        const uint32_t w = words_for(nb);
-        const uint64_t n = D.keys.n;
-        size_t s = align256((L + 3) / 4 * 4);
-        if (!D.ckeys) s += align256(size_t(w) * n * 8);
-        s += sort_workspace(opts, w, nb, n);
-        if (s > need) need = s;
-    }
+    if (!ws_bytes) return CKEY_ERR_INVALID;
+    RebuildPlan plan;
+    CKEY_TRY(plan_rebuild(idx, count, opts, ws != nullptr, plan));
     bool query;
-    CKEY_TRY(ws_check(ws, ws_bytes, need, query));
+    CKEY_TRY(ws_check(ws, ws_bytes, plan.total, query));
     if (query) return CKEY_OK;
-    hipStream_t st = as_stream(stream);
+    return enqueue_rebuild(idx, count, opts, plan, ws, as_stream(stream));
+}
+
+struct ckey_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
+                              void *ws, size_t ws_bytes, ckey_graph **out) {
+    if (!out || !ws) return CKEY_ERR_INVALID;
+    RebuildPlan plan;
+    CKEY_TRY(plan_rebuild(idx, count, opts, true, plan));
     for (uint32_t x = 0; x < count; ++x) {
-        const ckey_index_desc &D = idx[x];
-        const uint32_t L = D.keys.key_bytes;
-        const uint8_t *bm = bms[x].data();
-        const uint32_t nb = popcount_bitmap(bm, L);
-        const uint32_t w = words_for(nb);
-        const uint64_t n = D.keys.n;
-        uint8_t *p = static_cast<uint8_t *>(ws);
-        uint32_t *acc = reinterpret_cast<uint32_t *>(p);
-        p += align256((L + 3) / 4 * 4);
-        uint64_t *ck = D.ckeys;
-        if (!ck) {
-            ck = reinterpret_cast<uint64_t *>(p);
-            p += align256(size_t(w) * n * 8);
+        const ckey_sort_opts *o = idx[x].opts ? idx[x].opts : opts;
+        if (method_of(o) != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    }
+    if (ws_bytes < plan.total) return CKEY_ERR_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return CKEY_ERR_INVALID;
+    hipStream_t cs = nullptr;
+    CKEY_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    ckey_status st = CKEY_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return CKEY_ERR_HIP;
+    }
+    st = enqueue_rebuild(idx, count, opts, plan, ws, cs);
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (st != CKEY_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != CKEY_OK ? st : CKEY_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return CKEY_ERR_HIP;
+    }
+    *out = new ckey_graph{g, ex};
+    return CKEY_OK;
+}
+
+ckey_status ckey_graph_launch(ckey_graph *g, void *stream) {
+    if (!g) return CKEY_ERR_INVALID;
+    CKEY_HIP_TRY(hipGraphLaunch(g->exec, as_stream(stream)));
+    return CKEY_OK;
+}
+
+ckey_status ckey_graph_destroy(ckey_graph *g) {
+    if (!g) return CKEY_OK;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return CKEY_OK;
+}
+
+ckey_status ckey_tune_index(const ckey_index_desc *idx, const ckey_sort_opts *cand, uint32_t ncand,
+                            void *ws, size_t ws_bytes, void *stream, uint32_t *best,
+                            float *times_ms) {
+    if (!idx || !cand || ncand == 0 || !best || !ws) return CKEY_ERR_INVALID;
+    hipStream_t st = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CKEY_HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CKEY_ERR_HIP;
+    }
+    ckey_status status = CKEY_OK;
+    float best_ms = 0;
+    for (uint32_t c = 0; c < ncand && status == CKEY_OK; ++c) {
+        ckey_index_desc d = *idx;
+        d.opts = &cand[c];
+        size_t need = ws_bytes;
+        status = ckey_rebuild_index(&d, 1, nullptr, ws, &need, stream);  // warm-up
+        if (status != CKEY_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { status = CKEY_ERR_HIP; break; }
+        status = ckey_rebuild_index(&d, 1, nullptr, ws, &need, stream);
+        if (status != CKEY_OK) break;
+        float ms = 0;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            status = CKEY_ERR_HIP;
+            break;
         }
-        uint32_t *flags = D.flags ? D.flags : (opts ? opts->flags : nullptr);
-        CKEY_TRY(compress_launch(key_src(&D.keys), bm, ck, w, D.perm, flags, st));
-        CKEY_TRY(sort_dispatch(opts, ck, w, nb, D.perm, n, flags, p, st));
-        if (D.bitmap_out || D.pair_pos) {
-            CKEY_TRY(fill_u32(acc, (L + 3) / 4, 0, st));
-            CKEY_TRY(refine_launch(ck, w, n, bm, L, acc, D.pair_pos, flags, st));
-            if (D.bitmap_out) CKEY_TRY(bitmap_finalize(acc, D.bitmap_out, L, st));
+        if (times_ms) times_ms[c] = ms;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            *best = c;
         }
     }
-    return CKEY_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return status;
 }
 
 size_t ckey_cdf_model_bytes(uint32_t b_log2) { return learned_b_ok(b_log2) ? model_bytes(b_log2) : 0; }

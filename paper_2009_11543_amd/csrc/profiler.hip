@@ -55,6 +55,8 @@ __global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src
 int prof_begin(hipStream_t st, const char *name) {
     std::lock_guard<std::mutex> g(g_mu);
     if (!g_on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     Rec r{name, take_event(), take_event()};
     if (!r.a || !r.b) return -1;
     (void)hipEventRecord(r.a, st);

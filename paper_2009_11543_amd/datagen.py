@@ -119,3 +119,82 @@ def pack_varlen(rows, lengths):
     np.cumsum(lengths, out=offsets[1:])
     mask = np.arange(rows.shape[1])[None, :] < lengths[:, None]
     return np.ascontiguousarray(rows[mask]), offsets
+
+
+def _title_vocab(rng, size=50000):
+    """Unique [a-z]{2..12} words, first letter capitalised: (size, 12) bytes + lengths."""
+    out, lens, seen = [], [], set()
+    while len(out) < size:
+        m = 2 * (size - len(out)) + 100
+        L = rng.integers(2, 13, m)
+        chars = rng.integers(ord("a"), ord("z") + 1, (m, 12), dtype=np.uint8)
+        for i in range(m):
+            w = bytes(chars[i, : L[i]])
+            if w not in seen:
+                seen.add(w)
+                out.append(chars[i].copy())
+                lens.append(L[i])
+                if len(out) == size:
+                    break
+    vocab = np.stack(out)
+    vocab[:, 0] -= 32  # capitalise
+    lens = np.array(lens, np.int64)
+    vocab[np.arange(12)[None, :] >= lens[:, None]] = 0
+    return vocab, lens
+
+
+def title_keys(n, seed, width=48, max_len=40, min_len=8, words_per_row=10, vocab_size=50000):
+    """Title-like strings: words from a seeded synthetic vocabulary chosen by
+    Zipf(1.0), joined by single spaces until at least the row's length
+    l ~ U[min_len, max_len], truncated to l, zero-padded to `width` bytes."""
+    rng = rng_for(seed)
+    vocab, vlen = _title_vocab(rng, vocab_size)
+    target = rng.integers(min_len, max_len + 1, n)
+    w_cdf = np.cumsum(np.arange(1, vocab_size + 1, dtype=np.float64) ** -1.0)
+    w_cdf /= w_cdf[-1]
+    rows = np.zeros((n, width), np.uint8)
+    flat = rows.reshape(-1)
+    start = np.zeros(n, np.int64)
+    act = np.arange(n, dtype=np.int64)  # rows still shorter than their target
+    cols = np.arange(12, dtype=np.int64)[None, :]
+    for j in range(words_per_row):
+        if act.size == 0:
+            break
+        w = np.minimum(np.searchsorted(w_cdf, rng.random(act.size), side="right"), vocab_size - 1)
+        wl = vlen[w]
+        pos = start[act][:, None] + cols                      # (a, 12) target columns
+        ok = (cols < wl[:, None]) & (pos < target[act][:, None])
+        flat[(act[:, None] * width + pos)[ok]] = vocab[w][ok]
+        sp = start[act] + wl
+        oks = sp < target[act]
+        flat[act[oks] * width + sp[oks]] = ord(" ")
+        start[act] = sp + 1
+        act = act[start[act] < target[act]]
+    # a row that ends on a space keeps it; the zero padding ends the string
+    return rows
+
+
+def table_indexes(n=1 << 24, seed=1):
+    """Eight indexes of one synthetic table (fixed-width key rows each):
+    int64 uniform; int32 Zipf(1.2) over 2^20 distinct values; a 12-byte
+    composite (int32 day in a 10-year range, int64 uniform id); 48-byte titles;
+    two int32 and two int64 uniform columns."""
+    rng = rng_for(seed)
+    i64 = lambda: rng.integers(np.iinfo(np.int64).min, np.iinfo(np.int64).max, n, dtype=np.int64,
+                               endpoint=True)
+    i32 = lambda: rng.integers(np.iinfo(np.int32).min, np.iinfo(np.int32).max, n, dtype=np.int64,
+                               endpoint=True)
+    vals = np.unique(rng.integers(0, 1 << 32, (1 << 20) + (1 << 16), dtype=np.int64))
+    vals = rng.permutation(vals)[: 1 << 20] - (1 << 31)
+    zipf_col = vals[zipf_sampler(rng, 1.2, 1 << 20, n)]
+    day = rng.integers(16436, 16436 + 3652 + 1, n)
+    return {
+        "int64": encode_i64(i64()),
+        "int32_zipf": encode_i32(zipf_col),
+        "day_id": np.ascontiguousarray(np.concatenate([encode_i32(day), encode_i64(i64())], 1)),
+        "title": title_keys(n, seed + 100),
+        "int32_a": encode_i32(i32()),
+        "int32_b": encode_i32(i32()),
+        "int64_a": encode_i64(i64()),
+        "int64_b": encode_i64(i64()),
+    }
