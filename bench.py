@@ -35,6 +35,20 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def training_rows(name, n):
+    """Rows of the same generator at seed 2 (the training rebuild)."""
+    from paper_2009_11543_amd import datagen
+    if name == "dna64_2p26":
+        return datagen.dna_window_keys(n, seed=2)
+    if name == "prefix16_2p20":
+        return datagen.uniform_prefix_keys(n, seed=2)
+    if name == "uniform32_2p28":
+        return datagen.uniform_keys(n, seed=2)
+    if name == "cluster32_2p28":
+        return datagen.cluster_keys(n, seed=2)
+    raise SystemExit(f"unknown workload {name}")
+
+
 def workload(name):
     from paper_2009_11543_amd import datagen
     if name == "dna64_2p26":
@@ -96,6 +110,56 @@ def cpu_baseline(rows_all, n_sample):
                       f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s"}
 
 
+def bench_table(args, torch, ckey, prof, dev):
+    """Rebuild of all eight indexes of a 2^24-row table (refresh with the
+    current D-bitmaps; radix sorts): eight separate calls, one batched call
+    (indexes on forked streams), and a replay of the captured graph."""
+    from paper_2009_11543_amd import datagen
+    n = 1 << 24
+    log("generating the 8-index table")
+    tab = datagen.table_indexes(n, seed=1)
+    keys = {k: ckey.DeviceKeys(torch.from_numpy(v).to(dev)) for k, v in tab.items()}
+    widths = {k: v.shape[1] for k, v in tab.items()}
+    del tab
+    first = ckey.ckey_rebuild_index([{"keys": kk, "bitmap": None} for kk in keys.values()])
+    bms = {k: o["bitmap"].cpu().numpy() for k, o in zip(keys, first)}
+    dbits = {k: ckey.ckey_plan_query(b)["nbits"] for k, b in bms.items()}
+    log(f"|D| per index: {dbits}")
+    specs = [{"keys": keys[k], "bitmap": bms[k]} for k in keys]
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    wss = [torch.empty(ckey.ckey_rebuild_index_workspace([sp]), dtype=torch.uint8, device=dev)
+           for sp in specs]
+    seq_ms = timeit(lambda: [ckey.ckey_rebuild_index([sp], workspace=w) for sp, w in zip(specs, wss)],
+                    args.steps)
+    wsb = torch.empty(ckey.ckey_rebuild_index_workspace(specs), dtype=torch.uint8, device=dev)
+    bat_ms = timeit(lambda: ckey.ckey_rebuild_index(specs, workspace=wsb), args.steps)
+    g = ckey.RebuildGraph(specs)
+    graph_ms = timeit(g.launch, args.steps)
+    for (k, _), o in zip(keys.items(), g.outs):  # refreshed bitmaps equal the first build's
+        assert np.array_equal(o["bitmap"].cpu().numpy(), bms[k]), k
+    total = 8 * n
+    out = {"metric": "table rebuild rows/s (8 indexes x 2^24 rows, D-bitmap refresh)",
+           "value": total / (graph_ms / 1e3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": graph_ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "table8_2p24", "key_bytes": widths, "nbits": dbits,
+                      "method": "radix", "launch": "graph"},
+           "sequential_calls_ms": seq_ms, "batched_call_ms": bat_ms, "graph_replay_ms": graph_ms}
+    log(f"table: sequential {seq_ms:.2f} ms, batched {bat_ms:.2f} ms, graph {graph_ms:.2f} ms")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +168,8 @@ def main():
     ap.add_argument("--workload", default="dna64_2p26")
     ap.add_argument("--method", default="auto", choices=["auto", "radix", "splitter", "learned"],
                     help="sort method for the timed steps; auto = the fastest after calibration")
-    ap.add_argument("--bucket-log2", type=int, default=14)
+    ap.add_argument("--bucket-log2", type=int, default=0,
+                    help="log2 bucket count; 0 = about 4096 rows per bucket (2^14 at 2^26 rows)")
     ap.add_argument("--train-rows", type=int, default=1 << 24)
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
@@ -123,12 +188,16 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
 
+    if args.workload.startswith("table8"):
+        return bench_table(args, torch, ckey, prof, dev)
     log(f"generating workload {args.workload}")
     rows, desc = workload(args.workload)
     n, L = rows.shape
     keys = ckey.DeviceKeys(torch.from_numpy(rows).to(dev))
     torch.cuda.synchronize()
     log(f"keys resident: n={n} L={L}")
+    if args.bucket_log2 == 0:
+        args.bucket_log2 = max(8, min(16, n.bit_length() - 1 - 12))
 
     # copy probe: achievable HBM bandwidth
     buf_a = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
@@ -178,8 +247,7 @@ def main():
     if args.method in ("auto", "splitter", "learned"):
         from paper_2009_11543_amd import datagen
         log(f"training rebuild: {args.train_rows} rows, seed 2")
-        rows_t = datagen.dna_window_keys(args.train_rows, seed=2) if args.workload == "dna64_2p26" \
-            else workload(args.workload)[0][: args.train_rows]
+        rows_t = training_rows(args.workload, min(args.train_rows, n))
         keys_t = ckey.DeviceKeys(torch.from_numpy(rows_t).to(dev))
         del rows_t
         ckt, ridt = ckey.ckey_compress(keys_t, d_bitmap)

@@ -743,9 +743,17 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     std::vector<uint32_t> ranges(2 * size_t(novf));
     CKEY_HIP_TRY(hipMemcpyAsync(ranges.data(), ovf + 1, ranges.size() * 4, hipMemcpyDeviceToHost, st));
     CKEY_HIP_TRY(hipStreamSynchronize(st));
-    for (uint32_t q = 0; q < novf; ++q) {
-        const uint32_t s0 = ranges[2 * q], c = ranges[2 * q + 1];
-        CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
+    uint64_t rows = 0;
+    for (uint32_t q = 0; q < novf; ++q) rows += ranges[2 * q + 1];
+    if (novf > 64 || rows > n / 8) {
+        // Widespread overflow (data the thresholds do not split): one radix
+        // sort of everything by (key, row id) -- exact from any arrangement.
+        CKEY_TRY(radix_sort(ck, n, words, nbits, rid, n, 8, 32, flags, ws, st));
+    } else {
+        for (uint32_t q = 0; q < novf; ++q) {
+            const uint32_t s0 = ranges[2 * q], c = ranges[2 * q + 1];
+            CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
+        }
     }
     if (flags) CKEY_TRY(fill_flag_or(flags, CKEY_FLAG_BUCKET_OVERFLOW, st));
     return CKEY_OK;

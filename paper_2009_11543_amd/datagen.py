@@ -85,7 +85,7 @@ def dna_window_keys(n=1 << 26, seed=1, key_bytes=64, seq_len=1 << 27, p_mut=0.01
     return keys
 
 
-def uniform_keys(n=1 << 28, seed=1, key_bytes=32):
+def uniform_keys(n=1 << 28, seed=1, key_bytes=32):  # noqa: D401
     """Uniform random bytes, ``key_bytes`` per row."""
     rng = rng_for(seed)
     return np.frombuffer(rng.bytes(n * key_bytes), np.uint8).reshape(n, key_bytes).copy()
