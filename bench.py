@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "compress+sort keys/s & HBM GB/s at 2^26 keys vs plain GPU full-key sort"
-KERNEL_BYTES = ("compress", "hist", "onesweep", "assign_learned", "assign_splitter",
-                "bucket_pass", "bucket_sort")
+KERNEL_BYTES = ("compress", "compress_bucket", "hist", "onesweep", "assign_learned",
+                "assign_splitter", "bucket_pass", "bucket_sort")
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -274,8 +274,8 @@ def main():
                      dtype=torch.uint8, device=dev)
 
     def step(m):
-        ckey.ckey_compress(keys, d_bitmap, out=ck, rowids=rid)
-        ckey.ckey_sort(ck, nbits, rid, workspace=ws, flags=flags, **method_opts[m])
+        ckey.ckey_compress_sort(keys, d_bitmap, out=ck, rowids=rid, workspace=ws, flags=flags,
+                                **method_opts[m])
 
     def timed(m, steps):
         prof.on()
@@ -316,7 +316,8 @@ def main():
     # Algorithmic bytes per key of each kernel.
     key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
     rec = 8 * w + 4
-    per_key = {"compress": key_bytes_read + rec, "hist": 8 * w, "onesweep": 2 * rec,
+    per_key = {"compress": key_bytes_read + rec, "compress_bucket": key_bytes_read + rec + 2,
+               "hist": 8 * w, "onesweep": 2 * rec,
                "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_pass": 2 * rec + 3,
                "bucket_sort": 8 + 2 * rec}
     step_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
@@ -325,7 +326,7 @@ def main():
     achieved = dom_bytes / (kern[dom]["ms_per_launch"] / 1e3) / 1e9
     src = os.path.join(ROOT, "paper_2009_11543_amd", "csrc",
                        "k_radix.hip" if dom in ("onesweep", "hist", "bucket_pass") else
-                       "k_compress.hip" if dom == "compress" else "k_learned.hip")
+                       "k_compress.hip" if dom in ("compress", "compress_bucket") else "k_learned.hip")
     traffic = traffic_for(dom, args.workload, src)
 
     out = {

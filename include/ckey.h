@@ -128,6 +128,17 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
                       uint64_t n, const ckey_sort_opts *opts, void *workspace,
                       size_t *workspace_bytes, void *stream);
 
+/* Compress and sort in one call (Sec. 5 steps 2-3: extract the compressed
+ * keys, sort the (compressed key, row id) pairs): ckeys (device, words x n)
+ * and rowids (device uint32[n]) receive the sorted compressed keys and the row
+ * ids in full-key order.  Arguments as for ckey_compress and ckey_sort.  With
+ * a bucketing method and fixed-width keys, each key's bucket is found while
+ * the key is compressed (one pass over the keys instead of two).  Needs a
+ * workspace (the size ckey_sort needs). */
+ckey_status ckey_compress_sort(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
+                               uint32_t words, uint32_t *rowids, const ckey_sort_opts *opts,
+                               void *workspace, size_t *workspace_bytes, void *stream);
+
 /* One index to rebuild (Sec. 5 steps 2-3 and the DS-metadata refresh of Sec. 4.3). */
 typedef struct {
     ckey_keys keys;

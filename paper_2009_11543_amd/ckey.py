@@ -60,6 +60,8 @@ def _load():
     lib.ckey_sort.argtypes = [P, U32, U32, P, U64, ctypes.POINTER(ckey_sort_opts), P, SZP, P]
     lib.ckey_rebuild_index.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
                                        ctypes.POINTER(ckey_sort_opts), P, SZP, P]
+    lib.ckey_compress_sort.argtypes = [ctypes.POINTER(ckey_keys), P, P, U32, P,
+                                       ctypes.POINTER(ckey_sort_opts), P, SZP, P]
     lib.ckey_graph_create.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
                                       ctypes.POINTER(ckey_sort_opts), P, ctypes.c_size_t,
                                       ctypes.POINTER(ctypes.c_void_p)]
@@ -69,7 +71,7 @@ def _load():
                                     U32, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_float)]
     for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
-               "ckey_rebuild_index", "ckey_graph_create", "ckey_graph_launch", "ckey_graph_destroy",
+               "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch", "ckey_graph_destroy",
                "ckey_tune_index"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
@@ -194,6 +196,30 @@ def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=None, model=None, fl
     return ckey_sort_opts(method, digit_bits, bucket_log2, 0,
                           None if model is None else model.handle,
                           None if flags is None else flags.data_ptr())
+
+
+def ckey_compress_sort(keys, bitmap, out=None, rowids=None, words=None, workspace=None,
+                       stream=None, **opts):
+    """Compress and sort in one call: (sorted compressed keys (words, n) int64,
+    row ids in full-key order int32)."""
+    bm, p = _host_bitmap(bitmap)
+    plan = ckey_plan_query(bm)
+    w = plan["words"] if words is None else words
+    dev = keys.data.device
+    ck = torch.empty((w, keys.n), dtype=torch.int64, device=dev) if out is None else out
+    rid = torch.empty(keys.n, dtype=torch.int32, device=dev) if rowids is None else rowids
+    ks = keys.c_struct()
+    o = _opts(**opts)
+    need = ctypes.c_size_t(0)
+    _check("ckey_compress_sort", _lib.ckey_compress_sort(ctypes.byref(ks), p, None, w, None,
+                                                         ctypes.byref(o), None, ctypes.byref(need),
+                                                         None))
+    ws = _workspace(need.value, dev) if workspace is None else workspace
+    need = ctypes.c_size_t(ws.numel())
+    _check("ckey_compress_sort", _lib.ckey_compress_sort(ctypes.byref(ks), p, _ptr(ck), w, _ptr(rid),
+                                                         ctypes.byref(o), _ptr(ws), ctypes.byref(need),
+                                                         _stream(stream)))
+    return ck, rid
 
 
 def ckey_sort_workspace(words, nbits, n, **opts):

@@ -81,6 +81,22 @@ ckey_status sort_dispatch(const ckey_sort_opts *o, uint64_t *ck, uint32_t words,
                         o->bucket_log2, flags, ws, st);
 }
 
+// Compress then sort; for the bucketing methods the bucket of each key is
+// found while it is compressed when the keys allow the fused kernel.
+ckey_status compress_sort_dispatch(const ckey_sort_opts *o, const KeySrc &k, const uint8_t *bm,
+                                   uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid,
+                                   uint32_t *flags, void *ws, hipStream_t st) {
+    const uint32_t m = method_of(o);
+    if (m != CKEY_SORT_RADIX) {
+        const ckey_status s = compress_learned_sort(k, bm, ck, words, nbits, rid,
+                                                    m == CKEY_SORT_LEARNED ? 1 : 0, o->model,
+                                                    o->bucket_log2, flags, ws, st);
+        if (s != CKEY_ERR_UNSUPPORTED) return s;
+    }
+    CKEY_TRY(compress_launch(k, bm, ck, words, rid, flags, st));
+    return sort_dispatch(o, ck, words, nbits, rid, k.n, flags, ws, st);
+}
+
 struct IndexPlan {
     std::vector<uint8_t> bm;  // bitmap used (all ones for a first build)
     uint32_t nbits, words;
@@ -134,8 +150,8 @@ ckey_status enqueue_one(const ckey_index_desc &D, const ckey_sort_opts *o, const
         p += align256(size_t(P.words) * n * 8);
     }
     uint32_t *flags = D.flags ? D.flags : (o ? o->flags : nullptr);
-    CKEY_TRY(compress_launch(key_src(&D.keys), P.bm.data(), ck, P.words, D.perm, flags, st));
-    CKEY_TRY(sort_dispatch(o, ck, P.words, P.nbits, D.perm, n, flags, p, st));
+    CKEY_TRY(compress_sort_dispatch(o, key_src(&D.keys), P.bm.data(), ck, P.words, P.nbits, D.perm,
+                                    flags, p, st));
     if (D.bitmap_out || D.pair_pos) {
         CKEY_TRY(fill_u32(acc, (L + 3) / 4, 0, st));
         CKEY_TRY(refine_launch(ck, P.words, n, P.bm.data(), L, acc, D.pair_pos, flags, st));
@@ -260,6 +276,22 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
     if (n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
     return sort_dispatch(opts, ckeys, words, nbits, rowids, n, opts ? opts->flags : nullptr, ws,
                          as_stream(stream));
+}
+
+ckey_status ckey_compress_sort(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
+                               uint32_t words, uint32_t *rowids, const ckey_sort_opts *opts,
+                               void *ws, size_t *ws_bytes, void *stream) {
+    CKEY_TRY(check_keys(keys));
+    if (!bitmap) return CKEY_ERR_INVALID;
+    const uint32_t nbits = popcount_bitmap(bitmap, keys->key_bytes);
+    if (words < words_for(nbits)) return CKEY_ERR_INVALID;
+    CKEY_TRY(check_sort_opts(opts, ws != nullptr));
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, sort_workspace(opts, words, nbits, keys->n), query));
+    if (query) return CKEY_OK;
+    if (keys->n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
+    return compress_sort_dispatch(opts, key_src(keys), bitmap, ckeys, words, nbits, rowids,
+                                  opts ? opts->flags : nullptr, ws, as_stream(stream));
 }
 
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,

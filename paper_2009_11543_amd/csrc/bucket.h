@@ -1,0 +1,197 @@
+// Bucket assignment of a first compressed word x: the b with
+// T[b] <= x < T[b+1] for a sorted threshold table T (T[0] = 0).  Used by the
+// stand-alone assignment kernel and by compression fused with assignment.
+//   splitter: binary search of a 1-in-S sample of T held in LDS, then of T;
+//   learned:  a 4 -> 64 -> 1 ReLU MLP guesses b, then an exponential-then-
+//             binary search of T from the guess finds it exactly.
+#pragma once
+
+#include "internal.h"
+
+namespace ckey {
+
+constexpr int kH = 64;                         // hidden units
+constexpr int kBucketWG = 1024;                // threads per assigning workgroup
+constexpr uint32_t kBucketKeysPerWG = 65535;   // keeps packed 16-bit LDS counters exact
+
+struct BucketArgs {
+    const float *p;        // MLP parameters (learned)
+    const uint64_t *T;     // thresholds
+    uint32_t B, S;         // bucket count, splitter sample stride
+    uint16_t *bid;         // bucket ids (u16) or null
+    uint32_t *bid32;       // bucket ids (u32) or null
+    uint32_t *pred;        // network guesses or null (learned)
+    uint32_t *hist;        // global bucket histogram (added to) or null
+};
+
+// Splitter sample stride.  S == 1 means the top 32 bits of every threshold are
+// held in LDS (B <= 2^14: 64 KB) and the search runs in LDS, reading T itself
+// only where the top halves tie.
+inline uint32_t splitter_stride(uint32_t B) {
+    if (B <= (1u << 14)) return 1;
+    return B / 16 > 2048 ? B / 2048 : 16;
+}
+
+inline size_t bucket_lds_bytes(const BucketArgs &a, int amode) {
+    const size_t sample = a.S == 1 ? size_t(a.B) * 4 : size_t(a.B / a.S) * 8;
+    return size_t(a.B / 2) * 4 + (amode == 0 ? sample : 0) + 16;
+}
+
+// Dynamic LDS above 64 KB (B = 2^16) needs the kernel attribute raised once.
+inline void set_bucket_lds_limit(const void *fn) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+__device__ __forceinline__ void mlp_features(uint64_t x, float f[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f[j] = float(uint32_t(x >> (48 - 16 * j)) & 0xFFFFu) * (1.0f / 65536.0f);
+}
+
+__device__ __forceinline__ float mlp_eval(const float *__restrict__ p, const float f[4]) {
+    float y = p[6 * kH];
+#pragma unroll 16
+    for (int k = 0; k < kH; ++k) {
+        float a = p[4 * kH + k];
+        a = fmaf(p[4 * k + 0], f[0], a);
+        a = fmaf(p[4 * k + 1], f[1], a);
+        a = fmaf(p[4 * k + 2], f[2], a);
+        a = fmaf(p[4 * k + 3], f[3], a);
+        y = fmaf(p[5 * kH + k], fmaxf(a, 0.0f), y);
+    }
+    return y;
+}
+
+__device__ __forceinline__ uint32_t predict_bucket(const float *__restrict__ p, uint64_t x, uint32_t B) {
+    float f[4];
+    mlp_features(x, f);
+    const float y = mlp_eval(p, f) * float(B);
+    if (!(y > 0.0f)) return 0;  // also maps NaN to 0
+    if (y >= float(B)) return B - 1;
+    return uint32_t(y);
+}
+
+// Exact bucket from a start guess: exponential search outward, then binary.
+__device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ T, uint32_t B,
+                                                   uint64_t x, uint32_t pb, uint32_t &probes) {
+    uint32_t lo, hi;  // T[lo] <= x and (hi == B or T[hi] > x)
+    ++probes;
+    if (T[pb] <= x) {
+        lo = pb;
+        hi = B;
+        for (uint32_t step = 1;; step <<= 1) {
+            const uint32_t j = lo + step;
+            if (j >= B) break;
+            ++probes;
+            if (T[j] > x) { hi = j; break; }
+            lo = j;
+        }
+    } else {
+        hi = pb;
+        lo = 0;  // T[0] = 0 <= x
+        for (uint32_t step = 1;; step <<= 1) {
+            if (hi <= step) break;
+            const uint32_t j = hi - step;
+            ++probes;
+            if (T[j] <= x) { lo = j; break; }
+            hi = j;
+        }
+    }
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        ++probes;
+        if (T[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// LDS layout: B/2 packed 16-bit counters, then (splitter) the B/S sample of T.
+template <int AMODE>
+__device__ __forceinline__ void bucket_lds_init(const BucketArgs &a, uint32_t *s) {
+    if (a.hist)
+        for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) s[t] = 0;
+    if (AMODE == 0) {
+        if (a.S == 1) {
+            uint32_t *th = s + a.B / 2;
+            for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = uint32_t(a.T[t] >> 32);
+        } else {
+            uint64_t *ts = reinterpret_cast<uint64_t *>(s + a.B / 2);
+            for (uint32_t t = threadIdx.x; t < a.B / a.S; t += blockDim.x) ts[t] = a.T[uint64_t(t) * a.S];
+        }
+    }
+}
+
+template <int AMODE>
+__device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_t *s, uint64_t x,
+                                              uint32_t &probes, uint32_t &guess) {
+    if (AMODE == 1) {
+        guess = predict_bucket(a.p, x, a.B);
+        return correct_bucket(a.T, a.B, x, guess, probes);
+    }
+    if (a.S == 1) {  // every threshold's top half in LDS
+        const uint32_t *th = s + a.B / 2;
+        const uint32_t xh = uint32_t(x >> 32);
+        uint32_t lo = 0, hi = a.B;  // T[lo] <= x < T[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            const uint32_t t = th[mid];
+            bool le = t < xh;
+            if (t == xh) {  // top halves tie: compare the whole threshold
+                ++probes;
+                le = a.T[mid] <= x;
+            }
+            if (le) lo = mid; else hi = mid;
+        }
+        guess = lo;
+        return lo;
+    }
+    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s + a.B / 2);
+    uint32_t lo = 0, hi = a.B / a.S;  // ts[lo] <= x < ts[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ts[mid] <= x) lo = mid; else hi = mid;
+    }
+    uint32_t l2 = lo * a.S, h2 = min(a.B, (lo + 1) * a.S);
+    while (h2 - l2 > 1) {
+        const uint32_t mid = (l2 + h2) >> 1;
+        ++probes;
+        if (a.T[mid] <= x) l2 = mid; else h2 = mid;
+    }
+    guess = l2;
+    return l2;
+}
+
+template <int AMODE>
+__device__ __forceinline__ uint32_t bucket_assign_one(const BucketArgs &a, uint32_t *s, uint64_t x,
+                                                      uint64_t i, uint32_t &probes, uint32_t &err) {
+    uint32_t guess;
+    const uint32_t b = bucket_of<AMODE>(a, s, x, probes, guess);
+    err += b > guess ? b - guess : guess - b;
+    if (a.bid) a.bid[i] = uint16_t(b);
+    if (a.bid32) a.bid32[i] = b;
+    if (AMODE == 1 && a.pred) a.pred[i] = guess;
+    if (a.hist) atomicAdd(&s[b >> 1], 1u << (16 * (b & 1)));
+    return b;
+}
+
+template <int AMODE>
+__device__ __forceinline__ void bucket_assign_one(const BucketArgs &a, uint32_t *s, uint64_t x, uint64_t i) {
+    uint32_t probes = 0, err = 0;
+    (void)bucket_assign_one<AMODE>(a, s, x, i, probes, err);
+}
+
+__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, const uint32_t *s) {
+    if (!a.hist) return;
+    for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
+        const uint32_t v = s[t];
+        if (v & 0xFFFFu) atomicAdd(&a.hist[2 * t], v & 0xFFFFu);
+        if (v >> 16) atomicAdd(&a.hist[2 * t + 1], v >> 16);
+    }
+}
+
+// Compression fused with bucket assignment (k_compress.hip).  Fixed-width keys
+// whose compression fits one launch only (else CKEY_ERR_UNSUPPORTED).
+ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ckeys,
+                                   uint32_t words, uint32_t *rowids, uint32_t *flags, int amode,
+                                   const BucketArgs &ba, hipStream_t st);
+
+}  // namespace ckey

@@ -115,8 +115,11 @@ ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nb
 // one-sweep passes; the aux array is read, not reordered), moving the words
 // and row ids; the result is back in ck/rid.
 size_t aux_sort_workspace(uint32_t words, uint64_t n);
+// aux_full_hist (optional): histogram over all 2^aux_bits values, from which
+// the passes' histograms are derived instead of re-reading aux.
 ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
-                     uint32_t aux_bits, uint32_t *flags, void *ws, hipStream_t st);
+                     uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags, void *ws,
+                     hipStream_t st);
 
 // OR a value into a device flags word (a kernel, so it is stream-ordered).
 ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st);
@@ -128,6 +131,13 @@ size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_
 ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
                          int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
                          hipStream_t st);
+// Compression and bucketing sort in one pass over the keys: the bucket of
+// each key is found while it is compressed.  CKEY_ERR_UNSUPPORTED when the
+// keys do not allow the fused kernel (then compress and sort separately).
+ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ck,
+                                  uint32_t words, uint32_t nbits, uint32_t *rid, int mode,
+                                  const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
+                                  hipStream_t st);
 size_t model_bytes(uint32_t b_log2);
 ckey_status model_init(void *model, uint64_t seed, hipStream_t st);
 ckey_status model_thresholds(void *model, uint32_t b_log2, const uint64_t *sorted, uint64_t m,

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "bucket.h"
 #include "internal.h"
 
 namespace ckey {
@@ -63,14 +64,16 @@ struct SrcWord {
 
 // Gather of one key's D bits into its output words, for a loader that
 // fills the four big-endian words of a 16-byte chunk.
+// Returns output word 0 when this launch writes it (else 0).
 template <typename Loader>
-__device__ __forceinline__ void compress_key(const CompressPlan &plan, const Loader &ld,
-                                             uint64_t *__restrict__ ck, uint64_t n, uint64_t i) {
-    uint64_t acc = 0;
+__device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const Loader &ld,
+                                                 uint64_t *__restrict__ ck, uint64_t n, uint64_t i) {
+    uint64_t acc = 0, w0 = 0;
     uint32_t kw = plan.kw_init;
     // Stores outside [word_begin, word_end) belong to a neighbouring launch.
     auto store = [&](uint32_t kk, uint64_t val) {
         if (kk >= plan.word_begin && kk < plan.word_end) ck[uint64_t(kk) * n + i] = val;
+        if (kk == 0) w0 = val;
     };
     // Chunks are taken four at a time: all loads of a group are issued before
     // any of its output stores, so they overlap.
@@ -118,6 +121,7 @@ __device__ __forceinline__ void compress_key(const CompressPlan &plan, const Loa
     }
     store(kw, acc);
     for (uint32_t kk = plan.word_end; kk < plan.zero_end; ++kk) ck[uint64_t(kk) * n + i] = 0;
+    return w0;
 }
 
 template <int MODE>
@@ -250,7 +254,97 @@ __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan pla
     if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
 }
 
+// Compression fused with bucket assignment: each workgroup compresses a
+// range of up to kBucketKeysPerWG keys (grid-stride over its threads), finds
+// each key's bucket from its first compressed word while it is in registers,
+// and keeps a packed 16-bit bucket histogram in LDS.
+template <int MODE, int AMODE>
+__global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, CompressPlan plan,
+                                                               uint64_t *__restrict__ ck,
+                                                               uint32_t *__restrict__ rowids,
+                                                               BucketArgs ba) {
+    extern __shared__ uint32_t s_dyn[];
+    bucket_lds_init<AMODE>(ba, s_dyn);
+    __syncthreads();
+    const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
+    const uint64_t i1 = min<uint64_t>(k.n, i0 + kBucketKeysPerWG);
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG) {
+        GlobalLoader<MODE> ld{k.bytes + i * k.stride, k.L};
+        const uint64_t w0 = compress_key(plan, ld, ck, k.n, i);
+        if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
+        bucket_assign_one<AMODE>(ba, s_dyn, w0, i);
+    }
+    __syncthreads();
+    bucket_lds_flush(ba, s_dyn);
+}
+
 }  // namespace
+
+ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
+                                   uint32_t *rowids, uint32_t *flags, int amode, const BucketArgs &ba,
+                                   hipStream_t st) {
+    // Fused only for fixed-width keys whose compression fits one launch.
+    const int mode = load_mode(k);
+    std::vector<SrcWord> src;
+    uint32_t nbits = 0, nch = 0, lc = UINT32_MAX;
+    for (uint32_t j = 0; j < (k.L + 3) / 4; ++j) {
+        uint32_t m = 0;
+        for (uint32_t t = 0; t < 4; ++t) m = (m << 8) | (4 * j + t < k.L ? bm[4 * j + t] : 0u);
+        if (!m) continue;
+        src.push_back({j, m, nbits});
+        nbits += __builtin_popcount(m);
+        if (j / 4 != lc) { ++nch; lc = j / 4; }
+    }
+    const uint32_t w = nbits ? (nbits + 63) / 64 : 1;
+    if (k.offsets || nch > uint32_t(kMaxChunks) || words < w) return CKEY_ERR_UNSUPPORTED;
+    if (k.n == 0) return CKEY_OK;
+    CompressPlan plan{};
+    plan.write_rowids = 1;
+    plan.word_begin = 0;
+    plan.word_end = w;
+    plan.zero_end = words;
+    plan.kw_init = 0;
+    uint32_t cidx = 0;
+    lc = UINT32_MAX;
+    for (const SrcWord &sw : src) {
+        const uint32_t cb = sw.j / 4, q = sw.j % 4;
+        if (cb != lc) {
+            plan.chunk[cidx++] = cb;
+            lc = cb;
+        }
+        WordOp &op = plan.op[4 * (cidx - 1) + q];
+        op.m = sw.m;
+        compress_masks(sw.m, op.mv);
+        op.pc = __builtin_popcount(sw.m);
+        op.off = sw.off;
+    }
+    plan.n_chunks = cidx;
+    const uint32_t blocks = uint32_t((k.n + kBucketKeysPerWG - 1) / kBucketKeysPerWG);
+    const size_t lds = bucket_lds_bytes(ba, amode);
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1>));
+    const int pr_ = prof_begin(st, "compress_bucket");
+#define CKEY_LAUNCH_CB(M)                                                                              \
+    if (amode)                                                                                         \
+        hipLaunchKernelGGL((k_compress_bucket<M, 1>), dim3(blocks), dim3(kBucketWG), lds, st, k, plan, \
+                           ck, rowids, ba);                                                            \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_compress_bucket<M, 0>), dim3(blocks), dim3(kBucketWG), lds, st, k, plan, \
+                           ck, rowids, ba);
+    switch (mode) {
+        case kLoad16: CKEY_LAUNCH_CB(kLoad16) break;
+        case kLoad4: CKEY_LAUNCH_CB(kLoad4) break;
+        default: CKEY_LAUNCH_CB(kLoadBytes) break;
+    }
+#undef CKEY_LAUNCH_CB
+    prof_end(st, pr_);
+    (void)flags;
+    return launch_status();
+}
 
 ckey_status compress_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
                             uint32_t *rowids, uint32_t *flags, hipStream_t st) {

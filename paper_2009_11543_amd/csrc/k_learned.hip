@@ -26,13 +26,13 @@
 
 #include <vector>
 
+#include "bucket.h"
 #include "internal.h"
 
 namespace ckey {
 
 namespace {
 
-constexpr int kH = 64;
 constexpr int kNP = 6 * kH + 1;  // parameters
 constexpr int kNPad = 392;       // parameters + loss slot, padded
 constexpr int kLoss = kNP;       // index of the loss in a partial-sum row
@@ -49,68 +49,6 @@ inline const float *params_of(const void *model) {
 }
 inline const uint64_t *thresholds_of(const void *model) {
     return reinterpret_cast<const uint64_t *>(static_cast<const uint8_t *>(model) + kOffT);
-}
-
-__device__ __forceinline__ void features(uint64_t x, float f[4]) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) f[j] = float(uint32_t(x >> (48 - 16 * j)) & 0xFFFFu) * (1.0f / 65536.0f);
-}
-
-__device__ __forceinline__ float mlp_eval(const float *__restrict__ p, const float f[4]) {
-    float y = p[6 * kH];
-#pragma unroll 16
-    for (int k = 0; k < kH; ++k) {
-        float a = p[4 * kH + k];
-        a = fmaf(p[4 * k + 0], f[0], a);
-        a = fmaf(p[4 * k + 1], f[1], a);
-        a = fmaf(p[4 * k + 2], f[2], a);
-        a = fmaf(p[4 * k + 3], f[3], a);
-        y = fmaf(p[5 * kH + k], fmaxf(a, 0.0f), y);
-    }
-    return y;
-}
-
-__device__ __forceinline__ uint32_t predict_bucket(const float *__restrict__ p, uint64_t x, uint32_t B) {
-    float f[4];
-    features(x, f);
-    const float y = mlp_eval(p, f) * float(B);
-    if (!(y > 0.0f)) return 0;  // also maps NaN to 0
-    if (y >= float(B)) return B - 1;
-    return uint32_t(y);
-}
-
-// Exact bucket from a start guess: exponential search outward, then binary.
-__device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ T, uint32_t B,
-                                                   uint64_t x, uint32_t pb, uint32_t &probes) {
-    uint32_t lo, hi;  // T[lo] <= x and (hi == B or T[hi] > x)
-    ++probes;
-    if (T[pb] <= x) {
-        lo = pb;
-        hi = B;
-        for (uint32_t step = 1;; step <<= 1) {
-            const uint32_t j = lo + step;
-            if (j >= B) break;
-            ++probes;
-            if (T[j] > x) { hi = j; break; }
-            lo = j;
-        }
-    } else {
-        hi = pb;
-        lo = 0;  // T[0] = 0 <= x
-        for (uint32_t step = 1;; step <<= 1) {
-            if (hi <= step) break;
-            const uint32_t j = hi - step;
-            ++probes;
-            if (T[j] <= x) { lo = j; break; }
-            hi = j;
-        }
-    }
-    while (hi - lo > 1) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        ++probes;
-        if (T[mid] <= x) lo = mid; else hi = mid;
-    }
-    return lo;
 }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -175,7 +113,7 @@ __global__ __launch_bounds__(kWG) void k_mlp_grad(const float *__restrict__ p,
         const uint64_t x = valid ? prefix[i] : 0ull;
         const float t = valid ? (target ? target[i] : (float(i) + 0.5f) / float(m)) : 0.0f;
         float f[4];
-        features(x, f);
+        mlp_features(x, f);
         float h[kH];
         float y = p[6 * kH];
 #pragma unroll
@@ -252,59 +190,21 @@ __global__ __launch_bounds__(512) void k_mlp_reduce(const float *__restrict__ pa
 
 // ------------------------------------------------------- bucket assignment --
 
-// MODE 0: splitter search (LDS sample of T, then T); MODE 1: MLP prediction + correction.
+// Stand-alone assignment of first words w0[0..n) (MODE 0: splitter, 1: learned).
 template <int MODE>
-__global__ __launch_bounds__(kAssignWG) void k_bucket_assign(
-    const uint64_t *__restrict__ w0, uint64_t n, const float *__restrict__ p,
-    const uint64_t *__restrict__ T, uint32_t B, uint32_t S, uint16_t *__restrict__ bid,
-    uint32_t *__restrict__ bid32, uint32_t *__restrict__ pred, uint32_t *__restrict__ hist,
-    unsigned long long *__restrict__ stats) {
+__global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__restrict__ w0,
+                                                             uint64_t n, BucketArgs ba,
+                                                             unsigned long long *__restrict__ stats) {
     extern __shared__ uint32_t s_dyn[];
-    uint32_t *s_h = s_dyn;                                       // B/2 packed 16-bit counters
-    uint64_t *s_ts = reinterpret_cast<uint64_t *>(s_dyn + B / 2); // B/S sampled thresholds
-    const int tid = threadIdx.x;
-    if (hist)
-        for (uint32_t t = tid; t < B / 2; t += kAssignWG) s_h[t] = 0;
-    if (MODE == 0)
-        for (uint32_t t = tid; t < B / S; t += kAssignWG) s_ts[t] = T[uint64_t(t) * S];
+    bucket_lds_init<MODE>(ba, s_dyn);
     __syncthreads();
-    const uint64_t i0 = uint64_t(blockIdx.x) * kKeysPerAssignWG;
-    const uint64_t i1 = min<uint64_t>(n, i0 + kKeysPerAssignWG);
+    const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
+    const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
     uint32_t probes = 0, err = 0;
-    for (uint64_t i = i0 + tid; i < i1; i += kAssignWG) {
-        const uint64_t x = w0[i];
-        uint32_t b;
-        if (MODE == 1) {
-            const uint32_t pb = predict_bucket(p, x, B);
-            b = correct_bucket(T, B, x, pb, probes);
-            err += b > pb ? b - pb : pb - b;
-            if (pred) pred[i] = pb;
-        } else {
-            uint32_t lo = 0, hi = B / S;  // s_ts[lo] <= x < s_ts[hi]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_ts[mid] <= x) lo = mid; else hi = mid;
-            }
-            uint32_t l2 = lo * S, h2 = min(B, (lo + 1) * S);
-            while (h2 - l2 > 1) {
-                const uint32_t mid = (l2 + h2) >> 1;
-                ++probes;
-                if (T[mid] <= x) l2 = mid; else h2 = mid;
-            }
-            b = l2;
-        }
-        if (bid) bid[i] = uint16_t(b);
-        if (bid32) bid32[i] = b;
-        if (hist) atomicAdd(&s_h[b >> 1], 1u << (16 * (b & 1)));
-    }
-    if (hist) {
-        __syncthreads();
-        for (uint32_t t = tid; t < B / 2; t += kAssignWG) {
-            const uint32_t v = s_h[t];
-            if (v & 0xFFFFu) atomicAdd(&hist[2 * t], v & 0xFFFFu);
-            if (v >> 16) atomicAdd(&hist[2 * t + 1], v >> 16);
-        }
-    }
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
+        (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
+    __syncthreads();
+    bucket_lds_flush(ba, s_dyn);
     if (stats) {
         unsigned long long a = probes, e = err;
 #pragma unroll
@@ -312,7 +212,7 @@ __global__ __launch_bounds__(kAssignWG) void k_bucket_assign(
             a += __shfl_xor(a, off, 64);
             e += __shfl_xor(e, off, 64);
         }
-        if ((tid & 63) == 0) {
+        if ((threadIdx.x & 63) == 0) {
             atomicAdd(&stats[0], a);
             atomicAdd(&stats[1], e);
         }
@@ -364,7 +264,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     __shared__ uint32_t s_k[2][kCap];    // [0]: high, [1]: low half of the local key;
                                          // afterwards the staging buffer of the permute
     __shared__ uint16_t s_idx[2][kCap];  // element order, ping-pong
-    __shared__ uint32_t s_wc[NW][256];
+    __shared__ uint16_t s_wc[NW][256];  // per-wave digit counts, then offsets (< kCap)
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint32_t s_and[2], s_or[2], s_fail, s_redo;
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
@@ -472,7 +372,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 const uint32_t below = __popcll(peers & lane_lt);
                 uint32_t old = 0;
                 if (valid) old = s_wc[wave][dig];
-                if (valid && below == 0) s_wc[wave][dig] = old + uint32_t(__popcll(peers));
+                if (valid && below == 0) s_wc[wave][dig] = uint16_t(old + uint32_t(__popcll(peers)));
                 rank[u] = old + below;
             }
             __syncthreads();
@@ -488,7 +388,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 if (tid < 256) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
-                        s_wc[w][tid] = ds;
+                        s_wc[w][tid] = uint16_t(ds);
                         ds += c[w];
                     }
                 }
@@ -565,6 +465,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         return;
     }
     constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
+    int done_arr = -2;  // array already written out by the fix-up (-1: row ids)
     if (s_redo == 2u) {
         uint64_t *stg = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
         for (int k = -1; k < int(words); ++k) {
@@ -596,6 +497,16 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 }
             }
             __syncthreads();
+            if (k == (words == 1 ? -1 : int(words) - 1)) {  // order final: write this array out
+                if (a < 0) {
+                    for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[ord[j]]);
+                } else {
+                    uint64_t *wk = ck + uint64_t(a) * n + start;
+                    for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
+                }
+                done_arr = a;
+                __syncthreads();
+            }
         }
     }
     // Permute in place: stage each array's bucket slice in LDS (coalesced load,
@@ -603,6 +514,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     // order (coalesced store).
     uint64_t *stage = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
     for (uint32_t k = 0; k < words; ++k) {
+        if (int(k) == done_arr) continue;
         uint64_t *wk = ck + uint64_t(k) * n + start;
         uint64_t v[PER];
 #pragma unroll
@@ -619,6 +531,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stage[ord[j]];
         __syncthreads();
     }
+    if (done_arr == -1) return;
     uint32_t *stage32 = &s_k[0][0];
     uint32_t *rk = rid + start;
     {
@@ -656,36 +569,23 @@ LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
     return l;
 }
 
-uint32_t splitter_stride(uint32_t B) { return B / 16 > 2048 ? B / 2048 : 16; }
-
-size_t assign_lds(uint32_t B, int mode) {
-    return size_t(B / 2) * 4 + (mode == 0 ? size_t(B / splitter_stride(B)) * 8 : 0);
+BucketArgs bucket_args(const void *model, uint32_t B, uint16_t *bid, uint32_t *bid32, uint32_t *pred,
+                       uint32_t *hist) {
+    return BucketArgs{params_of(model), thresholds_of(model), B, splitter_stride(B), bid, bid32, pred, hist};
 }
 
-ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const void *model, uint32_t B,
-                          uint16_t *bid, uint32_t *bid32, uint32_t *pred, uint32_t *hist,
+ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const BucketArgs &ba,
                           unsigned long long *stats, hipStream_t st) {
     if (n == 0) return CKEY_OK;
-    const uint32_t S = splitter_stride(B);
-    const size_t lds = assign_lds(B, mode) + 16;
-    const uint64_t blocks = (n + kKeysPerAssignWG - 1) / kKeysPerAssignWG;
-    const float *p = params_of(model);
-    const uint64_t *T = thresholds_of(model);
-    static bool attr_set = false;
-    if (!attr_set) {  // dynamic LDS above 64 KB (B = 2^16)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_assign<0>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bucket_assign<1>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
+    const size_t lds = bucket_lds_bytes(ba, mode);
+    const uint64_t blocks = (n + kBucketKeysPerWG - 1) / kBucketKeysPerWG;
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<0>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<1>));
     const int pr = prof_begin(st, mode ? "assign_learned" : "assign_splitter");
     if (mode)
-        hipLaunchKernelGGL(k_bucket_assign<1>, dim3(uint32_t(blocks)), dim3(kAssignWG), lds, st, w0, n,
-                           p, T, B, S, bid, bid32, pred, hist, stats);
+        hipLaunchKernelGGL(k_bucket_assign<1>, dim3(uint32_t(blocks)), dim3(kBucketWG), lds, st, w0, n, ba, stats);
     else
-        hipLaunchKernelGGL(k_bucket_assign<0>, dim3(uint32_t(blocks)), dim3(kAssignWG), lds, st, w0, n,
-                           p, T, B, S, bid, bid32, pred, hist, stats);
+        hipLaunchKernelGGL(k_bucket_assign<0>, dim3(uint32_t(blocks)), dim3(kBucketWG), lds, st, w0, n, ba, stats);
     prof_end(st, pr);
     return launch_status();
 }
@@ -700,63 +600,99 @@ size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_
     return a > r ? a : r;
 }
 
-ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
-                         int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
-                         hipStream_t st) {
-    if (n < 2) return CKEY_OK;
-    const uint32_t B = 1u << b_log2;
-    const LLayout l = llayout(words, n, B);
-    uint8_t *w8 = static_cast<uint8_t *>(ws);
-    uint16_t *bid = reinterpret_cast<uint16_t *>(w8 + l.bid);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(w8 + l.hist);
-    uint32_t *starts = reinterpret_cast<uint32_t *>(w8 + l.starts);
-    uint32_t *cursor = reinterpret_cast<uint32_t *>(w8 + l.cursor);
-    uint32_t *ovf = reinterpret_cast<uint32_t *>(w8 + l.ovf);
+namespace {
 
-    CKEY_TRY(fill_u32(hist, B, 0, st));
-    CKEY_TRY(fill_u32(ovf, 1, 0, st));
-    CKEY_TRY(assign_launch(mode, ck, n, model, B, bid, nullptr, nullptr, hist, nullptr, st));
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, hist, B, starts, cursor);
+struct LPtrs {
+    uint16_t *bid;
+    uint32_t *hist, *starts, *cursor, *ovf;
+};
+
+LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
+    l = llayout(words, n, B);
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    return LPtrs{reinterpret_cast<uint16_t *>(w8 + l.bid), reinterpret_cast<uint32_t *>(w8 + l.hist),
+                 reinterpret_cast<uint32_t *>(w8 + l.starts), reinterpret_cast<uint32_t *>(w8 + l.cursor),
+                 reinterpret_cast<uint32_t *>(w8 + l.ovf)};
+}
+
+// From bucket ids and the bucket histogram: group by bucket, sort each bucket,
+// finish overflowing buckets with the radix sort.
+ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
+                          const void *model, uint32_t b_log2, const LPtrs &q, const LLayout &l,
+                          uint32_t *flags, void *ws, hipStream_t st) {
+    const uint32_t B = 1u << b_log2;
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, q.hist, B, q.starts, q.cursor);
     CKEY_TRY(launch_status());
     // Group rows by bucket: a stable sort by the bucket id (two one-sweep passes).
-    CKEY_TRY(aux_sort(ck, rid, bid, n, words, b_log2, flags, w8 + l.sortws, st));
+    CKEY_TRY(aux_sort(ck, rid, q.bid, n, words, b_log2, q.hist, flags, w8 + l.sortws, st));
     const uint64_t *T = thresholds_of(model);
     {
         const int pr = prof_begin(st, "bucket_sort");
         if (n / B <= 1600) {  // small buckets: 2560-row capacity, 512 threads, 4 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapSmall, 512> : words == 2 ? k_bucket_sort<2, kCapSmall, 512>
                     : words == 3 ? k_bucket_sort<3, kCapSmall, 512> : k_bucket_sort<0, kCapSmall, 512>;
-            hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, starts, T, B, ovf);
+            hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf);
         } else {
             auto kb = words == 1 ? k_bucket_sort<1, kCapLarge, 1024> : words == 2 ? k_bucket_sort<2, kCapLarge, 1024>
                     : words == 3 ? k_bucket_sort<3, kCapLarge, 1024> : k_bucket_sort<0, kCapLarge, 1024>;
-            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, starts, T, B, ovf);
+            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf);
         }
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());
     // Overflowing buckets: read their ranges back and finish them with the radix sort.
     uint32_t novf = 0;
-    CKEY_HIP_TRY(hipMemcpyAsync(&novf, ovf, 4, hipMemcpyDeviceToHost, st));
+    CKEY_HIP_TRY(hipMemcpyAsync(&novf, q.ovf, 4, hipMemcpyDeviceToHost, st));
     CKEY_HIP_TRY(hipStreamSynchronize(st));
     if (novf == 0) return CKEY_OK;
     std::vector<uint32_t> ranges(2 * size_t(novf));
-    CKEY_HIP_TRY(hipMemcpyAsync(ranges.data(), ovf + 1, ranges.size() * 4, hipMemcpyDeviceToHost, st));
+    CKEY_HIP_TRY(hipMemcpyAsync(ranges.data(), q.ovf + 1, ranges.size() * 4, hipMemcpyDeviceToHost, st));
     CKEY_HIP_TRY(hipStreamSynchronize(st));
     uint64_t rows = 0;
-    for (uint32_t q = 0; q < novf; ++q) rows += ranges[2 * q + 1];
+    for (uint32_t i = 0; i < novf; ++i) rows += ranges[2 * i + 1];
     if (novf > 64 || rows > n / 8) {
         // Widespread overflow (data the thresholds do not split): one radix
         // sort of everything by (key, row id) -- exact from any arrangement.
         CKEY_TRY(radix_sort(ck, n, words, nbits, rid, n, 8, 32, flags, ws, st));
     } else {
-        for (uint32_t q = 0; q < novf; ++q) {
-            const uint32_t s0 = ranges[2 * q], c = ranges[2 * q + 1];
+        for (uint32_t i = 0; i < novf; ++i) {
+            const uint32_t s0 = ranges[2 * i], c = ranges[2 * i + 1];
             CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
         }
     }
     if (flags) CKEY_TRY(fill_flag_or(flags, CKEY_FLAG_BUCKET_OVERFLOW, st));
     return CKEY_OK;
+}
+
+}  // namespace
+
+ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
+                         int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
+                         hipStream_t st) {
+    if (n < 2) return CKEY_OK;
+    const uint32_t B = 1u << b_log2;
+    LLayout l;
+    const LPtrs q = lptrs(ws, words, n, B, l);
+    CKEY_TRY(fill_u32(q.hist, B, 0, st));
+    CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
+    CKEY_TRY(assign_launch(mode, ck, n, bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), nullptr, st));
+    return bucket_finish(ck, words, nbits, rid, n, model, b_log2, q, l, flags, ws, st);
+}
+
+ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
+                                  uint32_t nbits, uint32_t *rid, int mode, const void *model,
+                                  uint32_t b_log2, uint32_t *flags, void *ws, hipStream_t st) {
+    const uint32_t B = 1u << b_log2;
+    const uint64_t n = k.n;
+    LLayout l;
+    const LPtrs q = lptrs(ws, words, n, B, l);
+    CKEY_TRY(fill_u32(q.hist, B, 0, st));
+    CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
+    CKEY_TRY(compress_bucket_launch(k, bm, ck, words, rid, flags, mode,
+                                    bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), st));
+    if (n < 2) return CKEY_OK;
+    return bucket_finish(ck, words, nbits, rid, n, model, b_log2, q, l, flags, ws, st);
 }
 
 // ------------------------------------------------------------- model API --
@@ -825,7 +761,8 @@ ckey_status model_train(void *model, const uint64_t *prefix, uint64_t m, uint32_
 ckey_status model_bucket(const void *model, uint32_t b_log2, int mode, const uint64_t *prefix,
                          uint64_t n, uint32_t *bucket, uint32_t *pred, unsigned long long *stats,
                          hipStream_t st) {
-    return assign_launch(mode, prefix, n, model, 1u << b_log2, nullptr, bucket, pred, nullptr, stats, st);
+    return assign_launch(mode, prefix, n, bucket_args(model, 1u << b_log2, nullptr, bucket, pred, nullptr),
+                         stats, st);
 }
 
 }  // namespace ckey

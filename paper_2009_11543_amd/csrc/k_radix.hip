@@ -342,8 +342,27 @@ AuxLayout aux_layout(uint32_t words, uint64_t n) {
 
 size_t aux_sort_workspace(uint32_t words, uint64_t n) { return aux_layout(words, n).total; }
 
+// Pass histograms of the two aux digits from a histogram over all 2^aux_bits
+// aux values (thread d owns digit value d of both passes).
+__global__ __launch_bounds__(kWG) void k_aux_hist(const uint32_t *__restrict__ full, uint32_t aux_bits,
+                                                  uint32_t lo, uint32_t *__restrict__ hist) {
+    const uint32_t d = threadIdx.x, hi = aux_bits - lo;
+    uint32_t s0 = 0, s1 = 0;
+    if (lo && d < (1u << lo))
+        for (uint32_t h = 0; h < (1u << hi); ++h) s0 += full[(h << lo) | d];
+    if (d < (1u << hi))
+        for (uint32_t l = 0; l < (1u << lo); ++l) s1 += full[(d << lo) | l];
+    if (lo) {
+        hist[d] = s0;
+        hist[kRadixMax + d] = s1;
+    } else {
+        hist[d] = s1;
+    }
+}
+
 ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
-                     uint32_t aux_bits, uint32_t *flags, void *ws, hipStream_t st) {
+                     uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags, void *ws,
+                     hipStream_t st) {
     if (n < 2 || aux_bits == 0) return CKEY_OK;
     const AuxLayout l = aux_layout(words, n);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
@@ -366,9 +385,11 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t 
         ha.out[p] = uint32_t(p);
     }
     ha.npass = uint32_t(ps.size());
-    uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
-    if (hblocks > 2048) hblocks = 2048;
-    {
+    if (aux_full_hist) {
+        hipLaunchKernelGGL(k_aux_hist, dim3(1), dim3(kWG), 0, st, aux_full_hist, aux_bits, lo, hist);
+    } else {
+        uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
+        if (hblocks > 2048) hblocks = 2048;
         const int pr_ = prof_begin(st, "hist");
         hipLaunchKernelGGL(k_hist<uint16_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, aux, n, ha, hist);
         prof_end(st, pr_);

@@ -251,3 +251,37 @@ def test_bucket_sort_patterns(ck, pattern):
     ck.ckey_sort(ckd, plan["nbits"], rid, method=ck.CKEY_SORT_SPLITTER, model=model)
     np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
     np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, d)[:, perm])
+
+
+@pytest.mark.parametrize("method", ["radix", "splitter", "learned"])
+@pytest.mark.parametrize("layout", ["fixed16", "stride_odd", "varlen"])
+def test_compress_sort_entry(ck, method, layout):
+    """ckey_compress_sort (fused compression + bucket assignment where the keys
+    allow it) against the oracle."""
+    rng = np.random.default_rng(31)
+    n, L = 50000, 24
+    if layout == "varlen":
+        lens = rng.integers(1, L + 1, n)
+        rows = rng.choice(np.frombuffer(b"ACGT", np.uint8), (n, L))
+        rows[np.arange(L)[None, :] >= lens[:, None]] = 0
+        flat, offs = datagen.pack_varlen(rows, lens)
+        k = O.Keys(flat, L=L, offsets=offs)
+        dk = ck.DeviceKeys.from_numpy(flat, key_bytes=L, offsets=offs)
+    else:
+        rows = rng.choice(np.frombuffer(b"ACGT", np.uint8), (n, L))
+        if layout == "stride_odd":
+            rows = np.concatenate([rows, np.zeros((n, 3), np.uint8)], 1)
+        k = O.Keys(rows, L=L)
+        dk = ck.DeviceKeys.from_numpy(rows, key_bytes=L)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    cko = O.compress(k, d)
+    opts = {}
+    if method != "radix":
+        model = ck.CdfModel(bucket_log2=8, seed=2)
+        ck.ckey_cdf_fit(model, to_dev(np.ascontiguousarray(cko[0, perm])), steps=100, batch=4096)
+        opts = dict(method=ck.CKEY_SORT_SPLITTER if method == "splitter" else ck.CKEY_SORT_LEARNED,
+                    model=model)
+    ckd, rid = ck.ckey_compress_sort(dk, d, **opts)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(ck.as_u64(ckd), cko[:, perm])
