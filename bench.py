@@ -65,9 +65,6 @@ def workload(name):
 class Prof:
     def __init__(self, lib):
         self.lib = lib
-        lib.ckey_profile_enable.argtypes = [ctypes.c_int]
-        lib.ckey_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
-                                          ctypes.POINTER(ctypes.c_uint64)]
 
     def on(self, flag=True):
         self.lib.ckey_profile_reset()
@@ -203,7 +200,6 @@ def main():
     buf_a = torch.empty(1 << 31, dtype=torch.uint8, device=dev)
     buf_b = torch.empty_like(buf_a)
     lib = ckey.lib()
-    lib.ckey_bench_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     for _ in range(2):
         lib.ckey_bench_copy(buf_b.data_ptr(), buf_a.data_ptr(), buf_a.numel(), st)

@@ -47,6 +47,12 @@ class ckey_index_desc(ctypes.Structure):
                 ("opts", ctypes.POINTER(ckey_sort_opts))]
 
 
+class ckey_cdf_train_opts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_11543_amd.build`")
@@ -70,9 +76,22 @@ def _load():
     lib.ckey_tune_index.argtypes = [ctypes.POINTER(ckey_index_desc), ctypes.POINTER(ckey_sort_opts),
                                     U32, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_float)]
+    lib.ckey_cdf_model_bytes.argtypes = [U32]
+    lib.ckey_cdf_model_bytes.restype = ctypes.c_size_t
+    lib.ckey_cdf_model_init.argtypes = [P, U32, U64, P]
+    lib.ckey_cdf_fit.argtypes = [P, U32, P, U64, ctypes.POINTER(ckey_cdf_train_opts), P, P, SZP, P]
+    lib.ckey_cdf_grad.argtypes = [P, P, P, U64, P, P, P, SZP, P]
+    lib.ckey_cdf_bucket.argtypes = [P, U32, U32, P, U64, P, P, P, P]
+    lib.ckey_profile_enable.argtypes = [ctypes.c_int]
+    lib.ckey_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.ckey_profile_reset.argtypes = []
+    lib.ckey_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
     for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
-               "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch", "ckey_graph_destroy",
-               "ckey_tune_index"):
+               "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch",
+               "ckey_graph_destroy", "ckey_tune_index", "ckey_cdf_model_init", "ckey_cdf_fit",
+               "ckey_cdf_grad", "ckey_cdf_bucket", "ckey_profile_enable", "ckey_profile_read",
+               "ckey_profile_reset", "ckey_bench_copy"):
         getattr(lib, fn).restype = ctypes.c_int
     return lib
 
@@ -364,27 +383,6 @@ def as_u64(t):
 
 
 # ----------------------------------------------------- learned bucketing --
-
-class ckey_cdf_train_opts(ctypes.Structure):
-    _fields_ = [("steps", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("seed", ctypes.c_uint64)]
-
-
-_lib.ckey_cdf_model_bytes.argtypes = [ctypes.c_uint32]
-_lib.ckey_cdf_model_bytes.restype = ctypes.c_size_t
-_lib.ckey_cdf_model_init.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
-_lib.ckey_cdf_fit.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
-                              ctypes.POINTER(ckey_cdf_train_opts), ctypes.c_void_p, ctypes.c_void_p,
-                              ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
-_lib.ckey_cdf_grad.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                               ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
-_lib.ckey_cdf_bucket.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
-                                 ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                 ctypes.c_void_p]
-for _fn in ("ckey_cdf_model_init", "ckey_cdf_fit", "ckey_cdf_grad", "ckey_cdf_bucket"):
-    getattr(_lib, _fn).restype = ctypes.c_int
 
 MODEL_PARAMS = 385
 _OFF_T = 8192

@@ -38,6 +38,16 @@ def test_exports_every_declared_symbol(ck):
         assert hasattr(lib, name), name
 
 
+def test_every_declared_symbol_is_typed_on_each_load(ck):
+    # An untyped ctypes call passes Python ints as C int: a device pointer
+    # would be cut to 32 bits.  Every load must declare every signature.
+    for lib in (ck.lib(), ck._load()):
+        for name in sorted(declared_symbols()):
+            f = getattr(lib, name)
+            assert f.argtypes is not None, name
+            assert f.restype is not None, name
+
+
 def test_status_strings(ck):
     assert ck.status_string(0) == "ok"
     assert "workspace" in ck.status_string(3)
