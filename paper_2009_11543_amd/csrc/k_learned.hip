@@ -253,6 +253,18 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict
 // (the rows are already grouped by bucket).  Every first word x in bucket b
 // lies in [T[b], T[b+1]), so all share the common prefix (cp bits) of that
 // range; the LDS sort key is x << cp, whose equal values are equal first words.
+//
+// 1. Order by the local key: LSD over its top three varying 8-bit digits (the
+//    first pass unstable, by LDS atomics -- the starting order is arbitrary;
+//    later passes stable, ranked with wave ballots), then every run of equal
+//    top digits is ranked in parallel by the whole local key.  A run longer
+//    than kTieCap instead redoes the LSD over every varying digit.
+// 2. Runs of equal local keys (equal first words) are ordered by the remaining
+//    words and the row id: each array is staged in LDS and the members of
+//    every run are ranked by it in parallel, stably (an LSD within the runs,
+//    row ids first, then words w-1 .. 1).
+// 3. The first words are written from LDS; the other arrays are staged in LDS
+//    (coalesced load) and written back in sorted order (coalesced store).
 template <int WC, int kCap, int kSortWG>
 __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict__ ck,
                                                          uint32_t *__restrict__ rid, uint64_t n,
@@ -261,12 +273,18 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                                                          const uint64_t *__restrict__ T, uint32_t B,
                                                          uint32_t *__restrict__ ovf) {
     constexpr int NW = kSortWG / 64;
+    constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
+    constexpr uint32_t kTieCap = 64;
+    static_assert(kCap <= 8192 && ((kCap + kSortWG - 1) / kSortWG) * 64 <= 512,
+                  "packed ids and ranks need 13 and 9 bits");
     __shared__ uint32_t s_k[2][kCap];    // [0]: high, [1]: low half of the local key;
-                                         // afterwards the staging buffer of the permute
+                                         // afterwards 8-byte staging of the other arrays
     __shared__ uint16_t s_idx[2][kCap];  // element order, ping-pong
-    __shared__ uint16_t s_wc[NW][256];  // per-wave digit counts, then offsets (< kCap)
+    __shared__ uint16_t s_run[kCap];     // start of the run of equal local keys at each position
+    __shared__ uint16_t s_wc[NW][256];   // per-wave digit counts, then offsets (< kCap)
+    __shared__ uint32_t s_red[NW][4];
     __shared__ uint32_t s_tmp[NW];
-    __shared__ uint32_t s_and[2], s_or[2], s_fail, s_redo;
+    __shared__ uint32_t s_flag[2];       // [0]: some run needs ordering / redo, [1]: run too long
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t b = blockIdx.x;
@@ -283,16 +301,9 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     }
     const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
     const uint32_t cp = lo == hi ? 64u : uint32_t(__clzll(lo ^ hi));
-    if (tid == 0) {
-        s_and[0] = s_and[1] = ~0u;
-        s_or[0] = s_or[1] = 0u;
-        s_fail = 0u;
-        s_redo = 0u;
-    }
-    __syncthreads();
+    const uint64_t pre = cp == 0 ? 0ull : cp >= 64 ? lo : (lo & ~(~0ull >> cp));  // shared prefix
     uint32_t a_and[2] = {~0u, ~0u}, a_or[2] = {0u, 0u};
     {
-        constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
         uint64_t xs[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {  // all loads first: PER in flight per thread
@@ -315,17 +326,37 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
             }
         }
     }
-    atomicAnd(&s_and[0], a_and[0]);
-    atomicOr(&s_or[0], a_or[0]);
-    atomicAnd(&s_and[1], a_and[1]);
-    atomicOr(&s_or[1], a_or[1]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a_and[0] &= __shfl_xor(a_and[0], off, 64);
+        a_and[1] &= __shfl_xor(a_and[1], off, 64);
+        a_or[0] |= __shfl_xor(a_or[0], off, 64);
+        a_or[1] |= __shfl_xor(a_or[1], off, 64);
+    }
+    if (lane == 0) {
+        s_red[wave][0] = a_and[0];
+        s_red[wave][1] = a_and[1];
+        s_red[wave][2] = a_or[0];
+        s_red[wave][3] = a_or[1];
+    }
+    if (tid < 2) s_flag[tid] = 0u;
     __syncthreads();
-    const uint32_t vary[2] = {s_and[0] ^ s_or[0], s_and[1] ^ s_or[1]};
+    uint32_t vary[2] = {0u, 0u};
+    {
+        uint32_t g_and[2] = {~0u, ~0u}, g_or[2] = {0u, 0u};
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            g_and[0] &= s_red[w][0];
+            g_and[1] &= s_red[w][1];
+            g_or[0] |= s_red[w][2];
+            g_or[1] |= s_red[w][3];
+        }
+        vary[0] = g_and[0] ^ g_or[0];
+        vary[1] = g_and[1] ^ g_or[1];
+    }
+    auto lkey = [&](uint32_t id) { return (uint64_t(s_k[0][id]) << 32) | s_k[1][id]; };
     // Digits of the 64-bit local key, 0 = least significant; d < 4 is in the low half.
     auto digit_varies = [&](int d) { return ((vary[d < 4 ? 1 : 0] >> (8 * (d & 3))) & 0xFFu) != 0; };
-    // First attempt: only the three most significant varying digits, then an
-    // insertion pass over runs of equal top digits.  If some run is long, redo
-    // with every varying digit.
     int dmin = 8, nvar = 0, nall = 0;
     for (int d = 7; d >= 0; --d)
         if (digit_varies(d)) {
@@ -339,29 +370,44 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     const uint32_t Q = ((cnt + NW * 64 - 1) / (NW * 64)) * 64;
     const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
     const uint64_t lane_lt = (1ull << lane) - 1ull;
+    uint32_t *cnt32 = reinterpret_cast<uint32_t *>(&s_wc[0][0]);  // 256 counters (unstable pass)
     for (int attempt = 0; attempt < 2; ++attempt) {
         const int dlo = attempt == 0 ? dmin : 0;
-        if (attempt == 1) {
-            for (uint32_t j = tid; j < cnt; j += kSortWG) s_idx[0][j] = uint16_t(j);
-            cur = 0;
-            __syncthreads();
-        }
+        bool first = true;
         for (int d = dlo; d < 8; ++d) {  // LSD over the chosen digits
             if (!digit_varies(d)) continue;
-            const int half = d < 4 ? 1 : 0;
+            const uint32_t *key = s_k[d < 4 ? 1 : 0];
             const uint32_t shift = 8 * (d & 3);
-            const uint32_t *key = s_k[half];
+            if (first) {
+                // Unstable counting pass straight from the load order.
+                first = false;
+                if (tid < 256) cnt32[tid] = 0u;
+                __syncthreads();
+                for (uint32_t j = tid; j < cnt; j += kSortWG) atomicAdd(&cnt32[(key[j] >> shift) & 0xFFu], 1u);
+                __syncthreads();
+                const uint32_t c = tid < 256 ? cnt32[tid] : 0u;
+                uint32_t all;
+                const uint32_t ex = block_excl_scan_n<kSortWG>(c, s_tmp, all);
+                if (tid < 256) cnt32[tid] = ex;
+                __syncthreads();
+                for (uint32_t j = tid; j < cnt; j += kSortWG) {
+                    const uint32_t pos = atomicAdd(&cnt32[(key[j] >> shift) & 0xFFu], 1u);
+                    s_idx[1][pos] = uint16_t(j);
+                }
+                __syncthreads();
+                cur = 1;
+                continue;
+            }
             for (int t = tid; t < NW * 256; t += kSortWG) (&s_wc[0][0])[t] = 0;
             __syncthreads();
-            uint32_t rank[kRounds], dg[kRounds];
-            uint16_t ids[kRounds];
+            // per element: id (13 bits) << 17 | digit << 9 | rank within the wave's slice (< 512)
+            uint32_t pk[kRounds];
 #pragma unroll
             for (int u = 0; u < kRounds; ++u) {
                 const uint32_t e = e0 + 64 * u + lane;
                 const bool valid = e < e1;
-                ids[u] = valid ? s_idx[cur][e] : uint16_t(0);
-                const uint32_t dig = valid ? (key[ids[u]] >> shift) & 0xFFu : 0u;
-                dg[u] = dig;
+                const uint32_t id = valid ? s_idx[cur][e] : 0u;
+                const uint32_t dig = valid ? (key[id] >> shift) & 0xFFu : 0u;
                 uint64_t peers = __ballot(valid);
 #pragma unroll
                 for (int bit = 0; bit < 8; ++bit) {
@@ -373,23 +419,22 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 uint32_t old = 0;
                 if (valid) old = s_wc[wave][dig];
                 if (valid && below == 0) s_wc[wave][dig] = uint16_t(old + uint32_t(__popcll(peers)));
-                rank[u] = old + below;
+                pk[u] = (id << 17) | (dig << 9) | (old + below);
             }
             __syncthreads();
             {
-                uint32_t c[NW], tot = 0;
+                uint32_t tot = 0;
+                if (tid < 256)
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    c[w] = tid < 256 ? s_wc[w][tid] : 0u;
-                    tot += c[w];
-                }
+                    for (int w = 0; w < NW; ++w) tot += s_wc[w][tid];
                 uint32_t all;
                 uint32_t ds = block_excl_scan_n<kSortWG>(tot, s_tmp, all);
                 if (tid < 256) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
+                        const uint32_t c = s_wc[w][tid];
                         s_wc[w][tid] = uint16_t(ds);
-                        ds += c[w];
+                        ds += c;
                     }
                 }
             }
@@ -397,66 +442,56 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 #pragma unroll
             for (int u = 0; u < kRounds; ++u) {
                 const uint32_t e = e0 + 64 * u + lane;
-                if (e < e1) s_idx[cur ^ 1][s_wc[wave][dg[u]] + rank[u]] = ids[u];
+                if (e < e1) s_idx[cur ^ 1][s_wc[wave][(pk[u] >> 9) & 0xFFu] + (pk[u] & 0x1FFu)] = uint16_t(pk[u] >> 17);
             }
             __syncthreads();
             cur ^= 1;
         }
         if (attempt == 1 || nall <= 3) break;  // every varying digit is sorted
-        // Runs of equal top digits: insertion sort by the whole local key (LDS).
+        // Runs of equal top digits: rank each member by the whole local key.
         const uint32_t sh = 8 * uint32_t(dmin);  // bits below the sorted digits
-        uint16_t *ordr = s_idx[cur];
-        auto top = [&](uint16_t id) { return ((uint64_t(s_k[0][id]) << 32) | s_k[1][id]) >> sh; };
+        const uint16_t *ordr = s_idx[cur];
+        uint16_t *dst = s_idx[cur ^ 1];
         for (uint32_t j = tid; j < cnt; j += kSortWG) {
-            const uint64_t t0 = top(ordr[j]);
-            if (j > 0 && top(ordr[j - 1]) == t0) continue;
-            uint32_t r = 1;
-            while (j + r < cnt && r <= 16u && top(ordr[j + r]) == t0) ++r;
-            if (r > 16u) {
-                s_redo = 1u;
+            const uint16_t id = ordr[j];
+            const uint64_t kv = lkey(id), t0 = kv >> sh;
+            uint32_t s = j;
+            while (s > 0 && j - s < kTieCap && (lkey(ordr[s - 1]) >> sh) == t0) --s;
+            uint32_t e = j + 1;
+            while (e < cnt && e - s <= kTieCap && (lkey(ordr[e]) >> sh) == t0) ++e;
+            if (e - s > kTieCap) s_flag[0] = 1u;  // redo with every digit
+            if (e - s == 1) {
+                dst[j] = id;
                 continue;
             }
-            for (uint32_t a = 1; a < r; ++a) {
-                const uint16_t v = ordr[j + a];
-                const uint64_t kv = (uint64_t(s_k[0][v]) << 32) | s_k[1][v];
-                uint32_t c = a;
-                while (c > 0) {
-                    const uint16_t u = ordr[j + c - 1];
-                    const uint64_t ku = (uint64_t(s_k[0][u]) << 32) | s_k[1][u];
-                    if (ku <= kv) break;  // stable: equal local keys keep their order
-                    ordr[j + c] = u;
-                    --c;
-                }
-                ordr[j + c] = v;
+            uint32_t r = 0;
+            for (uint32_t q = s; q < e; ++q) {
+                const uint64_t kq = lkey(ordr[q]);
+                r += (kq < kv || (kq == kv && q < j)) ? 1u : 0u;
             }
+            dst[s + r] = id;  // s + r < e <= cnt
         }
         __syncthreads();
-        if (!s_redo) break;
-    }
-    // Runs of equal first words (equal local keys) must be ordered by the
-    // remaining words, then the row id.  Record each run's length at its start
-    // in the free ping-pong buffer, then -- with the local keys no longer
-    // needed -- stage the row ids and then each remaining word (least
-    // significant first) in LDS and insertion-sort every run by it, stably:
-    // an LSD sort within the runs, with no global reads on the critical path.
-    uint16_t *ord = s_idx[cur];
-    uint16_t *runlen = s_idx[cur ^ 1];
-    for (uint32_t j = tid; j < cnt; j += kSortWG) {
-        const uint16_t i0 = ord[j];
-        uint32_t r = 0;
-        const bool starts = j == 0 || s_k[0][ord[j - 1]] != s_k[0][i0] || s_k[1][ord[j - 1]] != s_k[1][i0];
-        if (starts) {
-            r = 1;
-            while (j + r < cnt && r <= uint32_t(kRunCap) && s_k[0][ord[j + r]] == s_k[0][i0] &&
-                   s_k[1][ord[j + r]] == s_k[1][i0])
-                ++r;
-            if (r > uint32_t(kRunCap)) s_fail = 1u;
-            if (r > 1) s_redo = 2u;  // reused: "some run needs ordering"
+        if (!s_flag[0]) {
+            cur ^= 1;
+            break;
         }
-        runlen[j] = uint16_t(r);
+        __syncthreads();  // every thread has read the flag
+        if (tid == 0) s_flag[0] = 0u;
+    }
+    // Runs of equal local keys (equal first words): record each position's run
+    // start; a run longer than kRunCap sends the bucket to the radix fallback.
+    const uint16_t *ord0 = s_idx[cur];
+    for (uint32_t j = tid; j < cnt; j += kSortWG) {
+        const uint64_t k = lkey(ord0[j]);
+        uint32_t s = j;
+        while (s > 0 && j - s < uint32_t(kRunCap) && lkey(ord0[s - 1]) == k) --s;
+        if (j - s >= uint32_t(kRunCap)) s_flag[1] = 1u;
+        if (s < j) s_flag[0] = 1u;
+        s_run[j] = uint16_t(s);
     }
     __syncthreads();
-    if (s_fail) {  // leave the bucket as it is for the radix fallback
+    if (s_flag[1]) {  // leave the bucket as it is for the radix fallback
         if (tid == 0) {
             const uint32_t slot = atomicAdd(&ovf[0], 1u);
             ovf[1 + 2 * slot] = start;
@@ -464,10 +499,16 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         }
         return;
     }
-    constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
-    int done_arr = -2;  // array already written out by the fix-up (-1: row ids)
-    if (s_redo == 2u) {
-        uint64_t *stg = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
+    // First words, from the local keys (equal within a run, so already final).
+    for (uint32_t j = tid; j < cnt; j += kSortWG) {
+        const uint64_t l = lkey(ord0[j]);
+        ck[start + j] = cp >= 64 ? lo : (pre | (l >> cp));
+    }
+    const bool fixup = s_flag[0] != 0u;
+    __syncthreads();  // local keys are dead from here on
+    uint64_t *stg = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
+    int done_arr = 0;  // arrays already written: 0 (first words), then -1 (row ids) or a word
+    if (fixup) {
         for (int k = -1; k < int(words); ++k) {
             if (k == 0) continue;  // first words are equal within a run
             const int a = k < 0 ? -1 : int(words) - k;  // -1: row ids, then words w-1 .. 1
@@ -483,37 +524,44 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 if (j < cnt) stg[j] = v[u];
             }
             __syncthreads();
+            const uint16_t *ord = s_idx[cur];
+            uint16_t *dst = s_idx[cur ^ 1];
             for (uint32_t j = tid; j < cnt; j += kSortWG) {
-                const uint32_t r = runlen[j];
-                for (uint32_t q = 1; q < r; ++q) {  // stable insertion sort of ord[j..j+r)
-                    const uint16_t id = ord[j + q];
-                    const uint64_t key = stg[id];
-                    uint32_t c = q;
-                    while (c > 0 && stg[ord[j + c - 1]] > key) {
-                        ord[j + c] = ord[j + c - 1];
-                        --c;
-                    }
-                    ord[j + c] = id;
+                const uint16_t id = ord[j];
+                const uint32_t s = s_run[j];
+                const bool alone = s == j && (j + 1 == cnt || s_run[j + 1] != j);
+                if (alone) {
+                    dst[j] = id;
+                    continue;
                 }
+                const uint64_t x = stg[id];
+                uint32_t r = 0;
+                for (uint32_t q = s; q < cnt && s_run[q] == s; ++q) {
+                    const uint64_t xq = stg[ord[q]];
+                    r += (xq < x || (xq == x && q < j)) ? 1u : 0u;  // stable
+                }
+                dst[s + r] = id;
             }
             __syncthreads();
+            cur ^= 1;
             if (k == (words == 1 ? -1 : int(words) - 1)) {  // order final: write this array out
+                const uint16_t *fin = s_idx[cur];
                 if (a < 0) {
-                    for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[ord[j]]);
+                    for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[fin[j]]);
                 } else {
                     uint64_t *wk = ck + uint64_t(a) * n + start;
-                    for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
+                    for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[fin[j]];
                 }
                 done_arr = a;
                 __syncthreads();
             }
         }
     }
-    // Permute in place: stage each array's bucket slice in LDS (coalesced load,
-    // all of a thread's loads in flight at once), then write it back in sorted
-    // order (coalesced store).
-    uint64_t *stage = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
-    for (uint32_t k = 0; k < words; ++k) {
+    // Permute the remaining arrays in place: stage each bucket slice in LDS
+    // (coalesced load, all of a thread's loads in flight at once), then write
+    // it back in sorted order (coalesced store).
+    const uint16_t *ord = s_idx[cur];
+    for (uint32_t k = 1; k < words; ++k) {
         if (int(k) == done_arr) continue;
         uint64_t *wk = ck + uint64_t(k) * n + start;
         uint64_t v[PER];
@@ -525,10 +573,10 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const uint32_t j = tid + u * kSortWG;
-            if (j < cnt) stage[j] = v[u];
+            if (j < cnt) stg[j] = v[u];
         }
         __syncthreads();
-        for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stage[ord[j]];
+        for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
         __syncthreads();
     }
     if (done_arr == -1) return;
