@@ -42,6 +42,7 @@ def _load():
         lib.oracle_csort.argtypes = [P, U32, U64, P]
         lib.oracle_refine.argtypes = [P, U32, U64, P, P, U32, P, P]
         lib.oracle_variant.argtypes = keys + [U64, P]
+        lib.oracle_insert.argtypes = keys + [P, U64, P, U64, U64, P, P]
         lib.oracle_mlp_loss_grad.argtypes = [P, P, P, U64, P]
         lib.oracle_mlp_loss_grad.restype = ctypes.c_double
         lib.oracle_mlp_forward.argtypes = [P, P, U64, P]
@@ -183,6 +184,19 @@ def variant(k, ref_row=0):
     out = np.zeros(k.L, np.uint8)
     _load().oracle_variant(*k.args(), ref_row, _ptr(out))
     return out
+
+
+def insert(k, order, ins, dbitmap, variant=None, ref_row=0):
+    """Sequential inserts (Sec. 4.3) of rows ``ins`` into the index whose rows in
+    key order are ``order``.  Returns the updated (dbitmap, variant) copies."""
+    order = np.ascontiguousarray(order, np.uint32)
+    ins = np.ascontiguousarray(ins, np.uint32)
+    d = np.array(dbitmap, np.uint8, copy=True)
+    v = None if variant is None else np.array(variant, np.uint8, copy=True)
+    rc = _load().oracle_insert(*k.args(), _ptr(order), len(order), _ptr(ins), len(ins), ref_row,
+                               _ptr(d), _ptr(v))
+    assert rc == 0
+    return d, v
 
 
 # ------------------------------------------------------------ CDF model --

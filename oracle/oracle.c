@@ -329,6 +329,51 @@ int oracle_variant(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
 }
 
 /* ------------------------------------------------------------------------- */
+/* DS-metadata maintenance (Sec. 4.3).                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Inserts, one after another, as Sec. 4.3 describes them.  Rows order[0..ns)
+ * of the key set form the current index in key order; rows ins[0..m) are
+ * inserted in that sequence.  For each inserted key K: find its place between
+ * A and B (the last key <= K and the first key > K), then set
+ * max(D-bit(A, K), D-bit(K, B)) in the D-bitmap -- by Lemma 1 the smaller of
+ * the two is D-bit(A, B), which is set already -- and OR (K xor reference key)
+ * into the variant bitmap.  A missing neighbour (K first or last) or an equal
+ * one (D-bit -1) contributes nothing.  dbitmap (and variant, if not NULL) are
+ * L-byte bitmaps updated in place; ref_row is the reference key's row.
+ * Deletes (Sec. 4.3) leave both bitmaps unchanged, so they have no routine. */
+int oracle_insert(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                  uint32_t L, uint32_t stride, const uint32_t *order, uint64_t ns,
+                  const uint32_t *ins, uint64_t m, uint64_t ref_row,
+                  uint8_t *dbitmap, uint8_t *variant)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    uint32_t *cur = (uint32_t *)malloc((ns + m + 1) * sizeof(uint32_t));
+    if (!cur) return -1;
+    if (ns) memcpy(cur, order, ns * sizeof(uint32_t));
+    uint64_t c = ns;
+    for (uint64_t t = 0; t < m; ++t) {
+        uint32_t K = ins[t];
+        uint64_t lo = 0, hi = c; /* place: first index whose key is greater than K */
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (key_cmp(&k, cur[mid], K) <= 0) lo = mid + 1; else hi = mid;
+        }
+        int64_t da = lo > 0 ? key_dbit(&k, cur[lo - 1], K) : -1;
+        int64_t db = lo < c ? key_dbit(&k, K, cur[lo]) : -1;
+        int64_t mx = da > db ? da : db;
+        if (mx >= 0) set_bit(dbitmap, (uint32_t)mx);
+        memmove(cur + lo + 1, cur + lo, (c - lo) * sizeof(uint32_t));
+        cur[lo] = K;
+        ++c;
+        if (variant)
+            for (uint32_t j = 0; j < L; ++j) variant[j] |= key_byte(&k, K, j) ^ key_byte(&k, ref_row, j);
+    }
+    free(cur);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* CDF model for learned bucketing (not in the paper; the model of the       */
 /* learned bucketing extension).  fp64 reference of a 4 -> H -> 1 ReLU MLP.  */
 /* Parameter vector p (length 6H + 1):                                        */
