@@ -35,17 +35,17 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def training_rows(name, n):
-    """Rows of the same generator at seed 2 (the training rebuild)."""
+def training_rows(name, n, seed=2):
+    """Rows of the same generator at another seed (2: the training rebuild)."""
     from paper_2009_11543_amd import datagen
     if name == "dna64_2p26":
-        return datagen.dna_window_keys(n, seed=2)
+        return datagen.dna_window_keys(n, seed=seed)
     if name == "prefix16_2p20":
-        return datagen.uniform_prefix_keys(n, seed=2)
+        return datagen.uniform_prefix_keys(n, seed=seed)
     if name == "uniform32_2p28":
-        return datagen.uniform_keys(n, seed=2)
+        return datagen.uniform_keys(n, seed=seed)
     if name == "cluster32_2p28":
-        return datagen.cluster_keys(n, seed=2)
+        return datagen.cluster_keys(n, seed=seed)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -157,6 +157,63 @@ def bench_table(args, torch, ckey, prof, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev, batch_rows):
+    """DS-metadata calls at the workload's size (Sec. 4.3): the variant bitmap,
+    a first build that takes the variant bitmap (a sort-free superset of D) in
+    place of the all-ones bitmap, and a batched insert into the index."""
+    n, L = keys.n, keys.key_bytes
+
+    def ev_time(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    var = {}
+
+    def variant():
+        var["v"], var["r"] = ckey.ckey_variant_bitmap(keys)
+    ms = ev_time(variant, 5)
+    v_host = var["v"].cpu().numpy()
+    assert all((int(v) & int(d)) == int(d) for v, d in zip(v_host, d_bitmap)), "variant must cover D"
+    out["variant_bitmap"] = {"ms": ms, "gbps_key_bytes": n * L / (ms / 1e3) / 1e9,
+                             "popcount": int(np.unpackbits(v_host).sum()),
+                             "d_popcount": int(np.unpackbits(np.asarray(d_bitmap)).sum())}
+    log(f"variant bitmap: {ms:.3f} ms, |V|={out['variant_bitmap']['popcount']}")
+
+    res = {}
+
+    def first_build():
+        res["o"] = ckey.ckey_rebuild_index([{"keys": keys, "bitmap": v_host}])[0]
+    ms_fb = ev_time(first_build, 2)
+    assert torch.equal(res["o"]["perm"], ridf), "first build from the variant bitmap: order differs"
+    assert (res["o"]["bitmap"].cpu().numpy() == d_bitmap).all(), "first build: D differs"
+    out["first_build_from_variant"] = {
+        "ms": ms_fb + ms, "keys_per_s": n / ((ms_fb + ms) / 1e3),
+        "what": "ckey_variant_bitmap + ckey_rebuild_index(bitmap = variant, radix): perm and exact D"}
+    log(f"first build via variant bitmap: {ms_fb + ms:.2f} ms")
+
+    bk = ckey.DeviceKeys(torch.from_numpy(batch_rows).to(dev))
+    dbm = torch.from_numpy(np.asarray(d_bitmap).copy()).to(dev)
+
+    def insert():
+        ckey.ckey_insert_keys(keys, ridf, bk, dbm)
+    ms_in = ev_time(insert, 5)
+    got = dbm.cpu().numpy()
+    assert all((int(g) & int(d)) == int(d) for g, d in zip(got, d_bitmap))
+    out["insert_batch"] = {"ms": ms_in, "batch": int(bk.n), "index": n,
+                           "keys_per_s": bk.n / (ms_in / 1e3),
+                           "what": "ckey_insert_keys: batch full-key sort, binary search, new pairs' D-bits"}
+    log(f"insert {bk.n} keys into {n}: {ms_in:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +229,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-key", action="store_true")
+    ap.add_argument("--no-maintenance", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -352,6 +410,10 @@ def main():
             "speedup_of_compressed_radix": full * 1e3 / results["radix"][0] if "radix" in results else None,
             "what": "ckey_compress with an all-ones bitmap + ckey_sort over all 8L bits"},
     }
+    if not args.no_maintenance and full is not None:
+        del ck, ws
+        out["maintenance"] = bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev,
+                                               training_rows(args.workload, 1 << 16, seed=5))
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_sample} rows")
         out["cpu_baseline"] = cpu_baseline(rows, min(args.cpu_sample, n))

@@ -186,6 +186,47 @@ ckey_status ckey_tune_index(const ckey_index_desc *idx, const ckey_sort_opts *ca
                             uint32_t ncand, void *workspace, size_t workspace_bytes,
                             void *stream, uint32_t *best, float *times_ms);
 
+/* ---- DS-metadata maintenance (Sec. 4.3) --------------------------------------
+ * The DS-metadata of an index: the D-bitmap, the variant bitmap (1 where the
+ * keys may differ) and a reference key (any key of the index).  */
+
+/* Variant bitmap (Sec. 4.3, rebuild step 3): variant (device, key_bytes bytes,
+ * overwritten) = OR over all keys K of (K xor reference), keys zero-padded to
+ * key_bytes.  ref: device, key_bytes bytes, or NULL to take key 0 as the
+ * reference (an arbitrary index key, as the paper allows); ref_out (device,
+ * key_bytes bytes, or NULL) receives the reference used.  Every D position is
+ * a variant position, so the result is a superset of D that needs no sort: it
+ * can stand in for the all-ones bitmap of a first build.  n == 0 gives an
+ * all-zero bitmap.  Workspace: ceil(key_bytes/4) words (query with
+ * workspace == NULL). */
+ckey_status ckey_variant_bitmap(const ckey_keys *keys, const uint8_t *ref, uint8_t *variant,
+                                uint8_t *ref_out, uint32_t *flags, void *workspace,
+                                size_t *workspace_bytes, void *stream);
+
+/* Batched insert (Sec. 4.3, insert): the DS-metadata update for inserting
+ * every key of `batch` into the index `index`.  index_order (device
+ * uint32[index->n]) lists the index rows in key order (as ckey_rebuild_index's
+ * perm does); NULL: the rows are stored in key order.  batch_order likewise
+ * for the batch; NULL: the library sorts the batch itself (full-key radix sort
+ * in the workspace, which then grows with the batch and its key width).
+ * Both key sets must have the same key_bytes.  For each inserted key K that
+ * lands between A and B the paper sets max(D-bit(A,K), D-bit(K,B)) (the
+ * smaller is D-bit(A,B), already set, Lemma 1); for the whole batch this is
+ * every D-bit of an adjacent pair of the merged order that holds a batch key,
+ * OR-ed into dbitmap (device, key_bytes bytes, updated in place).  The result
+ * equals inserting the keys one by one, in any sequence, provided dbitmap
+ * covered the index's D before the call (always true of DS-metadata).  If
+ * variant (device, key_bytes bytes) is not NULL, (K xor ref) is OR-ed into it
+ * for every batch key; ref (device, key_bytes bytes) is then required.
+ * Deletes leave the DS-metadata unchanged (Sec. 4.3), so there is no delete
+ * call: the kept bitmaps stay valid supersets, and the next rebuild
+ * (ckey_rebuild_index) drops the stale bits. */
+ckey_status ckey_insert_keys(const ckey_keys *index, const uint32_t *index_order,
+                             const ckey_keys *batch, const uint32_t *batch_order,
+                             uint8_t *dbitmap, uint8_t *variant, const uint8_t *ref,
+                             uint32_t *flags, void *workspace, size_t *workspace_bytes,
+                             void *stream);
+
 /* ---- CDF model for learned bucketing (an extension; not in the paper) -------
  * Model memory is device memory owned by the caller, ckey_cdf_model_bytes()
  * long, 256-byte aligned: a 4 -> 64 -> 1 ReLU MLP (385 fp32 parameters, plus

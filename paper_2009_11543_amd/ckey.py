@@ -76,6 +76,9 @@ def _load():
     lib.ckey_tune_index.argtypes = [ctypes.POINTER(ckey_index_desc), ctypes.POINTER(ckey_sort_opts),
                                     U32, P, ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_float)]
+    lib.ckey_variant_bitmap.argtypes = [ctypes.POINTER(ckey_keys), P, P, P, P, P, SZP, P]
+    lib.ckey_insert_keys.argtypes = [ctypes.POINTER(ckey_keys), P, ctypes.POINTER(ckey_keys), P, P, P, P,
+                                     P, P, SZP, P]
     lib.ckey_cdf_model_bytes.argtypes = [U32]
     lib.ckey_cdf_model_bytes.restype = ctypes.c_size_t
     lib.ckey_cdf_model_init.argtypes = [P, U32, U64, P]
@@ -89,7 +92,7 @@ def _load():
     lib.ckey_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
     for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
                "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch",
-               "ckey_graph_destroy", "ckey_tune_index", "ckey_cdf_model_init", "ckey_cdf_fit",
+               "ckey_graph_destroy", "ckey_tune_index", "ckey_variant_bitmap", "ckey_insert_keys", "ckey_cdf_model_init", "ckey_cdf_fit",
                "ckey_cdf_grad", "ckey_cdf_bucket", "ckey_profile_enable", "ckey_profile_read",
                "ckey_profile_reset", "ckey_bench_copy"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -192,6 +195,42 @@ def ckey_distinction_bits(keys, order=None, flags=None, stream=None):
         ctypes.byref(ks), _ptr(order), _ptr(bm), _ptr(flags), _ptr(ws), ctypes.byref(need),
         _stream(stream)))
     return bm
+
+
+def ckey_variant_bitmap(keys, ref=None, flags=None, stream=None):
+    """(variant bitmap, reference key): two uint8 device tensors of key_bytes
+    bytes.  ``ref``: device uint8 tensor, or None for key 0 (Sec. 4.3)."""
+    ks = keys.c_struct()
+    need = ctypes.c_size_t(0)
+    _check("ckey_variant_bitmap", _lib.ckey_variant_bitmap(ctypes.byref(ks), None, None, None, None,
+                                                           None, ctypes.byref(need), None))
+    dev = keys.data.device
+    ws = _workspace(need.value, dev)
+    var = torch.empty(keys.key_bytes, dtype=torch.uint8, device=dev)
+    ref_out = torch.empty(keys.key_bytes, dtype=torch.uint8, device=dev)
+    _check("ckey_variant_bitmap", _lib.ckey_variant_bitmap(
+        ctypes.byref(ks), _ptr(ref), _ptr(var), _ptr(ref_out), _ptr(flags), _ptr(ws),
+        ctypes.byref(need), _stream(stream)))
+    return var, ref_out
+
+
+def ckey_insert_keys(index, index_order, batch, dbitmap, variant=None, ref=None, batch_order=None,
+                     flags=None, stream=None):
+    """DS-metadata update for inserting ``batch`` into ``index`` (Sec. 4.3):
+    ``dbitmap`` (and ``variant``, with ``ref``) -- device uint8 tensors of
+    key_bytes bytes -- are updated in place.  ``index_order``/``batch_order``:
+    int32 device tensors of row ids in key order, or None (stored in key order
+    / sort the batch inside)."""
+    ik, bk = index.c_struct(), batch.c_struct()
+    need = ctypes.c_size_t(0)
+    _check("ckey_insert_keys", _lib.ckey_insert_keys(
+        ctypes.byref(ik), None, ctypes.byref(bk), _ptr(batch_order), None, None, None, None, None,
+        ctypes.byref(need), None))
+    ws = _workspace(need.value, dbitmap.device)
+    _check("ckey_insert_keys", _lib.ckey_insert_keys(
+        ctypes.byref(ik), _ptr(index_order), ctypes.byref(bk), _ptr(batch_order), _ptr(dbitmap),
+        _ptr(variant), _ptr(ref), _ptr(flags), _ptr(ws), ctypes.byref(need), _stream(stream)))
+    return dbitmap, variant
 
 
 def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, stream=None):

@@ -256,6 +256,97 @@ ckey_status ckey_distinction_bits(const ckey_keys *keys, const uint32_t *order, 
     return bitmap_finalize(acc, bitmap, keys->key_bytes, st);
 }
 
+ckey_status ckey_variant_bitmap(const ckey_keys *keys, const uint8_t *ref, uint8_t *variant,
+                                uint8_t *ref_out, uint32_t *flags, void *ws, size_t *ws_bytes,
+                                void *stream) {
+    CKEY_TRY(check_keys(keys));
+    const uint32_t nw = (keys->key_bytes + 3) / 4;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, align256(nw * 4), query));
+    if (query) return CKEY_OK;
+    if (!variant) return CKEY_ERR_INVALID;
+    hipStream_t st = as_stream(stream);
+    uint32_t *acc = static_cast<uint32_t *>(ws);
+    const KeySrc k = key_src(keys);
+    CKEY_TRY(fill_u32(acc, nw, 0, st));
+    CKEY_TRY(variant_launch(k, ref, acc, flags, st));
+    CKEY_TRY(bitmap_finalize(acc, variant, keys->key_bytes, st));
+    if (ref_out) {
+        if (ref)
+            CKEY_HIP_TRY(hipMemcpyAsync(ref_out, ref, keys->key_bytes, hipMemcpyDeviceToDevice, st));
+        else
+            CKEY_TRY(ref_copy_launch(k, ref_out, st));
+    }
+    return CKEY_OK;
+}
+
+namespace {
+struct InsertLayout {
+    size_t pos, acc_d, acc_v, ck, rid, sortws, total;
+    uint32_t words, nbits;
+};
+
+InsertLayout insert_layout(const ckey_keys *batch, bool sort_batch) {
+    InsertLayout l{};
+    const uint64_t m = batch->n;
+    const uint32_t nw = (batch->key_bytes + 3) / 4;
+    size_t off = 0;
+    l.pos = off;   off += align256(size_t(m) * 4);
+    l.acc_d = off; off += align256(nw * 4);
+    l.acc_v = off; off += align256(nw * 4);
+    if (sort_batch) {  // full-key sort of the batch: compress with every position
+        l.nbits = 8 * batch->key_bytes;
+        l.words = words_for(l.nbits);
+        l.ck = off;  off += align256(size_t(l.words) * m * 8);
+        l.rid = off; off += align256(size_t(m) * 4);
+        l.sortws = off;
+        off += radix_workspace(l.words, l.nbits, m, 8);
+    }
+    l.total = off;
+    return l;
+}
+}  // namespace
+
+ckey_status ckey_insert_keys(const ckey_keys *index, const uint32_t *index_order,
+                             const ckey_keys *batch, const uint32_t *batch_order, uint8_t *dbitmap,
+                             uint8_t *variant, const uint8_t *ref, uint32_t *flags, void *ws,
+                             size_t *ws_bytes, void *stream) {
+    CKEY_TRY(check_keys(index));
+    CKEY_TRY(check_keys(batch));
+    if (index->key_bytes != batch->key_bytes) return CKEY_ERR_INVALID;
+    const InsertLayout l = insert_layout(batch, batch_order == nullptr);
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, l.total, query));
+    if (query) return CKEY_OK;
+    if (!dbitmap || (variant && !ref)) return CKEY_ERR_INVALID;
+    if (batch->n == 0) return CKEY_OK;
+    hipStream_t st = as_stream(stream);
+    uint8_t *w8 = static_cast<uint8_t *>(ws);
+    const KeySrc ix = key_src(index), bt = key_src(batch);
+    const uint32_t L = batch->key_bytes, nw = (L + 3) / 4;
+    const uint32_t *order = batch_order;
+    if (!order) {
+        const std::vector<uint8_t> ones(L, 0xFF);
+        uint64_t *ck = reinterpret_cast<uint64_t *>(w8 + l.ck);
+        uint32_t *rid = reinterpret_cast<uint32_t *>(w8 + l.rid);
+        CKEY_TRY(compress_launch(bt, ones.data(), ck, l.words, rid, flags, st));
+        CKEY_TRY(radix_sort(ck, batch->n, l.words, l.nbits, rid, batch->n, 8, 0, flags, w8 + l.sortws, st));
+        order = rid;
+    }
+    uint32_t *pos = reinterpret_cast<uint32_t *>(w8 + l.pos);
+    uint32_t *acc_d = reinterpret_cast<uint32_t *>(w8 + l.acc_d);
+    CKEY_TRY(fill_u32(acc_d, nw, 0, st));
+    CKEY_TRY(insert_launch(ix, index_order, bt, order, pos, acc_d, flags, st));
+    CKEY_TRY(bitmap_or_finalize(acc_d, dbitmap, L, st));
+    if (variant) {
+        uint32_t *acc_v = reinterpret_cast<uint32_t *>(w8 + l.acc_v);
+        CKEY_TRY(fill_u32(acc_v, nw, 0, st));
+        CKEY_TRY(variant_launch(bt, ref, acc_v, flags, st));
+        CKEY_TRY(bitmap_or_finalize(acc_v, variant, L, st));
+    }
+    return CKEY_OK;
+}
+
 ckey_status ckey_compress(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
                           uint32_t words, uint32_t *rowids, uint32_t *flags, void *stream) {
     CKEY_TRY(check_keys(keys));

@@ -96,6 +96,22 @@ struct HostPlan;
 ckey_status compress_launch(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ckeys,
                             uint32_t words, uint32_t *rowids, uint32_t *flags, hipStream_t st);
 
+// DS-metadata maintenance (k_maintain.hip).  acc_words: u32 view of a bitmap
+// (zeroed by the caller), OR-ed into.
+// Variant bitmap of k against ref (device, L bytes; nullptr: key 0 of k).
+ckey_status variant_launch(const KeySrc &k, const uint8_t *ref, uint32_t *acc_words,
+                           uint32_t *flags, hipStream_t st);
+// Key 0 of k, zero-padded to L bytes (all zero when k is empty).
+ckey_status ref_copy_launch(const KeySrc &k, uint8_t *out, hipStream_t st);
+// OR a little-endian u32 bitmap accumulator into a byte bitmap of L bytes.
+ckey_status bitmap_or_finalize(const uint32_t *acc_words, uint8_t *bitmap, uint32_t L, hipStream_t st);
+// Batched insert of bt (in key order bt_order, or as stored) into the index ix
+// (key order ix_order, or as stored): pos[j] receives the place of batch key j,
+// acc_words the D-bits of the new adjacent pairs.
+ckey_status insert_launch(const KeySrc &ix, const uint32_t *ix_order, const KeySrc &bt,
+                          const uint32_t *bt_order, uint32_t *pos, uint32_t *acc_words,
+                          uint32_t *flags, hipStream_t st);
+
 // Refresh of the D-bitmap from sorted compressed keys (k_refine.hip).
 ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
                           const uint8_t *bitmap_in_host, uint32_t L, uint32_t *acc_words,

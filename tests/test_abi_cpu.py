@@ -124,3 +124,35 @@ def test_workspace_queries(ck):
     small = ctypes.c_size_t(16)
     assert lib.ckey_rebuild_index(ctypes.byref(d), 1, None, ctypes.c_void_p(256),
                                   ctypes.byref(small), None) == ck.CKEY_ERR_WORKSPACE
+
+
+def test_maintenance_argument_errors_and_queries(ck):
+    lib = ck.lib()
+    need = ctypes.c_size_t(0)
+    ia = ck.ckey_keys(1, None, 100, 16, 16)
+    ba = ck.ckey_keys(1, None, 10, 8, 8)   # key widths differ
+    assert lib.ckey_insert_keys(ctypes.byref(ia), None, ctypes.byref(ba), None, None, None, None,
+                                None, None, ctypes.byref(need), None) == ck.CKEY_ERR_INVALID
+    bb = ck.ckey_keys(1, None, 1000, 16, 16)
+    assert lib.ckey_insert_keys(ctypes.byref(ia), None, ctypes.byref(bb), ctypes.c_void_p(256), None,
+                                None, None, None, None, ctypes.byref(need), None) == 0
+    given = need.value
+    assert given >= 1000 * 4  # places of the batch keys
+    assert lib.ckey_insert_keys(ctypes.byref(ia), None, ctypes.byref(bb), None, None, None, None,
+                                None, None, ctypes.byref(need), None) == 0
+    assert need.value >= given + 1000 * (16 + 4)  # plus the batch's own full-key sort
+    # real call without the D-bitmap, or with a variant bitmap but no reference
+    ws = ctypes.c_void_p(256)
+    big = ctypes.c_size_t(1 << 40)
+    assert lib.ckey_insert_keys(ctypes.byref(ia), None, ctypes.byref(bb), None, None, None, None,
+                                None, ws, ctypes.byref(big), None) == ck.CKEY_ERR_INVALID
+    assert lib.ckey_insert_keys(ctypes.byref(ia), None, ctypes.byref(bb), None, ctypes.c_void_p(512),
+                                ctypes.c_void_p(768), None, None, ws, ctypes.byref(big),
+                                None) == ck.CKEY_ERR_INVALID
+    assert lib.ckey_variant_bitmap(ctypes.byref(ia), None, None, None, None, None, ctypes.byref(need),
+                                   None) == 0 and need.value >= 16
+    assert lib.ckey_variant_bitmap(ctypes.byref(ia), None, None, None, None, ws, ctypes.byref(big),
+                                   None) == ck.CKEY_ERR_INVALID   # no output bitmap
+    small = ctypes.c_size_t(1)
+    assert lib.ckey_variant_bitmap(ctypes.byref(ia), None, ctypes.c_void_p(512), None, None, ws,
+                                   ctypes.byref(small), None) == ck.CKEY_ERR_WORKSPACE
