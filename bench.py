@@ -157,6 +157,90 @@ def bench_table(args, torch, ckey, prof, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_zipf(args, torch, ckey, dev):
+    """The paper's sensitivity datasets (Table 4): Zipf(s, n, m) keys, 10^7 rows
+    each.  Per dataset: |D| from a full-key first build, the sort key sizes of
+    Table 4, and the GPU time of the full-key sort against the compressed key
+    sort (compress + radix sort with D), the analogue of the paper's total
+    time ratio."""
+    from paper_2009_11543_amd import datagen
+    n = args.zipf_rows
+    rid_bits = max(1, (n - 1).bit_length())
+
+    def ev_time(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows_out = []
+    tot_keys, tot_ms = 0, 0.0
+    for (ds, s, L, m, full_b, comp_b) in datagen.ZIPF_TABLE4:
+        if args.zipf_datasets and ds not in args.zipf_datasets:
+            continue
+        rows = datagen.zipf_keys(n, s, L, m, seed=1)
+        keys = ckey.DeviceKeys(torch.from_numpy(rows).to(dev))
+        del rows
+        ones = np.full(L, 0xFF, np.uint8)
+        wf = (8 * L + 63) // 64
+        ckf = torch.empty((wf, n), dtype=torch.int64, device=dev)
+        ridf = torch.empty(n, dtype=torch.int32, device=dev)
+        wsf = torch.empty(ckey.ckey_sort_workspace(wf, 8 * L, n), dtype=torch.uint8, device=dev)
+
+        def full_sort():
+            ckey.ckey_compress(keys, ones, out=ckf, rowids=ridf)
+            ckey.ckey_sort(ckf, 8 * L, ridf, workspace=wsf)
+        full_ms = ev_time(full_sort, 2)
+        d = ckey.ckey_distinction_bits(keys, order=ridf).cpu().numpy()
+        del ckf, wsf
+        plan = ckey.ckey_plan_query(d)
+        nb, w = plan["nbits"], plan["words"]
+        ck = torch.empty((w, n), dtype=torch.int64, device=dev)
+        rid = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = torch.empty(ckey.ckey_sort_workspace(w, nb, n), dtype=torch.uint8, device=dev)
+
+        def comp_sort():
+            ckey.ckey_compress_sort(keys, d, out=ck, rowids=rid, workspace=ws)
+        comp_ms = ev_time(comp_sort, 3)
+        assert torch.equal(rid, ridf), f"Zipf dataset {ds}: compressed order differs"
+        # Table 4's compressed sort key: |D| plus the record ID's variant bits,
+        # in 8-byte words.  The rid variant bits r of the paper's rows are not
+        # given; report the range of r for which |D| reproduces the table.
+        ok_r = [r for r in range(0, 65) if -(-(nb + r) // 64) * 8 == comp_b]
+        rows_out.append({"dataset": ds, "s": s, "key_bytes": L, "m": m, "nbits": nb,
+                         "full_sort_key_bytes": L + 8, "table4_full": full_b,
+                         "comp_sort_key_bytes_dense_rid": -(-(nb + rid_bits) // 64) * 8,
+                         "table4_comp": comp_b, "rid_bits_matching_table4": [min(ok_r), max(ok_r)] if ok_r else None,
+                         "full_key_sort_ms": full_ms, "compressed_sort_ms": comp_ms,
+                         "gpu_time_ratio": full_ms / comp_ms})
+        log(f"Zipf ds {ds} ({s},{L},{m}): |D|={nb} full {full_ms:.1f} ms comp {comp_ms:.2f} ms "
+            f"ratio {full_ms / comp_ms:.1f}")
+        tot_keys += n
+        tot_ms += comp_ms
+        del keys, ck, rid, ws, ridf
+        torch.cuda.empty_cache()
+    common = None
+    for r in rows_out:
+        rr = r["rid_bits_matching_table4"]
+        if rr is None:
+            common = (1, 0)
+            break
+        common = tuple(rr) if common is None else (max(common[0], rr[0]), min(common[1], rr[1]))
+    out = {"metric": "compress+sort keys/s on the Zipf(s,n,m) datasets of Table 4",
+           "value": tot_keys / (tot_ms / 1e3), "unit": "keys/s", "n_gpus": 1, "steps": 3,
+           "warmup": 1, "ms_per_step": tot_ms / max(1, len(rows_out)), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "zipf_table4", "rows_per_dataset": n, "method": "radix"},
+           "datasets": rows_out,
+           "rid_bits_matching_every_dataset": None if common is None or common[0] > common[1] else list(common)}
+    print(json.dumps(out), flush=True)
+
+
 def bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev, batch_rows):
     """DS-metadata calls at the workload's size (Sec. 4.3): the variant bitmap,
     a first build that takes the variant bitmap (a sort-free superset of D) in
@@ -230,6 +314,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-key", action="store_true")
     ap.add_argument("--no-maintenance", action="store_true")
+    ap.add_argument("--zipf-rows", type=int, default=10_000_000)
+    ap.add_argument("--zipf-datasets", type=int, nargs="*", default=None,
+                    help="Table 4 dataset numbers for --workload zipf_table4 (default all)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -245,6 +332,8 @@ def main():
 
     if args.workload.startswith("table8"):
         return bench_table(args, torch, ckey, prof, dev)
+    if args.workload == "zipf_table4":
+        return bench_zipf(args, torch, ckey, dev)
     log(f"generating workload {args.workload}")
     rows, desc = workload(args.workload)
     n, L = rows.shape

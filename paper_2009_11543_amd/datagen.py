@@ -85,6 +85,55 @@ def dna_window_keys(n=1 << 26, seed=1, key_bytes=64, seq_len=1 << 27, p_mut=0.01
     return keys
 
 
+# Table 4 of the paper: (dataset, s, key bytes, m, full sort key bytes,
+# compressed sort key bytes) of its Zipf(s, n, m) datasets of 10 million keys.
+ZIPF_TABLE4 = [
+    (1, 2.5, 48, 0, 56, 40), (2, 2.5, 56, 0, 64, 40), (3, 2.5, 64, 0, 72, 40),
+    (4, 2.5, 72, 0, 80, 40), (5, 2.5, 80, 0, 88, 40), (6, 2.5, 88, 0, 96, 40),
+    (7, 2.5, 96, 0, 104, 40), (8, 2.5, 104, 0, 112, 40), (9, 2.5, 112, 0, 120, 40),
+    (10, 1.5, 40, 0, 48, 24), (11, 1.5, 40, 1, 48, 24), (12, 1.5, 40, 2, 48, 24),
+    (13, 1.5, 40, 3, 48, 24), (14, 1.5, 40, 4, 48, 24),
+    (15, 1.5, 64, 0, 72, 24), (16, 1.5, 64, 1, 72, 24), (17, 1.5, 64, 2, 72, 24),
+    (18, 1.5, 64, 3, 72, 24), (19, 1.5, 64, 4, 72, 24), (20, 1.5, 64, 5, 72, 24),
+]
+
+
+def zipf_letter_table(s, bits=20):
+    """Inverse-CDF table of Zipf(s, 26) over lower-case letters: entry u (of
+    2^bits) is the letter of the uniform draw (u + 1/2) / 2^bits."""
+    w = np.arange(1, 27, dtype=np.float64) ** (-float(s))
+    cdf = np.cumsum(w) / w.sum()
+    u = (np.arange(1 << bits, dtype=np.float64) + 0.5) / float(1 << bits)
+    return (0x61 + np.minimum(np.searchsorted(cdf, u, side="right"), 25)).astype(np.uint8)
+
+
+def zipf_keys(n=10_000_000, s=2.5, key_bytes=64, m=0, seed=1):
+    """The paper's Zipf(s, n, m) keys (Sec. 6): in every 8-byte word of a key
+    the first m bytes hold one fixed printable ASCII byte (seeded) and the
+    other 8 - m bytes are lower-case letters drawn from Zipf(s, 26) ('a' the
+    most frequent), through a 2^20-entry inverse-CDF table of 32-bit draws."""
+    rng = rng_for(seed)
+    fixed = np.uint8(rng.integers(0x21, 0x7F))
+    table = zipf_letter_table(s)
+    pos = np.arange(key_bytes)
+    lmask = (pos % 8) >= m
+    nl = int(lmask.sum())
+    out = np.empty((n, key_bytes), np.uint8)
+    out[:, ~lmask] = fixed
+    if nl:
+        chunk = max(1, (1 << 25) // nl)
+        for r0 in range(0, n, chunk):
+            r1 = min(n, r0 + chunk)
+            cnt = (r1 - r0) * nl
+            raw = rng.bit_generator.random_raw((cnt + 1) // 2).view(np.uint32)[:cnt]
+            letters = table[raw >> 12].reshape(r1 - r0, nl)
+            if nl == key_bytes:
+                out[r0:r1] = letters
+            else:
+                out[r0:r1, lmask] = letters
+    return out
+
+
 def uniform_keys(n=1 << 28, seed=1, key_bytes=32):  # noqa: D401
     """Uniform random bytes, ``key_bytes`` per row."""
     rng = rng_for(seed)
