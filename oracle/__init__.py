@@ -43,6 +43,10 @@ def _load():
         lib.oracle_refine.argtypes = [P, U32, U64, P, P, U32, P, P]
         lib.oracle_variant.argtypes = keys + [U64, P]
         lib.oracle_insert.argtypes = keys + [P, U64, P, U64, U64, P, P]
+        lib.oracle_tree_fill.argtypes = [ctypes.c_double, P, P]
+        lib.oracle_tree_shape.argtypes = [U64, ctypes.c_double, P]
+        lib.oracle_tree_shape.restype = U32
+        lib.oracle_bulk_load.argtypes = keys + [P, U32, ctypes.c_double, P]
         lib.oracle_mlp_loss_grad.argtypes = [P, P, P, U64, P]
         lib.oracle_mlp_loss_grad.restype = ctypes.c_double
         lib.oracle_mlp_forward.argtypes = [P, P, U64, P]
@@ -197,6 +201,32 @@ def insert(k, order, ins, dbitmap, variant=None, ref_row=0):
                                _ptr(d), _ptr(v))
     assert rc == 0
     return d, v
+
+
+TREE_NODE = 256
+
+
+def tree_fill(fill):
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().oracle_tree_fill(fill, ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def tree_shape(n, fill):
+    """Nodes per level, leaves first (Sec. 5.3)."""
+    lv = np.zeros(32, np.uint64)
+    h = _load().oracle_tree_shape(n, fill, _ptr(lv))
+    return [int(x) for x in lv[:h]]
+
+
+def bulk_load(k, perm, pk=32, fill=0.9):
+    """Index tree bulk load (Sec. 5.3): uint8 array (nodes, 256)."""
+    perm = np.ascontiguousarray(perm, np.uint32)
+    total = sum(tree_shape(k.n, fill))
+    nodes = np.zeros((max(total, 1), TREE_NODE), np.uint8)
+    rc = _load().oracle_bulk_load(*k.args(), _ptr(perm), pk, fill, _ptr(nodes))
+    assert rc == 0
+    return nodes[:total]
 
 
 # ------------------------------------------------------------ CDF model --

@@ -374,6 +374,138 @@ int oracle_insert(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Index tree bulk load (Sec. 5.3, index construction).                       */
+/*                                                                            */
+/* Sorted keys fill 256-byte nodes bottom-up: leaves of at most 14 entries of */
+/* 16 bytes (24-byte header plus an 8-byte next pointer: (256-32)/16 = 14),   */
+/* inner nodes of at most 9 entries of 24 bytes; each node is filled with     */
+/* floor(fanout * fill) entries, the last node of a level with the rest.      */
+/* Node layout (little-endian; unused bytes zero):                            */
+/*   header: high rid u64 @0, count u16 @8, level u16 @10 (0 = leaf),         */
+/*           zero u32 @12, sorted position of the node's first key u64 @16    */
+/*   leaf:   next leaf's node index u64 @24 (all ones for the last leaf),     */
+/*           entries @32: partial key u32, D position u16, key length u16,    */
+/*           record ID u64                                                    */
+/*   inner:  entries @24: partial key u32, D position u16, key length u16,    */
+/*           child node index u64, child's highest key's record ID u64        */
+/* Levels are stored leaves first, each level's nodes in key order; the      */
+/* children of an inner node are consecutive nodes of the level below.        */
+/* An entry's D position is that of its key against the previous entry's key  */
+/* at the same level (0xFFFF: first entry of the level; 0xFFFE: equal keys).  */
+/* Its partial key is the pk bits after that position (Sec. 4.2), MSB-first   */
+/* and left-aligned in 32 bits; the first entry takes the key's first pk      */
+/* bits, an entry equal to its predecessor all zeros.                         */
+/* ------------------------------------------------------------------------- */
+
+#define TREE_NODE 256
+#define TREE_LEAF_FANOUT 14
+#define TREE_INNER_FANOUT 9
+#define TREE_MAX_LEVELS 32
+
+static void put16(uint8_t *p, uint16_t v) { for (int b = 0; b < 2; ++b) p[b] = (uint8_t)(v >> (8 * b)); }
+static void put32(uint8_t *p, uint32_t v) { for (int b = 0; b < 4; ++b) p[b] = (uint8_t)(v >> (8 * b)); }
+static void put64(uint8_t *p, uint64_t v) { for (int b = 0; b < 8; ++b) p[b] = (uint8_t)(v >> (8 * b)); }
+
+/* Entries per node for a fill factor in (0, 1]. */
+void oracle_tree_fill(double fill, uint32_t *leaf_per, uint32_t *inner_per)
+{
+    uint32_t a = (uint32_t)floor(TREE_LEAF_FANOUT * fill), b = (uint32_t)floor(TREE_INNER_FANOUT * fill);
+    *leaf_per = a < 1 ? 1 : a;
+    *inner_per = b < 2 ? 2 : b;
+}
+
+/* Nodes per level (leaves first); returns the height (0 for n == 0). */
+uint32_t oracle_tree_shape(uint64_t n, double fill, uint64_t *level_nodes)
+{
+    uint32_t lp, ip, h = 0;
+    oracle_tree_fill(fill, &lp, &ip);
+    if (n == 0) return 0;
+    uint64_t nodes = (n + lp - 1) / lp;
+    level_nodes[h++] = nodes;
+    while (nodes > 1) {
+        nodes = (nodes + ip - 1) / ip;
+        level_nodes[h++] = nodes;
+    }
+    return h;
+}
+
+static uint16_t entry_dpos(const keyset *k, int first, uint64_t prev_row, uint64_t row)
+{
+    if (first) return 0xFFFF;
+    int64_t d = key_dbit(k, prev_row, row);
+    return d < 0 ? 0xFFFE : (uint16_t)d;
+}
+
+static uint32_t partial_key(const keyset *k, uint64_t row, uint16_t dpos, uint32_t pk)
+{
+    if (dpos == 0xFFFE) return 0;
+    uint32_t start = dpos == 0xFFFF ? 0 : (uint32_t)dpos + 1, v = 0;
+    for (uint32_t t = 0; t < pk; ++t) {
+        uint32_t p = start + t;
+        if (p < 8 * k->L && key_bit(k, row, p)) v |= 1u << (31 - t);
+    }
+    return v;
+}
+
+static uint16_t key_length(const keyset *k, uint64_t row)
+{
+    uint32_t len;
+    key_ptr(k, row, &len);
+    return (uint16_t)(len < k->L ? len : k->L);
+}
+
+/* nodes: (sum of level_nodes) * 256 bytes, written completely. */
+int oracle_bulk_load(const uint8_t *bytes, const uint64_t *offsets, uint64_t n,
+                     uint32_t L, uint32_t stride, const uint32_t *perm, uint32_t pk,
+                     double fill, uint8_t *nodes)
+{
+    keyset k = {bytes, offsets, n, L, stride};
+    uint64_t level_nodes[TREE_MAX_LEVELS], first[TREE_MAX_LEVELS], span[TREE_MAX_LEVELS];
+    uint32_t lp, ip, h = oracle_tree_shape(n, fill, level_nodes);
+    oracle_tree_fill(fill, &lp, &ip);
+    uint64_t total = 0;
+    for (uint32_t l = 0; l < h; ++l) {
+        first[l] = total;
+        total += level_nodes[l];
+        span[l] = l == 0 ? lp : span[l - 1] * ip; /* keys under a full node of level l */
+    }
+    memset(nodes, 0, total * TREE_NODE);
+    for (uint32_t l = 0; l < h; ++l) {
+        for (uint64_t j = 0; j < level_nodes[l]; ++j) {
+            uint8_t *nd = nodes + (first[l] + j) * TREE_NODE;
+            uint64_t lo = j * span[l], hi = (j + 1) * span[l] < n ? (j + 1) * span[l] : n;
+            uint64_t per = l == 0 ? lp : ip;
+            uint64_t below = l == 0 ? n : level_nodes[l - 1];       /* entries of this level */
+            uint64_t e0 = j * per, e1 = e0 + per < below ? e0 + per : below;
+            put64(nd + 0, perm[hi - 1]);
+            put16(nd + 8, (uint16_t)(e1 - e0));
+            put16(nd + 10, (uint16_t)l);
+            put64(nd + 16, lo);
+            if (l == 0) put64(nd + 24, j + 1 < level_nodes[0] ? j + 1 : ~0ull);
+            for (uint64_t e = e0; e < e1; ++e) {
+                /* the entry's key: sorted position e (leaf) or the highest key of child e */
+                uint64_t pos = l == 0 ? e : ((e + 1) * span[l - 1] < n ? (e + 1) * span[l - 1] : n) - 1;
+                uint64_t ppos = 0;
+                if (e > 0) ppos = l == 0 ? e - 1 : e * span[l - 1] - 1;
+                uint64_t row = perm[pos];
+                uint16_t dp = entry_dpos(&k, e == 0, e > 0 ? perm[ppos] : 0, row);
+                uint8_t *en = l == 0 ? nd + 32 + (e - e0) * 16 : nd + 24 + (e - e0) * 24;
+                put32(en + 0, partial_key(&k, row, dp, pk));
+                put16(en + 4, dp);
+                put16(en + 6, key_length(&k, row));
+                if (l == 0) {
+                    put64(en + 8, row);
+                } else {
+                    put64(en + 8, first[l - 1] + e);
+                    put64(en + 16, row);
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* CDF model for learned bucketing (not in the paper; the model of the       */
 /* learned bucketing extension).  fp64 reference of a 4 -> H -> 1 ReLU MLP.  */
 /* Parameter vector p (length 6H + 1):                                        */
