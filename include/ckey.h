@@ -227,6 +227,71 @@ ckey_status ckey_insert_keys(const ckey_keys *index, const uint32_t *index_order
                              uint32_t *flags, void *workspace, size_t *workspace_bytes,
                              void *stream);
 
+/* ---- Index tree bulk load (Sec. 5.3, index construction) ---------------------
+ * The sorted output of a rebuild filled bottom-up into the paper's index tree:
+ * 256-byte nodes with a 24-byte header; leaves hold up to 14 entries of 16
+ * bytes (after an 8-byte next pointer), inner nodes up to 9 entries of 24
+ * bytes.  A full node holds floor(fanout * fill) entries (at least 1 in a
+ * leaf, 2 in an inner node); the last node of a level holds the rest.  Levels
+ * are stored leaves first, each in key order, so node indexes are positions
+ * in the caller's node array.  Layout (little-endian, unused bytes zero):
+ *   header: record ID of the node's highest key u64 @0, entry count u16 @8,
+ *           level u16 @10 (0 = leaf), zero u32 @12, sorted position of the
+ *           node's first key u64 @16
+ *   leaf:   next leaf's node index u64 @24 (all ones for the last leaf),
+ *           entries @32: partial key u32, D position u16, key length u16,
+ *           record ID u64
+ *   inner:  entries @24: partial key u32, D position u16, key length u16,
+ *           child node index u64, record ID of the child's highest key u64
+ * An entry's D position is that of its key against the previous entry's key
+ * on the same level (CKEY_DPOS_FIRST for a level's first entry,
+ * CKEY_DPOS_EQUAL for a key equal to the previous one); its partial key
+ * (Sec. 4.2) is the pk bits after that position, MSB-first, left-aligned in
+ * 32 bits (the first entry: the key's first pk bits; an equal key: 0). */
+#define CKEY_TREE_NODE_BYTES 256u
+#define CKEY_TREE_LEAF_FANOUT 14u
+#define CKEY_TREE_INNER_FANOUT 9u
+#define CKEY_TREE_MAX_LEVELS 32u
+#define CKEY_DPOS_FIRST 0xFFFFu
+#define CKEY_DPOS_EQUAL 0xFFFEu
+
+typedef struct {
+    uint32_t height;          /* levels, leaves included (0 for n == 0)        */
+    uint32_t leaf_entries;    /* entries of a full leaf                        */
+    uint32_t inner_entries;   /* entries of a full inner node                  */
+    uint32_t reserved;
+    uint64_t level_nodes[CKEY_TREE_MAX_LEVELS]; /* nodes per level, leaves first */
+    uint64_t level_first[CKEY_TREE_MAX_LEVELS]; /* index of each level's first node */
+    uint64_t total_nodes;     /* the node array holds total_nodes * 256 bytes  */
+} ckey_tree_shape;
+
+/* Host only: the tree's shape for n keys and a fill factor in (0, 1]. */
+ckey_status ckey_tree_plan(uint64_t n, float fill, ckey_tree_shape *shape);
+
+typedef struct {
+    ckey_keys keys;           /* the index's keys (lengths; bits read by record ID) */
+    const uint32_t *perm;     /* device uint32[n]: rows in key order               */
+    const uint64_t *ckeys;    /* device uint64[words*n]: the sorted compressed keys */
+    uint32_t words;
+    const uint8_t *cbitmap;   /* host, key_bytes: the bitmap ckeys were made with   */
+    const uint32_t *pair_pos; /* device uint32[n-1]: the rebuild's per-pair D positions */
+    const uint8_t *variant;   /* host, key_bytes, or NULL                           */
+    const uint8_t *ref;       /* device, key_bytes: reference key (with variant)    */
+} ckey_tree_input;
+
+/* Build the tree into `nodes` (device, shape.total_nodes * 256 bytes) from a
+ * rebuild's outputs: perm, the sorted compressed keys and pair_pos of
+ * ckey_rebuild_index (made with cbitmap).  Each partial-key bit is taken as
+ * Sec. 5.3 lists: from the compressed key when cbitmap has its position, from
+ * the reference key when the variant bitmap has 0 there, else from the key
+ * itself by record ID (option b).  Without a variant bitmap every position
+ * outside cbitmap is read from the key.  deref (device uint64, or NULL) is
+ * increased by the number of entries that read their key.  pk_bits: 1..32.
+ * Leaf D positions come from pair_pos; inner ones from the level below
+ * (Lemma 1).  Workspace: 4 * key_bytes (query with workspace == NULL). */
+ckey_status ckey_bulk_load(const ckey_tree_input *in, uint32_t pk_bits, float fill, void *nodes,
+                           uint64_t *deref, void *workspace, size_t *workspace_bytes, void *stream);
+
 /* ---- CDF model for learned bucketing (an extension; not in the paper) -------
  * Model memory is device memory owned by the caller, ckey_cdf_model_bytes()
  * long, 256-byte aligned: a 4 -> 64 -> 1 ReLU MLP (385 fp32 parameters, plus

@@ -206,7 +206,13 @@ def insert(k, order, ins, dbitmap, variant=None, ref_row=0):
 TREE_NODE = 256
 
 
+def _f32(fill):
+    """The fill factor as the library receives it (a C float)."""
+    return float(np.float32(fill))
+
+
 def tree_fill(fill):
+    fill = _f32(fill)
     a, b = ctypes.c_uint32(), ctypes.c_uint32()
     _load().oracle_tree_fill(fill, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
@@ -215,7 +221,7 @@ def tree_fill(fill):
 def tree_shape(n, fill):
     """Nodes per level, leaves first (Sec. 5.3)."""
     lv = np.zeros(32, np.uint64)
-    h = _load().oracle_tree_shape(n, fill, _ptr(lv))
+    h = _load().oracle_tree_shape(n, _f32(fill), _ptr(lv))
     return [int(x) for x in lv[:h]]
 
 
@@ -224,7 +230,7 @@ def bulk_load(k, perm, pk=32, fill=0.9):
     perm = np.ascontiguousarray(perm, np.uint32)
     total = sum(tree_shape(k.n, fill))
     nodes = np.zeros((max(total, 1), TREE_NODE), np.uint8)
-    rc = _load().oracle_bulk_load(*k.args(), _ptr(perm), pk, fill, _ptr(nodes))
+    rc = _load().oracle_bulk_load(*k.args(), _ptr(perm), pk, _f32(fill), _ptr(nodes))
     assert rc == 0
     return nodes[:total]
 

@@ -47,6 +47,19 @@ class ckey_index_desc(ctypes.Structure):
                 ("opts", ctypes.POINTER(ckey_sort_opts))]
 
 
+class ckey_tree_shape(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_uint32), ("leaf_entries", ctypes.c_uint32),
+                ("inner_entries", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("level_nodes", ctypes.c_uint64 * 32), ("level_first", ctypes.c_uint64 * 32),
+                ("total_nodes", ctypes.c_uint64)]
+
+
+class ckey_tree_input(ctypes.Structure):
+    _fields_ = [("keys", ckey_keys), ("perm", ctypes.c_void_p), ("ckeys", ctypes.c_void_p),
+                ("words", ctypes.c_uint32), ("cbitmap", ctypes.c_void_p), ("pair_pos", ctypes.c_void_p),
+                ("variant", ctypes.c_void_p), ("ref", ctypes.c_void_p)]
+
+
 class ckey_cdf_train_opts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
@@ -79,6 +92,8 @@ def _load():
     lib.ckey_variant_bitmap.argtypes = [ctypes.POINTER(ckey_keys), P, P, P, P, P, SZP, P]
     lib.ckey_insert_keys.argtypes = [ctypes.POINTER(ckey_keys), P, ctypes.POINTER(ckey_keys), P, P, P, P,
                                      P, P, SZP, P]
+    lib.ckey_tree_plan.argtypes = [U64, ctypes.c_float, ctypes.POINTER(ckey_tree_shape)]
+    lib.ckey_bulk_load.argtypes = [ctypes.POINTER(ckey_tree_input), U32, ctypes.c_float, P, P, P, SZP, P]
     lib.ckey_cdf_model_bytes.argtypes = [U32]
     lib.ckey_cdf_model_bytes.restype = ctypes.c_size_t
     lib.ckey_cdf_model_init.argtypes = [P, U32, U64, P]
@@ -92,7 +107,7 @@ def _load():
     lib.ckey_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
     for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
                "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch",
-               "ckey_graph_destroy", "ckey_tune_index", "ckey_variant_bitmap", "ckey_insert_keys", "ckey_cdf_model_init", "ckey_cdf_fit",
+               "ckey_graph_destroy", "ckey_tune_index", "ckey_variant_bitmap", "ckey_insert_keys", "ckey_tree_plan", "ckey_bulk_load", "ckey_cdf_model_init", "ckey_cdf_fit",
                "ckey_cdf_grad", "ckey_cdf_bucket", "ckey_profile_enable", "ckey_profile_read",
                "ckey_profile_reset", "ckey_bench_copy"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -231,6 +246,46 @@ def ckey_insert_keys(index, index_order, batch, dbitmap, variant=None, ref=None,
         ctypes.byref(ik), _ptr(index_order), ctypes.byref(bk), _ptr(batch_order), _ptr(dbitmap),
         _ptr(variant), _ptr(ref), _ptr(flags), _ptr(ws), ctypes.byref(need), _stream(stream)))
     return dbitmap, variant
+
+
+TREE_NODE_BYTES = 256
+DPOS_FIRST, DPOS_EQUAL = 0xFFFF, 0xFFFE
+
+
+def ckey_tree_plan(n, fill=0.9):
+    """Shape of the index tree for n keys (host only)."""
+    sh = ckey_tree_shape()
+    _check("ckey_tree_plan", _lib.ckey_tree_plan(n, fill, ctypes.byref(sh)))
+    h = sh.height
+    return {"height": h, "leaf_entries": sh.leaf_entries, "inner_entries": sh.inner_entries,
+            "level_nodes": list(sh.level_nodes[:h]), "level_first": list(sh.level_first[:h]),
+            "total_nodes": sh.total_nodes}
+
+
+def ckey_bulk_load(keys, perm, ckeys, cbitmap, pair_pos, pk=32, fill=0.9, variant=None, ref=None,
+                   nodes=None, deref=None, stream=None):
+    """Index tree (Sec. 5.3) from a rebuild's outputs: perm, the sorted
+    compressed keys (words, n) made with host bitmap ``cbitmap``, and pair_pos.
+    Returns (nodes: uint8 device tensor (total_nodes, 256), deref: int64[1])."""
+    cb, cbp = _host_bitmap(cbitmap)
+    var, varp = (None, None) if variant is None else _host_bitmap(variant)
+    dev = keys.data.device
+    shape = ckey_tree_plan(keys.n, fill)
+    if nodes is None:
+        nodes = torch.empty((shape["total_nodes"], TREE_NODE_BYTES), dtype=torch.uint8, device=dev)
+    if deref is None:
+        deref = torch.zeros(1, dtype=torch.int64, device=dev)
+    inp = ckey_tree_input(keys.c_struct(), perm.data_ptr() if keys.n else None,
+                          ckeys.data_ptr() if keys.n else None, ckeys.shape[0], cbp,
+                          pair_pos.data_ptr() if pair_pos is not None and pair_pos.numel() else None,
+                          varp, None if ref is None else ref.data_ptr())
+    need = ctypes.c_size_t(0)
+    _check("ckey_bulk_load", _lib.ckey_bulk_load(ctypes.byref(inp), pk, fill, None, None, None,
+                                                 ctypes.byref(need), None))
+    ws = _workspace(need.value, dev)
+    _check("ckey_bulk_load", _lib.ckey_bulk_load(ctypes.byref(inp), pk, fill, _ptr(nodes), _ptr(deref),
+                                                 _ptr(ws), ctypes.byref(need), _stream(stream)))
+    return nodes, deref
 
 
 def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, stream=None):

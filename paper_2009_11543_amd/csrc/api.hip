@@ -347,6 +347,42 @@ ckey_status ckey_insert_keys(const ckey_keys *index, const uint32_t *index_order
     return CKEY_OK;
 }
 
+ckey_status ckey_tree_plan(uint64_t n, float fill, ckey_tree_shape *shape) {
+    if (!shape || !(fill > 0.0f && fill <= 1.0f)) return CKEY_ERR_INVALID;
+    if (n > CKEY_MAX_ROWS) return CKEY_ERR_UNSUPPORTED;
+    const TreePlan t = tree_plan(n, fill);
+    memset(shape, 0, sizeof(*shape));
+    shape->height = t.height;
+    shape->leaf_entries = t.leaf_entries;
+    shape->inner_entries = t.inner_entries;
+    for (uint32_t l = 0; l < t.height; ++l) {
+        shape->level_nodes[l] = t.level_nodes[l];
+        shape->level_first[l] = t.level_first[l];
+    }
+    shape->total_nodes = t.total_nodes;
+    return CKEY_OK;
+}
+
+ckey_status ckey_bulk_load(const ckey_tree_input *in, uint32_t pk_bits, float fill, void *nodes,
+                           uint64_t *deref, void *ws, size_t *ws_bytes, void *stream) {
+    if (!in) return CKEY_ERR_INVALID;
+    CKEY_TRY(check_keys(&in->keys));
+    if (pk_bits < 1 || pk_bits > 32 || !(fill > 0.0f && fill <= 1.0f)) return CKEY_ERR_INVALID;
+    const uint32_t L = in->keys.key_bytes;
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, tree_workspace(L), query));
+    if (query) return CKEY_OK;
+    const uint64_t n = in->keys.n;
+    if (n == 0) return CKEY_OK;
+    if (!nodes || !in->perm || !in->ckeys || !in->cbitmap || (n > 1 && !in->pair_pos)) return CKEY_ERR_INVALID;
+    if (in->variant && !in->ref) return CKEY_ERR_INVALID;
+    if (in->words < words_for(popcount_bitmap(in->cbitmap, L))) return CKEY_ERR_INVALID;
+    const TreePlan t = tree_plan(n, fill);
+    return bulk_load_launch(key_src(&in->keys), in->perm, in->ckeys, in->cbitmap, in->pair_pos,
+                            in->variant, in->ref, pk_bits, t, nodes,
+                            reinterpret_cast<unsigned long long *>(deref), ws, as_stream(stream));
+}
+
 ckey_status ckey_compress(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
                           uint32_t words, uint32_t *rowids, uint32_t *flags, void *stream) {
     CKEY_TRY(check_keys(keys));

@@ -112,6 +112,22 @@ ckey_status insert_launch(const KeySrc &ix, const uint32_t *ix_order, const KeyS
                           const uint32_t *bt_order, uint32_t *pos, uint32_t *acc_words,
                           uint32_t *flags, hipStream_t st);
 
+// Index tree bulk load (k_tree.hip).
+struct TreePlan {
+    uint32_t height, leaf_entries, inner_entries;
+    uint64_t level_nodes[CKEY_TREE_MAX_LEVELS];
+    uint64_t level_first[CKEY_TREE_MAX_LEVELS];
+    uint64_t span[CKEY_TREE_MAX_LEVELS];  // keys under a full node of each level (saturating past n)
+    uint64_t total_nodes;
+};
+TreePlan tree_plan(uint64_t n, float fill);
+size_t tree_workspace(uint32_t L);
+ckey_status bulk_load_launch(const KeySrc &k, const uint32_t *perm, const uint64_t *ckeys,
+                             const uint8_t *cbitmap_host, const uint32_t *pair_pos,
+                             const uint8_t *variant_host, const uint8_t *ref, uint32_t pk,
+                             const TreePlan &t, void *nodes, unsigned long long *deref, void *ws,
+                             hipStream_t st);
+
 // Refresh of the D-bitmap from sorted compressed keys (k_refine.hip).
 ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
                           const uint8_t *bitmap_in_host, uint32_t L, uint32_t *acc_words,
