@@ -241,7 +241,8 @@ def bench_zipf(args, torch, ckey, dev):
     print(json.dumps(out), flush=True)
 
 
-def bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev, batch_rows):
+def bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev, batch_rows, model_opts=None,
+                      method_name="radix", model_for=None):
     """DS-metadata calls at the workload's size (Sec. 4.3): the variant bitmap,
     a first build that takes the variant bitmap (a sort-free superset of D) in
     place of the all-ones bitmap, and a batched insert into the index."""
@@ -271,17 +272,64 @@ def bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev, batch_rows):
                              "d_popcount": int(np.unpackbits(np.asarray(d_bitmap)).sum())}
     log(f"variant bitmap: {ms:.3f} ms, |V|={out['variant_bitmap']['popcount']}")
 
+    # A CDF model for keys compressed with the variant bitmap (the first word
+    # differs from the D-compressed one), trained like the main one.
+    model_opts_v = None
+    vname = "radix"
+    if model_opts is not None and model_for is not None:
+        model_opts_v = dict(model_opts)
+        model_opts_v["model"] = model_for(v_host)
+        vname = method_name
+
     res = {}
 
     def first_build():
-        res["o"] = ckey.ckey_rebuild_index([{"keys": keys, "bitmap": v_host}])[0]
+        res["o"] = ckey.ckey_rebuild_index([{"keys": keys, "bitmap": v_host, "opts": model_opts_v}])[0]
     ms_fb = ev_time(first_build, 2)
     assert torch.equal(res["o"]["perm"], ridf), "first build from the variant bitmap: order differs"
     assert (res["o"]["bitmap"].cpu().numpy() == d_bitmap).all(), "first build: D differs"
     out["first_build_from_variant"] = {
         "ms": ms_fb + ms, "keys_per_s": n / ((ms_fb + ms) / 1e3),
-        "what": "ckey_variant_bitmap + ckey_rebuild_index(bitmap = variant, radix): perm and exact D"}
+        "what": f"ckey_variant_bitmap + ckey_rebuild_index(bitmap = variant, {vname}): perm and exact D"}
     log(f"first build via variant bitmap: {ms_fb + ms:.2f} ms")
+    del res
+
+    # Index reconstruction end to end (Sec. 5): a rebuild (compress, sort,
+    # refreshed D, per-pair positions), then the tree (Sec. 5.3).  Partial-key
+    # bits outside the compression bitmap are either read from the key by
+    # record ID (option b, compression bitmap D) or not needed because the
+    # compression bitmap is the variant bitmap, a superset of D that sorts the
+    # same (option a).
+    shape = ckey.ckey_tree_plan(n, 0.9)
+    recon = {"tree_height": shape["height"], "tree_nodes": shape["total_nodes"]}
+    tree = {}
+    for label, cbm, mo, mname in (("option_b_D", np.asarray(d_bitmap), model_opts, method_name),
+                                  ("option_a_variant", v_host, model_opts_v, vname)):
+        rb = {}
+
+        def rebuild():
+            rb["o"] = ckey.ckey_rebuild_index([{"keys": keys, "bitmap": cbm, "want_pair_pos": True,
+                                                "want_ckeys": True, "opts": mo}])[0]
+        ms_rb = ev_time(rebuild, 3)
+        o = rb["o"]
+        assert torch.equal(o["perm"], ridf)
+        assert (o["bitmap"].cpu().numpy() == d_bitmap).all()
+
+        def bulk():
+            tree["nodes"], tree["deref"] = ckey.ckey_bulk_load(keys, o["perm"], o["ckeys"], cbm, o["pair_pos"],
+                                                               pk=32, fill=0.9, variant=v_host, ref=var["r"],
+                                                               nodes=tree.get("nodes"))
+        ms_bl = ev_time(bulk, 3)
+        recon[label] = {"rebuild_ms": ms_rb, "bulk_load_ms": ms_bl, "total_ms": ms_rb + ms_bl,
+                        "keys_per_s": n / ((ms_rb + ms_bl) / 1e3), "sort": mname,
+                        "entries_reading_their_key": int(tree["deref"].item())}
+        log(f"index reconstruction ({label}): rebuild {ms_rb:.2f} ms + bulk load {ms_bl:.2f} ms")
+        del rb, o
+    del tree
+    recon["what"] = ("ckey_rebuild_index + ckey_bulk_load (pk 32, fill 0.9, variant bitmap and reference key); "
+                     "option_b_D: compression bitmap D, partial-key bits outside it read by record ID; "
+                     "option_a_variant: compression bitmap = variant bitmap")
+    out["index_reconstruction"] = recon
 
     bk = ckey.DeviceKeys(torch.from_numpy(batch_rows).to(dev))
     dbm = torch.from_numpy(np.asarray(d_bitmap).copy()).to(dev)
@@ -501,8 +549,23 @@ def main():
     }
     if not args.no_maintenance and full is not None:
         del ck, ws
+        mo = None
+        model_for = None
+        if best != "radix":
+            mo = dict(method_opts[best])
+
+            def model_for(bitmap):
+                rows_t = training_rows(args.workload, min(args.train_rows, n))
+                kt = ckey.DeviceKeys(torch.from_numpy(rows_t).to(dev))
+                del rows_t
+                ckt, ridt = ckey.ckey_compress(kt, bitmap)
+                ckey.ckey_sort(ckt, ckey.ckey_plan_query(bitmap)["nbits"], ridt)
+                mv = ckey.CdfModel(bucket_log2=args.bucket_log2, seed=3)
+                ckey.ckey_cdf_fit(mv, ckt[0].contiguous(), steps=args.train_steps, batch=1 << 16)
+                return mv
         out["maintenance"] = bench_maintenance(torch, ckey, keys, ridf, d_bitmap, dev,
-                                               training_rows(args.workload, 1 << 16, seed=5))
+                                               training_rows(args.workload, 1 << 16, seed=5), mo, best,
+                                               model_for)
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_sample} rows")
         out["cpu_baseline"] = cpu_baseline(rows, min(args.cpu_sample, n))

@@ -378,7 +378,7 @@ ckey_status ckey_bulk_load(const ckey_tree_input *in, uint32_t pk_bits, float fi
     if (in->variant && !in->ref) return CKEY_ERR_INVALID;
     if (in->words < words_for(popcount_bitmap(in->cbitmap, L))) return CKEY_ERR_INVALID;
     const TreePlan t = tree_plan(n, fill);
-    return bulk_load_launch(key_src(&in->keys), in->perm, in->ckeys, in->cbitmap, in->pair_pos,
+    return bulk_load_launch(key_src(&in->keys), in->perm, in->ckeys, in->words, in->cbitmap, in->pair_pos,
                             in->variant, in->ref, pk_bits, t, nodes,
                             reinterpret_cast<unsigned long long *>(deref), ws, as_stream(stream));
 }

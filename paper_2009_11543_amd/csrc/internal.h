@@ -123,7 +123,7 @@ struct TreePlan {
 TreePlan tree_plan(uint64_t n, float fill);
 size_t tree_workspace(uint32_t L);
 ckey_status bulk_load_launch(const KeySrc &k, const uint32_t *perm, const uint64_t *ckeys,
-                             const uint8_t *cbitmap_host, const uint32_t *pair_pos,
+                             uint32_t words, const uint8_t *cbitmap_host, const uint32_t *pair_pos,
                              const uint8_t *variant_host, const uint8_t *ref, uint32_t pk,
                              const TreePlan &t, void *nodes, unsigned long long *deref, void *ws,
                              hipStream_t st);

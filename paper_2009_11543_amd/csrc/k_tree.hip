@@ -67,8 +67,17 @@ struct PkArgs {
     const uint32_t *perm;
     const uint64_t *ck;     // sorted compressed keys, word-major
     uint64_t n;
+    uint32_t words;
     const uint8_t *ref;     // device reference key (null: no variant bitmap)
     uint32_t pk;
+};
+
+// Per-workgroup copies of the tables, indexed by key byte.
+struct LdsTables {
+    uint8_t cb[CKEY_MAX_KEY_BYTES];    // compression bitmap
+    uint8_t var[CKEY_MAX_KEY_BYTES];   // variant bitmap (all ones: none given)
+    uint8_t ref[CKEY_MAX_KEY_BYTES];   // reference key
+    uint16_t rank[CKEY_MAX_KEY_BYTES]; // compressed index of each byte's first position
 };
 
 __device__ __forceinline__ uint8_t key_byte_at(const KeySrc &k, uint64_t row, uint32_t j) {
@@ -85,59 +94,96 @@ __device__ __forceinline__ uint16_t key_len_of(const KeySrc &k, uint64_t row) {
     return uint16_t(len < k.L ? len : k.L);
 }
 
-__device__ uint32_t partial_key(const PkArgs &a, const uint8_t *s_cb, const uint8_t *s_var,
-                                const uint16_t *s_rank, uint64_t pos, uint64_t row, uint16_t dpos,
-                                bool &deref) {
+// The 32 bits at positions [start, start+32) of the key at sorted position pos
+// (row `row`), assembled byte by byte over the (at most five) key bytes the
+// window touches: class-A bits deposited from the compressed key's run of
+// bits, class-B bits from the reference key, class-C bits from the key.
+__device__ uint32_t partial_key(const PkArgs &a, const LdsTables &t, uint64_t pos, uint64_t row,
+                                uint16_t dpos, bool &deref) {
     if (dpos == kEqual) return 0u;
     const uint32_t start = dpos == kFirst ? 0u : uint32_t(dpos) + 1u;
-    const uint32_t nbit = 8 * a.keys.L;
-    uint32_t v = 0;
-    for (uint32_t t = 0; t < a.pk; ++t) {
-        const uint32_t p = start + t;
-        if (p >= nbit) break;
-        const uint32_t byte = p >> 3, sh = p & 7u, m = 0x80u >> sh;
-        const uint32_t cbb = s_cb[byte];
-        uint32_t bit;
-        if (cbb & m) {  // A: in the compressed key
-            const uint32_t c = s_rank[byte] + (sh ? __popc(cbb >> (8 - sh)) : 0u);
-            bit = uint32_t(a.ck[uint64_t(c >> 6) * a.n + pos] >> (63 - (c & 63u))) & 1u;
-        } else if (!(s_var[byte] & m)) {  // B: invariant, from the reference key
-            bit = (uint32_t(a.ref[byte]) >> (7 - sh)) & 1u;
-        } else {  // C: from the key (dereference by record ID)
-            bit = (uint32_t(key_byte_at(a.keys, row, byte)) >> (7 - sh)) & 1u;
-            deref = true;
+    const uint32_t L = a.keys.L;
+    if (start >= 8 * L) return 0u;
+    const uint32_t b0 = start >> 3, sh = start & 7u;
+    uint32_t cbq[5], varq[5], wm[5];
+    uint32_t c_any = 0, a_any = 0;
+    const uint32_t end = min(start + a.pk, 8 * L);  // window [start, end)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const uint32_t j = b0 + q;
+        const uint32_t lo = max(start, 8 * j), hi = min(end, 8 * j + 8);  // window bits of byte j
+        wm[q] = lo < hi ? (0xFFu >> (lo - 8 * j)) & ~(0xFFu >> (hi - 8 * j)) & 0xFFu : 0u;
+        cbq[q] = j < L ? uint32_t(t.cb[j]) : 0u;
+        varq[q] = j < L ? uint32_t(t.var[j]) : 0u;
+        c_any |= varq[q] & ~cbq[q] & wm[q];
+        a_any |= cbq[q] & wm[q];
+    }
+    uint32_t keyq[5] = {0, 0, 0, 0, 0};
+    if (c_any) {  // option C (b): read the key by record ID
+        deref = true;
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+            if (wm[q]) keyq[q] = key_byte_at(a.keys, row, b0 + q);
+    }
+    uint32_t F = 0;  // the compressed key's bits from the window's first class-A position on
+    if (a_any) {
+        const uint32_t c0 = uint32_t(t.rank[b0]) + __popc(cbq[0] & ~(0xFFu >> sh) & 0xFFu);
+        const uint32_t k0 = c0 >> 6, o = c0 & 63u;
+        const uint64_t w0 = a.ck[uint64_t(k0) * a.n + pos];
+        const uint64_t w1 = (o && k0 + 1 < a.words) ? a.ck[uint64_t(k0 + 1) * a.n + pos] : 0ull;
+        const uint64_t x = o ? (w0 << o) | (w1 >> (64 - o)) : w0;
+        F = uint32_t(x >> 32);
+    }
+    uint64_t v40 = 0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        uint32_t byte = (uint32_t(t.ref[b0 + q < L ? b0 + q : 0]) & ~varq[q]) | (keyq[q] & varq[q] & ~cbq[q]);
+        uint32_t m = cbq[q] & wm[q];
+        while (m) {  // deposit the next compressed bits into this byte's class-A positions
+            const uint32_t hb = 31u - __clz(m);
+            byte |= (F >> 31) << hb;
+            F <<= 1;
+            m &= ~(1u << hb);
         }
-        v |= bit << (31 - t);
+        v40 = (v40 << 8) | (byte & wm[q]);
     }
-    return v;
+    return uint32_t(v40 >> (8 - sh));  // bits past the window are zero
 }
 
-__device__ __forceinline__ void load_tables(const TreeTables &tt, uint32_t L, uint8_t *s_cb,
-                                            uint8_t *s_var, uint16_t *s_rank) {
+__device__ __forceinline__ void load_tables(const TreeTables &tt, const uint8_t *ref, uint32_t L,
+                                            LdsTables &t) {
     for (uint32_t j = threadIdx.x; j < L; j += blockDim.x) {
-        s_cb[j] = tt.cb[j];
-        s_var[j] = tt.var[j];
-        s_rank[j] = tt.rank[j];
+        t.cb[j] = tt.cb[j];
+        t.var[j] = tt.var[j];
+        t.ref[j] = ref ? ref[j] : uint8_t(0);
+        t.rank[j] = tt.rank[j];
     }
 }
 
-__device__ __forceinline__ void count_deref(bool deref, unsigned long long *cnt) {
-    const uint64_t b = __ballot(deref);
-    if (cnt && (threadIdx.x & 63) == 0 && b) atomicAdd(cnt, (unsigned long long)__popcll(b));
+// One global atomic per workgroup (a single counter shared by the whole grid).
+__device__ __forceinline__ void count_deref(uint32_t mine, uint32_t *s_cnt, unsigned long long *cnt) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt && *s_cnt) atomicAdd(cnt, (unsigned long long)*s_cnt);
 }
+
+constexpr uint32_t kTreeBlocks = 4096;  // grid-stride launches
 
 __global__ __launch_bounds__(kWG) void k_leaf_level(PkArgs a, TreeTables tt,
                                                     const uint32_t *__restrict__ pair_pos,
                                                     uint32_t lp, uint64_t nleaves,
                                                     uint8_t *__restrict__ nodes,
                                                     unsigned long long *__restrict__ deref_cnt) {
-    __shared__ uint8_t s_cb[CKEY_MAX_KEY_BYTES], s_var[CKEY_MAX_KEY_BYTES];
-    __shared__ uint16_t s_rank[CKEY_MAX_KEY_BYTES];
-    load_tables(tt, a.keys.L, s_cb, s_var, s_rank);
+    __shared__ LdsTables s_t;
+    __shared__ uint32_t s_cnt;
+    load_tables(tt, a.ref, a.keys.L, s_t);
+    if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    const uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x;
-    bool deref = false;
-    if (i < a.n) {
+    uint32_t nderef = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x; i < a.n; i += uint64_t(gridDim.x) * kWG) {
+        bool deref = false;
         const uint64_t j = i / lp, slot = i % lp;
         const uint64_t row = a.perm[i];
         uint16_t dpos = kFirst;
@@ -145,7 +191,8 @@ __global__ __launch_bounds__(kWG) void k_leaf_level(PkArgs a, TreeTables tt,
             const uint32_t pp = pair_pos[i - 1];
             dpos = pp == 0xFFFFFFFFu ? kEqual : uint16_t(pp);
         }
-        const uint32_t pkv = partial_key(a, s_cb, s_var, s_rank, i, row, dpos, deref);
+        const uint32_t pkv = partial_key(a, s_t, i, row, dpos, deref);
+        nderef += deref ? 1u : 0u;
         uint64_t *nd = reinterpret_cast<uint64_t *>(nodes + j * kNode);
         nd[4 + 2 * slot] = uint64_t(pkv) | (uint64_t(dpos) << 32) | (uint64_t(key_len_of(a.keys, row)) << 48);
         nd[5 + 2 * slot] = row;
@@ -158,7 +205,7 @@ __global__ __launch_bounds__(kWG) void k_leaf_level(PkArgs a, TreeTables tt,
             for (uint64_t q = 4 + 2 * cnt; q < kNode / 8; ++q) nd[q] = 0;  // unused entries
         }
     }
-    count_deref(deref, deref_cnt);
+    count_deref(nderef, &s_cnt, deref_cnt);
 }
 
 // Level l >= 1: one thread per child node e of level l-1.
@@ -168,13 +215,14 @@ __global__ __launch_bounds__(kWG) void k_inner_level(PkArgs a, TreeTables tt, ui
                                                      uint64_t span, uint64_t first,
                                                      uint8_t *__restrict__ nodes,
                                                      unsigned long long *__restrict__ deref_cnt) {
-    __shared__ uint8_t s_cb[CKEY_MAX_KEY_BYTES], s_var[CKEY_MAX_KEY_BYTES];
-    __shared__ uint16_t s_rank[CKEY_MAX_KEY_BYTES];
-    load_tables(tt, a.keys.L, s_cb, s_var, s_rank);
+    __shared__ LdsTables s_t;
+    __shared__ uint32_t s_cnt;
+    load_tables(tt, a.ref, a.keys.L, s_t);
+    if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    const uint64_t e = uint64_t(blockIdx.x) * kWG + threadIdx.x;
-    bool deref = false;
-    if (e < nchildren) {
+    uint32_t nderef = 0;
+    for (uint64_t e = uint64_t(blockIdx.x) * kWG + threadIdx.x; e < nchildren; e += uint64_t(gridDim.x) * kWG) {
+        bool deref = false;
         const uint64_t j = e / ip, slot = e % ip;
         const uint64_t pos = min<uint64_t>(a.n, (e + 1) * child_span) - 1;  // child's highest key
         const uint64_t row = a.perm[pos];
@@ -189,7 +237,8 @@ __global__ __launch_bounds__(kWG) void k_inner_level(PkArgs a, TreeTables tt, ui
                 dpos = d < dpos ? d : dpos;
             }
         }
-        const uint32_t pkv = partial_key(a, s_cb, s_var, s_rank, pos, row, dpos, deref);
+        const uint32_t pkv = partial_key(a, s_t, pos, row, dpos, deref);
+        nderef += deref ? 1u : 0u;
         uint64_t *nd = reinterpret_cast<uint64_t *>(nodes + (first + j) * kNode);
         nd[3 + 3 * slot] = uint64_t(pkv) | (uint64_t(dpos) << 32) | (uint64_t(key_len_of(a.keys, row)) << 48);
         nd[4 + 3 * slot] = child_first + e;
@@ -202,7 +251,7 @@ __global__ __launch_bounds__(kWG) void k_inner_level(PkArgs a, TreeTables tt, ui
             for (uint64_t q = 3 + 3 * cnt; q < kNode / 8; ++q) nd[q] = 0;  // unused entries, pad
         }
     }
-    count_deref(deref, deref_cnt);
+    count_deref(nderef, &s_cnt, deref_cnt);
 }
 
 }  // namespace
@@ -233,7 +282,7 @@ TreePlan tree_plan(uint64_t n, float fill) {
 size_t tree_workspace(uint32_t L) { return align256(size_t(L) * 4); }
 
 ckey_status bulk_load_launch(const KeySrc &k, const uint32_t *perm, const uint64_t *ck,
-                             const uint8_t *cbitmap_host, const uint32_t *pair_pos,
+                             uint32_t words, const uint8_t *cbitmap_host, const uint32_t *pair_pos,
                              const uint8_t *variant_host, const uint8_t *ref, uint32_t pk,
                              const TreePlan &t, void *nodes, unsigned long long *deref, void *ws,
                              hipStream_t st) {
@@ -247,17 +296,17 @@ ckey_status bulk_load_launch(const KeySrc &k, const uint32_t *perm, const uint64
     for (uint32_t j = 0; j < CKEY_MAX_KEY_BYTES; ++j) bm.b[j] = j < L ? (variant_host ? variant_host[j] : 0xFF) : 0;
     hipLaunchKernelGGL(k_tree_table, dim3(1), dim3(kWG), 0, st, bm, L, tt.var, nullptr);
     CKEY_TRY(launch_status());
-    PkArgs a{k, perm, ck, k.n, ref, pk};
+    PkArgs a{k, perm, ck, k.n, words, ref, pk};
     uint8_t *nd = static_cast<uint8_t *>(nodes);
     const int pr = prof_begin(st, "tree_leaves");
-    hipLaunchKernelGGL(k_leaf_level, dim3(uint32_t((k.n + kWG - 1) / kWG)), dim3(kWG), 0, st, a, tt,
+    hipLaunchKernelGGL(k_leaf_level, dim3(uint32_t(min<uint64_t>(kTreeBlocks, (k.n + kWG - 1) / kWG))), dim3(kWG), 0, st, a, tt,
                        pair_pos, t.leaf_entries, t.level_nodes[0], nd, deref);
     prof_end(st, pr);
     CKEY_TRY(launch_status());
     for (uint32_t l = 1; l < t.height; ++l) {
         const uint64_t nch = t.level_nodes[l - 1];
         const int pr2 = prof_begin(st, "tree_inner");
-        hipLaunchKernelGGL(k_inner_level, dim3(uint32_t((nch + kWG - 1) / kWG)), dim3(kWG), 0, st, a, tt, l,
+        hipLaunchKernelGGL(k_inner_level, dim3(uint32_t(min<uint64_t>(kTreeBlocks, (nch + kWG - 1) / kWG))), dim3(kWG), 0, st, a, tt, l,
                            t.inner_entries, nch, t.level_first[l - 1], t.span[l - 1], t.span[l],
                            t.level_first[l], nd, deref);
         prof_end(st, pr2);
