@@ -104,7 +104,22 @@ def cpu_baseline(rows_all, n_sample):
     assert len(perm) == n_sample
     return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample} rows of the workload; oracle compress (bit by bit) + "
-                      f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s"}
+                      f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s"}, d, perm
+
+
+def cpu_rowcol(rows_all, n_sample, d, perm_ref):
+    """The paper's own CPU pipeline on the host cores: PEXT compression (Sec.
+    5.1) and the row-column sort (Appendix A), on the same sample."""
+    from paper_2009_11543_amd import rowcol
+    rows = np.ascontiguousarray(rows_all[:n_sample])
+    threads = min(16, os.cpu_count() or 1)
+    perm, _, t = rowcol.compress_sort(rows, d, threads=threads)
+    assert np.array_equal(perm, perm_ref), "row-column sort order differs from the oracle's"
+    dt = t["compress_s"] + t["sort_s"]
+    return {"value": n_sample / dt, "unit": "keys/s", "cores": threads,
+            "kind": "row-column sort (Appendix A) + PEXT compression (Sec. 5.1)",
+            "sample": f"first {n_sample} rows; compress {t['compress_s']:.3f} s + sort {t['sort_s']:.3f} s "
+                      f"(C = {t['cache_bytes']} B per thread)"}
 
 
 def bench_table(args, torch, ckey, prof, dev):
@@ -568,7 +583,9 @@ def main():
                                                model_for)
     if not args.no_cpu_baseline:
         log(f"cpu baseline on {args.cpu_sample} rows")
-        out["cpu_baseline"] = cpu_baseline(rows, min(args.cpu_sample, n))
+        out["cpu_baseline"], d_s, perm_s = cpu_baseline(rows, min(args.cpu_sample, n))
+        out["cpu_rowcol"] = cpu_rowcol(rows, min(args.cpu_sample, n), d_s, perm_s)
+        log(f"cpu row-column: {out['cpu_rowcol']['value'] / 1e6:.1f} M keys/s on {out['cpu_rowcol']['cores']} threads")
     print(json.dumps(out), flush=True)
 
 
