@@ -24,17 +24,22 @@ struct BucketArgs {
     uint32_t *hist;        // global bucket histogram (added to) or null
 };
 
-// Splitter sample stride.  S == 1 means the top 32 bits of every threshold are
-// held in LDS (B <= 2^14: 64 KB) and the search runs in LDS, reading T itself
-// only where the top halves tie.
+// Splitter sample stride.  S == 1 means every threshold is held in LDS
+// (B <= 2^14: 128 KB) and the search runs in LDS alone.
 inline uint32_t splitter_stride(uint32_t B) {
     if (B <= (1u << 14)) return 1;
     return B / 16 > 2048 ? B / 2048 : 16;
 }
 
+// LDS layout: (splitter) the threshold sample, then (if a.hist) B/2 packed
+// 16-bit counters.
+inline size_t bucket_sample_words(const BucketArgs &a, int amode) {
+    if (amode != 0) return 0;
+    return a.S == 1 ? size_t(a.B) * 2 : size_t(a.B / a.S) * 2;
+}
+
 inline size_t bucket_lds_bytes(const BucketArgs &a, int amode) {
-    const size_t sample = a.S == 1 ? size_t(a.B) * 4 : size_t(a.B / a.S) * 8;
-    return size_t(a.B / 2) * 4 + (amode == 0 ? sample : 0) + 16;
+    return bucket_sample_words(a, amode) * 4 + (a.hist ? size_t(a.B / 2) * 4 : 0);
 }
 
 // Dynamic LDS above 64 KB (B = 2^16) needs the kernel attribute raised once.
@@ -104,17 +109,23 @@ __device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ 
     return lo;
 }
 
-// LDS layout: B/2 packed 16-bit counters, then (splitter) the B/S sample of T.
+template <int AMODE>
+__device__ __forceinline__ uint32_t *bucket_counters(const BucketArgs &a, uint32_t *s) {
+    return s + (AMODE == 0 ? (a.S == 1 ? 2 * a.B : (a.B / a.S) * 2) : 0);
+}
+
 template <int AMODE>
 __device__ __forceinline__ void bucket_lds_init(const BucketArgs &a, uint32_t *s) {
-    if (a.hist)
-        for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) s[t] = 0;
+    if (a.hist) {
+        uint32_t *h = bucket_counters<AMODE>(a, s);
+        for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) h[t] = 0;
+    }
     if (AMODE == 0) {
         if (a.S == 1) {
-            uint32_t *th = s + a.B / 2;
-            for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = uint32_t(a.T[t] >> 32);
+            uint64_t *th = reinterpret_cast<uint64_t *>(s);
+            for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = a.T[t];
         } else {
-            uint64_t *ts = reinterpret_cast<uint64_t *>(s + a.B / 2);
+            uint64_t *ts = reinterpret_cast<uint64_t *>(s);
             for (uint32_t t = threadIdx.x; t < a.B / a.S; t += blockDim.x) ts[t] = a.T[uint64_t(t) * a.S];
         }
     }
@@ -127,24 +138,17 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
         guess = predict_bucket(a.p, x, a.B);
         return correct_bucket(a.T, a.B, x, guess, probes);
     }
-    if (a.S == 1) {  // every threshold's top half in LDS
-        const uint32_t *th = s + a.B / 2;
-        const uint32_t xh = uint32_t(x >> 32);
+    if (a.S == 1) {  // every threshold in LDS
+        const uint64_t *th = reinterpret_cast<const uint64_t *>(s);
         uint32_t lo = 0, hi = a.B;  // T[lo] <= x < T[hi]
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            const uint32_t t = th[mid];
-            bool le = t < xh;
-            if (t == xh) {  // top halves tie: compare the whole threshold
-                ++probes;
-                le = a.T[mid] <= x;
-            }
-            if (le) lo = mid; else hi = mid;
+            if (th[mid] <= x) lo = mid; else hi = mid;
         }
         guess = lo;
         return lo;
     }
-    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s + a.B / 2);
+    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s);
     uint32_t lo = 0, hi = a.B / a.S;  // ts[lo] <= x < ts[hi]
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -160,6 +164,32 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
     return l2;
 }
 
+// Splitter search of several keys at once (every threshold in LDS, S == 1, B a
+// power of two): a fixed log2(B)-step lower bound per key, the keys' steps
+// interleaved so their LDS reads overlap.  b[q] = the largest b with
+// T[b] <= x[q] (T[0] = 0).
+template <int N>
+__device__ __forceinline__ void splitter_search_n(const BucketArgs &a, const uint32_t *s,
+                                                  const uint64_t *x, uint32_t *b) {
+    const uint64_t *th = reinterpret_cast<const uint64_t *>(s);
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] = 0;
+    for (uint32_t step = a.B >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const uint32_t m = b[q] + step;
+            b[q] = th[m] <= x[q] ? m : b[q];
+        }
+    }
+}
+
+template <int AMODE>
+__device__ __forceinline__ void bucket_record(const BucketArgs &a, uint32_t *s, uint32_t b, uint64_t i) {
+    if (a.bid) a.bid[i] = uint16_t(b);
+    if (a.bid32) a.bid32[i] = b;
+    if (a.hist) atomicAdd(&bucket_counters<AMODE>(a, s)[b >> 1], 1u << (16 * (b & 1)));
+}
+
 template <int AMODE>
 __device__ __forceinline__ uint32_t bucket_assign_one(const BucketArgs &a, uint32_t *s, uint64_t x,
                                                       uint64_t i, uint32_t &probes, uint32_t &err) {
@@ -169,7 +199,7 @@ __device__ __forceinline__ uint32_t bucket_assign_one(const BucketArgs &a, uint3
     if (a.bid) a.bid[i] = uint16_t(b);
     if (a.bid32) a.bid32[i] = b;
     if (AMODE == 1 && a.pred) a.pred[i] = guess;
-    if (a.hist) atomicAdd(&s[b >> 1], 1u << (16 * (b & 1)));
+    if (a.hist) atomicAdd(&bucket_counters<AMODE>(a, s)[b >> 1], 1u << (16 * (b & 1)));
     return b;
 }
 
@@ -179,10 +209,12 @@ __device__ __forceinline__ void bucket_assign_one(const BucketArgs &a, uint32_t 
     (void)bucket_assign_one<AMODE>(a, s, x, i, probes, err);
 }
 
-__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, const uint32_t *s) {
+template <int AMODE>
+__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *s) {
     if (!a.hist) return;
+    const uint32_t *h = bucket_counters<AMODE>(a, s);
     for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
-        const uint32_t v = s[t];
+        const uint32_t v = h[t];
         if (v & 0xFFFFu) atomicAdd(&a.hist[2 * t], v & 0xFFFFu);
         if (v >> 16) atomicAdd(&a.hist[2 * t + 1], v >> 16);
     }

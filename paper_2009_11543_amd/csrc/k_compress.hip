@@ -84,7 +84,7 @@ __device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const
             const uint32_t c = c0 + g;
 #pragma unroll
             for (int q = 0; q < 4; ++q) x[g][q] = 0;
-            if (c < plan.n_chunks) ld(plan, c, x[g]);
+            if (c < plan.n_chunks) ld(plan, c, g, x[g]);
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -128,7 +128,7 @@ template <int MODE>
 struct GlobalLoader {
     const uint8_t *p;
     uint32_t len;
-    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, uint32_t *x) const {
+    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, int, uint32_t *x) const {
         const uint32_t cb = plan.chunk[c];
         if (MODE == kLoad16) {
             const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
@@ -192,7 +192,7 @@ struct LdsLoader {
         if (have < 4) v &= ~(0xFFFFFFFFu >> (8 * have));
         return v;
     }
-    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, uint32_t *x) const {
+    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, int, uint32_t *x) const {
         const uint32_t cb = plan.chunk[c];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
@@ -254,11 +254,24 @@ __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan pla
     if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
 }
 
+// Chunks already in registers, for keys of at most four 16-byte chunks (the
+// compress loop then runs one group, whose slot g is the chunk index).
+struct RegLoader {
+    const uint4 *v;
+    __device__ __forceinline__ void operator()(const CompressPlan &, uint32_t, int g, uint32_t *x) const {
+        const uint4 u = v[g];
+        x[0] = __builtin_bswap32(u.x);
+        x[1] = __builtin_bswap32(u.y);
+        x[2] = __builtin_bswap32(u.z);
+        x[3] = __builtin_bswap32(u.w);
+    }
+};
+
 // Compression fused with bucket assignment: each workgroup compresses a
 // range of up to kBucketKeysPerWG keys (grid-stride over its threads), finds
 // each key's bucket from its first compressed word while it is in registers,
 // and keeps a packed 16-bit bucket histogram in LDS.
-template <int MODE, int AMODE>
+template <int MODE, int AMODE, int KPI>
 __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, CompressPlan plan,
                                                                uint64_t *__restrict__ ck,
                                                                uint32_t *__restrict__ rowids,
@@ -268,6 +281,52 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
     __syncthreads();
     const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
     const uint64_t i1 = min<uint64_t>(k.n, i0 + kBucketKeysPerWG);
+    if (KPI > 1) {
+        // kLoad16 keys of at most four chunks, KPI keys per thread per
+        // iteration: every key's loads are issued before any of them is
+        // compressed, so their latencies overlap (a loop waits on its own
+        // stores too, as loads and stores share one in-order counter).
+        const uint64_t last = i1 - 1;
+        for (uint64_t base = i0 + threadIdx.x; base < i1; base += uint64_t(KPI) * kBucketWG) {
+            uint4 kc[KPI][4];
+#pragma unroll
+            for (int q = 0; q < KPI; ++q) {
+                const uint64_t r = min<uint64_t>(base + uint64_t(q) * kBucketWG, last);
+                const uint8_t *p = k.bytes + r * k.stride;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)  // unused slots reload chunk 0: in bounds, ignored
+                    kc[q][c] = *reinterpret_cast<const uint4 *>(p + 16 * plan.chunk[uint32_t(c) < plan.n_chunks ? c : 0]);
+            }
+            uint64_t w0[KPI];
+#pragma unroll
+            for (int q = 0; q < KPI; ++q) {
+                const uint64_t r = base + uint64_t(q) * kBucketWG;
+                w0[q] = 0;
+                if (r < i1) {
+                    w0[q] = compress_key(plan, RegLoader{kc[q]}, ck, k.n, r);
+                    if (plan.write_rowids && rowids) rowids[r] = uint32_t(r);
+                }
+            }
+            if (AMODE == 0 && ba.S == 1) {  // the keys' searches interleaved
+                uint32_t b[KPI];
+                splitter_search_n<KPI>(ba, s_dyn, w0, b);
+#pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_assign_one<AMODE>(ba, s_dyn, w0[q], r);
+                }
+            }
+        }
+        __syncthreads();
+        bucket_lds_flush<AMODE>(ba, s_dyn);
+        return;
+    }
     for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG) {
         GlobalLoader<MODE> ld{k.bytes + i * k.stride, k.L};
         const uint64_t w0 = compress_key(plan, ld, ck, k.n, i);
@@ -275,7 +334,7 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
         bucket_assign_one<AMODE>(ba, s_dyn, w0, i);
     }
     __syncthreads();
-    bucket_lds_flush(ba, s_dyn);
+    bucket_lds_flush<AMODE>(ba, s_dyn);
 }
 
 }  // namespace
@@ -321,24 +380,37 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
     plan.n_chunks = cidx;
     const uint32_t blocks = uint32_t((k.n + kBucketKeysPerWG - 1) / kBucketKeysPerWG);
     const size_t lds = bucket_lds_bytes(ba, amode);
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1>));
+#ifndef CKEY_KPI
+#define CKEY_KPI 4
+#endif
+    constexpr int kKPI = CKEY_KPI;
+    const bool multi = mode == kLoad16 && cidx <= 4;
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, kKPI>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0, 1>));
+    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1, 1>));
     const int pr_ = prof_begin(st, "compress_bucket");
-#define CKEY_LAUNCH_CB(M)                                                                              \
+#define CKEY_LAUNCH_CB(M, KPI)                                                                         \
     if (amode)                                                                                         \
-        hipLaunchKernelGGL((k_compress_bucket<M, 1>), dim3(blocks), dim3(kBucketWG), lds, st, k, plan, \
-                           ck, rowids, ba);                                                            \
+        hipLaunchKernelGGL((k_compress_bucket<M, 1, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
+                           plan, ck, rowids, ba);                                                      \
     else                                                                                               \
-        hipLaunchKernelGGL((k_compress_bucket<M, 0>), dim3(blocks), dim3(kBucketWG), lds, st, k, plan, \
-                           ck, rowids, ba);
+        hipLaunchKernelGGL((k_compress_bucket<M, 0, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
+                           plan, ck, rowids, ba);
     switch (mode) {
-        case kLoad16: CKEY_LAUNCH_CB(kLoad16) break;
-        case kLoad4: CKEY_LAUNCH_CB(kLoad4) break;
-        default: CKEY_LAUNCH_CB(kLoadBytes) break;
+        case kLoad16:
+            if (multi) {
+                CKEY_LAUNCH_CB(kLoad16, kKPI)
+            } else {
+                CKEY_LAUNCH_CB(kLoad16, 1)
+            }
+            break;
+        case kLoad4: CKEY_LAUNCH_CB(kLoad4, 1) break;
+        default: CKEY_LAUNCH_CB(kLoadBytes, 1) break;
     }
 #undef CKEY_LAUNCH_CB
     prof_end(st, pr_);

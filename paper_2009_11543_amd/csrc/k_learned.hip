@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
         (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
     __syncthreads();
-    bucket_lds_flush(ba, s_dyn);
+    bucket_lds_flush<MODE>(ba, s_dyn);
     if (stats) {
         unsigned long long a = probes, e = err;
 #pragma unroll

@@ -171,6 +171,11 @@ __device__ __forceinline__ void count_deref(uint32_t mine, uint32_t *s_cnt, unsi
 
 constexpr uint32_t kTreeBlocks = 4096;  // grid-stride launches
 
+inline uint32_t grid_blocks(uint64_t items) {
+    const uint64_t b = (items + kWG - 1) / kWG;
+    return uint32_t(b < kTreeBlocks ? b : kTreeBlocks);
+}
+
 __global__ __launch_bounds__(kWG) void k_leaf_level(PkArgs a, TreeTables tt,
                                                     const uint32_t *__restrict__ pair_pos,
                                                     uint32_t lp, uint64_t nleaves,
@@ -299,14 +304,14 @@ ckey_status bulk_load_launch(const KeySrc &k, const uint32_t *perm, const uint64
     PkArgs a{k, perm, ck, k.n, words, ref, pk};
     uint8_t *nd = static_cast<uint8_t *>(nodes);
     const int pr = prof_begin(st, "tree_leaves");
-    hipLaunchKernelGGL(k_leaf_level, dim3(uint32_t(min<uint64_t>(kTreeBlocks, (k.n + kWG - 1) / kWG))), dim3(kWG), 0, st, a, tt,
+    hipLaunchKernelGGL(k_leaf_level, dim3(grid_blocks(k.n)), dim3(kWG), 0, st, a, tt,
                        pair_pos, t.leaf_entries, t.level_nodes[0], nd, deref);
     prof_end(st, pr);
     CKEY_TRY(launch_status());
     for (uint32_t l = 1; l < t.height; ++l) {
         const uint64_t nch = t.level_nodes[l - 1];
         const int pr2 = prof_begin(st, "tree_inner");
-        hipLaunchKernelGGL(k_inner_level, dim3(uint32_t(min<uint64_t>(kTreeBlocks, (nch + kWG - 1) / kWG))), dim3(kWG), 0, st, a, tt, l,
+        hipLaunchKernelGGL(k_inner_level, dim3(grid_blocks(nch)), dim3(kWG), 0, st, a, tt, l,
                            t.inner_entries, nch, t.level_first[l - 1], t.span[l - 1], t.span[l],
                            t.level_first[l], nd, deref);
         prof_end(st, pr2);
