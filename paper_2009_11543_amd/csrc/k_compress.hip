@@ -380,10 +380,7 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
     plan.n_chunks = cidx;
     const uint32_t blocks = uint32_t((k.n + kBucketKeysPerWG - 1) / kBucketKeysPerWG);
     const size_t lds = bucket_lds_bytes(ba, amode);
-#ifndef CKEY_KPI
-#define CKEY_KPI 4
-#endif
-    constexpr int kKPI = CKEY_KPI;
+    constexpr int kKPI = 4;  // keys per thread per iteration
     const bool multi = mode == kLoad16 && cidx <= 4;
     set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
     set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, kKPI>));
