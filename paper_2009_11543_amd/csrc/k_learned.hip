@@ -249,6 +249,43 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict
 }
 
 
+// Runs over positions [0, cnt) held thread-contiguously: thread t owns
+// positions [P*t, P*t + P), and bit u of `starts` says that owned position u
+// begins a run (position 0 always does).  Block-wide prefix max of run starts
+// and suffix min of the next run starts (wave shuffles, one LDS exchange) give
+// the thread the start of the run that its first position belongs to (*cs)
+// and the first run start after its positions (*ce, cnt if none).  Every
+// thread of the workgroup calls it; s_x holds 2 * NT/64 ints.
+template <int P, int NT>
+__device__ __forceinline__ void run_carries(uint32_t cnt, uint32_t starts, uint32_t *cs, uint32_t *ce,
+                                            int32_t *s_x) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int32_t j0 = P * tid, kNone = 0x7FFFFFFF;
+    int32_t pm = starts ? j0 + 31 - int32_t(__clz(starts)) : -1;  // last start here
+    int32_t sm = starts ? j0 + int32_t(__ffs(starts)) - 1 : kNone;  // first start here
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t a = __shfl_up(pm, off, 64), b = __shfl_down(sm, off, 64);
+        if (lane >= off) pm = max(pm, a);
+        if (lane + off < 64) sm = min(sm, b);
+    }
+    int32_t pex = __shfl_up(pm, 1, 64), sex = __shfl_down(sm, 1, 64);
+    if (lane == 0) pex = -1;
+    if (lane == 63) sex = kNone;
+    if (lane == 63) s_x[wave] = pm;
+    if (lane == 0) s_x[NW + wave] = sm;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        if (w < wave) pex = max(pex, s_x[w]);
+        if (w > wave) sex = min(sex, s_x[NW + w]);
+    }
+    __syncthreads();  // s_x may be reused
+    *cs = uint32_t(pex < 0 ? 0 : pex);
+    *ce = sex == kNone ? cnt : uint32_t(sex);
+}
+
 // One workgroup per bucket, in place on rows [starts[b], starts[b+1]) of ck/rid
 // (the rows are already grouped by bucket).  Every first word x in bucket b
 // lies in [T[b], T[b+1]), so all share the common prefix (cp bits) of that
@@ -285,6 +322,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     __shared__ uint32_t s_red[NW][4];
     __shared__ uint32_t s_tmp[NW];
     __shared__ uint32_t s_flag[2];       // [0]: some run needs ordering / redo, [1]: run too long
+    __shared__ int32_t s_rb[2 * NW];     // run_bounds exchange
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t b = blockIdx.x;
@@ -449,27 +487,51 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         }
         if (attempt == 1 || nall <= 3) break;  // every varying digit is sorted
         // Runs of equal top digits: rank each member by the whole local key.
+        // Each thread takes PER consecutive positions; run bounds come from
+        // block scans, so a long run costs its members one pass over it.
         const uint32_t sh = 8 * uint32_t(dmin);  // bits below the sorted digits
         const uint16_t *ordr = s_idx[cur];
         uint16_t *dst = s_idx[cur ^ 1];
-        for (uint32_t j = tid; j < cnt; j += kSortWG) {
-            const uint16_t id = ordr[j];
-            const uint64_t kv = lkey(id), t0 = kv >> sh;
-            uint32_t s = j;
-            while (s > 0 && j - s < kTieCap && (lkey(ordr[s - 1]) >> sh) == t0) --s;
-            uint32_t e = j + 1;
-            while (e < cnt && e - s <= kTieCap && (lkey(ordr[e]) >> sh) == t0) ++e;
-            if (e - s > kTieCap) s_flag[0] = 1u;  // redo with every digit
-            if (e - s == 1) {
-                dst[j] = id;
-                continue;
+        {
+            const uint32_t j0 = PER * uint32_t(tid);
+            uint32_t starts = 0;
+            uint64_t prevt = (j0 > 0 && j0 - 1 < cnt) ? lkey(ordr[j0 - 1]) >> sh : 0ull;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = j0 + u;
+                if (j < cnt) {
+                    const uint64_t t = lkey(ordr[j]) >> sh;
+                    if (j == 0 || t != prevt) starts |= 1u << u;
+                    prevt = t;
+                }
             }
-            uint32_t r = 0;
-            for (uint32_t q = s; q < e; ++q) {
-                const uint64_t kq = lkey(ordr[q]);
-                r += (kq < kv || (kq == kv && q < j)) ? 1u : 0u;
+            uint32_t cs, ce;
+            run_carries<PER, kSortWG>(cnt, starts, &cs, &ce, s_rb);
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = j0 + u;
+                if (j >= cnt) break;
+                if ((starts >> u) & 1u) cs = j;
+                const uint32_t later = starts >> (u + 1);
+                const uint32_t re = later ? j + uint32_t(__ffs(later)) : ce;
+                const uint32_t len = re - cs;
+                const uint16_t id = ordr[j];
+                if (len > kTieCap) {  // redo with every digit (dst is discarded)
+                    s_flag[0] = 1u;
+                    continue;
+                }
+                if (len == 1) {
+                    dst[j] = id;
+                    continue;
+                }
+                const uint64_t kv = lkey(id);
+                uint32_t r = 0;
+                for (uint32_t q = cs; q < re; ++q) {
+                    const uint64_t kq = lkey(ordr[q]);
+                    r += (kq < kv || (kq == kv && q < j)) ? 1u : 0u;
+                }
+                dst[cs + r] = id;  // cs + r < re <= cnt
             }
-            dst[s + r] = id;  // s + r < e <= cnt
         }
         __syncthreads();
         if (!s_flag[0]) {
@@ -482,13 +544,32 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     // Runs of equal local keys (equal first words): record each position's run
     // start; a run longer than kRunCap sends the bucket to the radix fallback.
     const uint16_t *ord0 = s_idx[cur];
-    for (uint32_t j = tid; j < cnt; j += kSortWG) {
-        const uint64_t k = lkey(ord0[j]);
-        uint32_t s = j;
-        while (s > 0 && j - s < uint32_t(kRunCap) && lkey(ord0[s - 1]) == k) --s;
-        if (j - s >= uint32_t(kRunCap)) s_flag[1] = 1u;
-        if (s < j) s_flag[0] = 1u;
-        s_run[j] = uint16_t(s);
+    {
+        const uint32_t j0 = PER * uint32_t(tid);
+        uint32_t starts = 0;
+        uint64_t prevk = (j0 > 0 && j0 - 1 < cnt) ? lkey(ord0[j0 - 1]) : 0ull;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = j0 + u;
+            if (j < cnt) {
+                const uint64_t k = lkey(ord0[j]);
+                if (j == 0 || k != prevk) starts |= 1u << u;
+                prevk = k;
+            }
+        }
+        uint32_t cs, ce;
+        run_carries<PER, kSortWG>(cnt, starts, &cs, &ce, s_rb);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = j0 + u;
+            if (j >= cnt) break;
+            if ((starts >> u) & 1u) cs = j;
+            const uint32_t later = starts >> (u + 1);
+            const uint32_t len = (later ? j + uint32_t(__ffs(later)) : ce) - cs;
+            if (len > uint32_t(kRunCap)) s_flag[1] = 1u;
+            if (len > 1) s_flag[0] = 1u;
+            s_run[j] = uint16_t(cs);
+        }
     }
     __syncthreads();
     if (s_flag[1]) {  // leave the bucket as it is for the radix fallback

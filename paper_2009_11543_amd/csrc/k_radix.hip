@@ -267,6 +267,201 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     }
 }
 
+// The same pass for WC = 1..4 words with every array of the tile loaded into
+// registers before any work: one memory round trip per tile instead of one per
+// array, so the loads of all arrays overlap.  KPT keys per thread (fewer for
+// more words, to fit the registers); each slot's digit is kept in LDS to find
+// its destination.
+template <int WC, int KPT>
+__global__ __launch_bounds__(kWG) void k_onesweep_pre(
+    Bufs bf, uint64_t n, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback,
+    uint32_t *tile_counter, uint32_t *flags) {
+    constexpr int TILE = kWG * KPT;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_wc[kWaves][kRadixMax];  // per-wave bucket counts, then offsets
+    __shared__ uint32_t s_tstart[kRadixMax];      // tile-local bucket starts
+    __shared__ uint32_t s_gbase[kRadixMax];       // global index of tile-local slot 0 per bucket
+    __shared__ uint32_t s_tmp[4];
+    __shared__ uint64_t s_buf[TILE];
+    __shared__ uint8_t s_dig[TILE];               // digit of each slot, in slot order
+
+    const bool rid_pass = ps.word == kRidWord;
+    const bool aux_pass = ps.word == kAuxWord;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (int t = tid; t < kWaves * kRadixMax; t += kWG) (&s_wc[0][0])[t] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = uint64_t(tile) * TILE;
+    const uint32_t cnt = uint32_t(min<uint64_t>(TILE, n - base));
+    const uint32_t dmask = (1u << ps.bits) - 1u;
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+
+    uint64_t wv[WC][KPT];
+    uint32_t rv[KPT], av[KPT], dig[KPT], lpos[KPT];
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {  // every load of the tile first
+        const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+        const bool valid = li < cnt;
+#pragma unroll
+        for (int k = 0; k < WC; ++k) wv[k][m] = valid ? bf.src[uint64_t(k) * bf.src_ld + base + li] : 0ull;
+        rv[m] = valid ? bf.src_rid[base + li] : 0u;
+        av[m] = (valid && aux_pass) ? uint32_t(bf.src_aux[base + li]) : 0u;
+    }
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        uint64_t x = rid_pass ? uint64_t(rv[m]) : uint64_t(av[m]);
+#pragma unroll
+        for (int k = 0; k < WC; ++k)
+            if (uint32_t(k) == ps.word) x = wv[k][m];
+        dig[m] = uint32_t(x >> ps.shift) & dmask;
+    }
+
+    // Stable rank within the wave: peers = lanes holding the same digit.
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+        const bool valid = li < cnt;
+        uint64_t peers = __ballot(valid);
+        for (uint32_t b = 0; b < ps.bits; ++b) {
+            const bool bit = (dig[m] >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t below = __popcll(peers & lane_lt);
+        const uint32_t tot = __popcll(peers);
+        uint32_t old = 0;
+        if (valid) old = s_wc[wave][dig[m]];
+        if (valid && below == 0) s_wc[wave][dig[m]] = old + tot;
+        lpos[m] = old + below;
+    }
+    __syncthreads();
+
+    // Thread `tid` owns bucket `tid`: publish, look back, global base.
+    {
+        const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
+        __hip_atomic_store(lb, (tile == 0 ? kFlagInc : kFlagAgg) | tot, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        s_wc[0][tid] = 0;
+        s_wc[1][tid] = c0;
+        s_wc[2][tid] = c0 + c1;
+        s_wc[3][tid] = c0 + c1 + c2;
+        uint32_t all;
+        const uint32_t tstart = block_excl_scan(tot, s_tmp, all);
+        s_tstart[tid] = tstart;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            uint32_t j = tile - 1, spins = 0;
+            for (;;) {
+                const uint32_t e = __hip_atomic_load(lookback + uint64_t(j) * kRadixMax + tid,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = e & ~kValMask;
+                if (f == 0) {
+                    if (++spins > kSpinLimit) {
+                        if (flags) atomicOr(flags, CKEY_FLAG_SPIN_LIMIT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += e & kValMask;
+                if (f == kFlagInc || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_gbase[tid] = bstart[tid] + excl - tstart;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+        lpos[m] += s_tstart[dig[m]] + s_wc[wave][dig[m]];
+        if (li < cnt) s_dig[lpos[m]] = uint8_t(dig[m]);
+    }
+    __syncthreads();
+    uint32_t gdst[KPT];
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const uint32_t j = m * kWG + tid;
+        // every index is < n unless a look-back gave up (CKEY_FLAG_SPIN_LIMIT)
+        gdst[m] = j < cnt ? s_gbase[s_dig[j]] + j : 0xFFFFFFFFu;
+    }
+    // Reorder each array through LDS and write it in slot order.
+#pragma unroll
+    for (int k = 0; k < WC; ++k) {
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+            if (li < cnt) s_buf[lpos[m]] = wv[k][m];
+        }
+        __syncthreads();
+        uint64_t *kdst = bf.dst + uint64_t(k) * bf.dst_ld;
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t j = m * kWG + tid;
+            if (j < cnt && gdst[m] < n) kdst[gdst[m]] = s_buf[j];
+        }
+        __syncthreads();
+    }
+    uint32_t *s_buf32 = reinterpret_cast<uint32_t *>(s_buf);
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+        if (li < cnt) s_buf32[lpos[m]] = rv[m];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < KPT; ++m) {
+        const uint32_t j = m * kWG + tid;
+        if (j < cnt && gdst[m] < n) bf.dst_rid[gdst[m]] = s_buf32[j];
+    }
+    if (aux_pass && bf.dst_aux) {
+        uint16_t *s_buf16 = reinterpret_cast<uint16_t *>(s_buf32 + TILE);  // past the row ids
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+            if (li < cnt) s_buf16[lpos[m]] = uint16_t(av[m]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t j = m * kWG + tid;
+            if (j < cnt && gdst[m] < n) bf.dst_aux[gdst[m]] = s_buf16[j];
+        }
+    }
+}
+
+// Keys per thread of the load-first pass kernel for a word count, and the
+// tile each pass kernel uses (the load-first kernel moves the bucket-id
+// passes; the radix passes keep the 4096-key tiles, measured faster there).
+inline int pre_kpt(uint32_t words) { return words == 1 ? 12 : words == 2 ? 10 : 8; }
+inline uint64_t pass_tile(uint32_t words, bool aux) {
+    return (aux && words >= 1 && words <= 4) ? uint64_t(kWG) * pre_kpt(words) : uint64_t(kTile);
+}
+
+void launch_pass(uint32_t words, bool aux, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
+                 const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
+                 hipStream_t st) {
+    const dim3 g = dim3(uint32_t(tiles)), b = dim3(kWG);
+    if (!aux) {
+        auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
+                  : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
+        hipLaunchKernelGGL(kern, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
+        return;
+    }
+    switch (words) {
+        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 8>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        default: hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags); break;
+    }
+}
+
 __global__ void k_copy_back(Bufs bf, uint64_t n, uint32_t words) {
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
@@ -308,7 +503,7 @@ Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t r
     make_passes(words, nbits, d, rid_bits, ps);
     Layout l{};
     l.npass = uint32_t(ps.size());
-    l.tiles = (n + kTile - 1) / kTile;
+    l.tiles = (n + pass_tile(words, false) - 1) / pass_tile(words, false);
     size_t off = 0;
     l.alt_keys = off; off += align256(size_t(words) * n * 8);
     l.alt_rid = off;  off += align256(size_t(n) * 4);
@@ -326,7 +521,7 @@ struct AuxLayout {
 
 AuxLayout aux_layout(uint32_t words, uint64_t n) {
     AuxLayout l{};
-    l.tiles = (n + kTile - 1) / kTile;
+    l.tiles = (n + pass_tile(words, true) - 1) / pass_tile(words, true);
     size_t off = 0;
     l.alt_keys = off; off += align256(size_t(words) * n * 8);
     l.alt_rid = off;  off += align256(size_t(n) * 4);
@@ -400,13 +595,11 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t 
     // With two passes: caller -> workspace (moving aux) -> caller.
     Bufs first{ck, rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
     Bufs second{alt, alt_rid, ck, rid, n, n, alt_aux, nullptr};
-    auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
-              : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         const int pr_ = prof_begin(st, "bucket_pass");
-        hipLaunchKernelGGL(kern, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, p == 0 ? first : second,
-                           n, words, ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+        launch_pass(words, true, l.tiles, p == 0 ? first : second, n, ps[p], hist + p * kRadixMax, lookback,
+                    counters + p, flags, st);
         prof_end(st, pr_);
         CKEY_TRY(launch_status());
     }
@@ -477,10 +670,8 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
             const int pr_ = prof_begin(st, "onesweep");
-            auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
-                      : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
-            hipLaunchKernelGGL(kern, dim3(uint32_t(l.tiles)), dim3(kWG), 0, st, cur, n, words,
-                               ps[p], hist + p * kRadixMax, lookback, counters + p, flags);
+            launch_pass(words, false, l.tiles, cur, n, ps[p], hist + p * kRadixMax, lookback, counters + p,
+                        flags, st);
             prof_end(st, pr_);
         }
         CKEY_TRY(launch_status());
