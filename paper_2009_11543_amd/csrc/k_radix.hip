@@ -8,12 +8,15 @@
 //
 //   k_hist      one read of every key word: histograms of every digit pass.
 //   k_scan      exclusive scan of each pass histogram -> global bucket starts.
-//   k_onesweep  one pass per digit: a workgroup takes the next 4096-key tile
-//               (atomic tile counter), ranks keys stably with wave64 ballots,
+//   k_onesweep  one pass per digit: a workgroup takes the next tile (atomic
+//               tile counter), ranks keys stably with wave64 ballots,
 //               publishes its per-bucket counts, looks back over the
 //               predecessor tiles' published counts (decoupled look-back), and
 //               scatters every word and the row id through an LDS reorder
 //               buffer so each bucket's run is written contiguously.
+//               Keys of 1..4 words take k_onesweep_pre (1024 threads, every
+//               array loaded before any work, 6144..12288-key tiles: longer
+//               runs per bucket and tile); wider keys take 4096-key tiles.
 //
 // The look-back waits only on tiles whose workgroups started earlier (tile
 // numbers are handed out in start order), so every wait ends; a spin bound
@@ -91,7 +94,8 @@ __global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist) {
     h[threadIdx.x] = e;
 }
 
-// WC: the word count when it is small enough to unroll (1..4), else 0 (runtime `words`).
+// Pass over keys wider than 4 words.  WC: a fixed word count to unroll, or 0
+// (runtime `words`).
 template <int WC>
 __global__ __launch_bounds__(kWG) void k_onesweep(
     Bufs bf, uint64_t n, uint32_t words_rt, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback, uint32_t *tile_counter,
@@ -271,17 +275,19 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 // registers before any work: one memory round trip per tile instead of one per
 // array, so the loads of all arrays overlap.  KPT keys per thread (fewer for
 // more words, to fit the registers); each slot's digit is kept in LDS to find
-// its destination.
-template <int WC, int KPT>
-__global__ __launch_bounds__(kWG) void k_onesweep_pre(
+// its destination.  NT threads: larger tiles make each bucket's run per tile
+// longer, so the scattered writes come in longer pieces.
+template <int WC, int KPT, int NT>
+__global__ __launch_bounds__(NT) void k_onesweep_pre(
     Bufs bf, uint64_t n, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback,
     uint32_t *tile_counter, uint32_t *flags) {
-    constexpr int TILE = kWG * KPT;
+    constexpr int TILE = NT * KPT;
+    constexpr int NW = NT / 64;
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wc[kWaves][kRadixMax];  // per-wave bucket counts, then offsets
+    __shared__ uint32_t s_wc[NW][kRadixMax];      // per-wave bucket counts, then offsets
     __shared__ uint32_t s_tstart[kRadixMax];      // tile-local bucket starts
     __shared__ uint32_t s_gbase[kRadixMax];       // global index of tile-local slot 0 per bucket
-    __shared__ uint32_t s_tmp[4];
+    __shared__ uint32_t s_tmp[NW];
     __shared__ uint64_t s_buf[TILE];
     __shared__ uint8_t s_dig[TILE];               // digit of each slot, in slot order
 
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
     const bool aux_pass = ps.word == kAuxWord;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (int t = tid; t < kWaves * kRadixMax; t += kWG) (&s_wc[0][0])[t] = 0;
+    for (int t = tid; t < NW * kRadixMax; t += NT) (&s_wc[0][0])[t] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = uint64_t(tile) * TILE;
@@ -337,43 +343,48 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
     }
     __syncthreads();
 
-    // Thread `tid` owns bucket `tid`: publish, look back, global base.
+    // Thread `tid` < 256 owns bucket `tid`: publish, look back, global base.
     {
-        const uint32_t c0 = s_wc[0][tid], c1 = s_wc[1][tid], c2 = s_wc[2][tid], c3 = s_wc[3][tid];
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
-        __hip_atomic_store(lb, (tile == 0 ? kFlagInc : kFlagAgg) | tot, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        s_wc[0][tid] = 0;
-        s_wc[1][tid] = c0;
-        s_wc[2][tid] = c0 + c1;
-        s_wc[3][tid] = c0 + c1 + c2;
-        uint32_t all;
-        const uint32_t tstart = block_excl_scan(tot, s_tmp, all);
-        s_tstart[tid] = tstart;
-        uint32_t excl = 0;
-        if (tile > 0) {
-            uint32_t j = tile - 1, spins = 0;
-            for (;;) {
-                const uint32_t e = __hip_atomic_load(lookback + uint64_t(j) * kRadixMax + tid,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t f = e & ~kValMask;
-                if (f == 0) {
-                    if (++spins > kSpinLimit) {
-                        if (flags) atomicOr(flags, CKEY_FLAG_SPIN_LIMIT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += e & kValMask;
-                if (f == kFlagInc || j == 0) break;
-                --j;
+        uint32_t tot = 0;
+        if (tid < kRadixMax) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = s_wc[w][tid];
+                s_wc[w][tid] = tot;  // the wave's offset inside the tile's bucket run
+                tot += c;
             }
-            __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_gbase[tid] = bstart[tid] + excl - tstart;
+        uint32_t all;
+        const uint32_t tstart = block_excl_scan_n<NT>(tot, s_tmp, all);
+        if (tid < kRadixMax) {
+            s_tstart[tid] = tstart;
+            uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
+            __hip_atomic_store(lb, (tile == 0 ? kFlagInc : kFlagAgg) | tot, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t excl = 0;
+            if (tile > 0) {
+                uint32_t j = tile - 1, spins = 0;
+                for (;;) {
+                    const uint32_t e = __hip_atomic_load(lookback + uint64_t(j) * kRadixMax + tid,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t f = e & ~kValMask;
+                    if (f == 0) {
+                        if (++spins > kSpinLimit) {
+                            if (flags) atomicOr(flags, CKEY_FLAG_SPIN_LIMIT);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += e & kValMask;
+                    if (f == kFlagInc || j == 0) break;
+                    --j;
+                }
+                __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s_gbase[tid] = bstart[tid] + excl - tstart;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -386,7 +397,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
     uint32_t gdst[KPT];
 #pragma unroll
     for (int m = 0; m < KPT; ++m) {
-        const uint32_t j = m * kWG + tid;
+        const uint32_t j = m * NT + tid;
         // every index is < n unless a look-back gave up (CKEY_FLAG_SPIN_LIMIT)
         gdst[m] = j < cnt ? s_gbase[s_dig[j]] + j : 0xFFFFFFFFu;
     }
@@ -402,7 +413,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
         uint64_t *kdst = bf.dst + uint64_t(k) * bf.dst_ld;
 #pragma unroll
         for (int m = 0; m < KPT; ++m) {
-            const uint32_t j = m * kWG + tid;
+            const uint32_t j = m * NT + tid;
             if (j < cnt && gdst[m] < n) kdst[gdst[m]] = s_buf[j];
         }
         __syncthreads();
@@ -416,7 +427,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < KPT; ++m) {
-        const uint32_t j = m * kWG + tid;
+        const uint32_t j = m * NT + tid;
         if (j < cnt && gdst[m] < n) bf.dst_rid[gdst[m]] = s_buf32[j];
     }
     if (aux_pass && bf.dst_aux) {
@@ -429,7 +440,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < KPT; ++m) {
-            const uint32_t j = m * kWG + tid;
+            const uint32_t j = m * NT + tid;
             if (j < cnt && gdst[m] < n) bf.dst_aux[gdst[m]] = s_buf16[j];
         }
     }
@@ -438,27 +449,27 @@ __global__ __launch_bounds__(kWG) void k_onesweep_pre(
 // Keys per thread of the load-first pass kernel for a word count, and the
 // tile each pass kernel uses (the load-first kernel moves the bucket-id
 // passes; the radix passes keep the 4096-key tiles, measured faster there).
-inline int pre_kpt(uint32_t words) { return words == 1 ? 12 : words == 2 ? 10 : 8; }
-inline uint64_t pass_tile(uint32_t words, bool aux) {
-    return (aux && words >= 1 && words <= 4) ? uint64_t(kWG) * pre_kpt(words) : uint64_t(kTile);
+inline int pre_kpt(uint32_t words) { return words == 1 ? 12 : words == 2 ? 10 : words == 3 ? 8 : 6; }
+constexpr int kPreNT = 1024;  // threads of the load-first kernel
+// Passes over 1..4 words take the load-first kernel, wider keys the 256-thread one.
+inline bool use_pre(uint32_t words) { return words >= 1 && words <= 4; }
+inline uint64_t pass_tile(uint32_t words) {
+    return use_pre(words) ? uint64_t(kPreNT) * pre_kpt(words) : uint64_t(kTile);
 }
 
-void launch_pass(uint32_t words, bool aux, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
+void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
                  const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
                  hipStream_t st) {
-    const dim3 g = dim3(uint32_t(tiles)), b = dim3(kWG);
-    if (!aux) {
-        auto kern = words == 1 ? k_onesweep<1> : words == 2 ? k_onesweep<2>
-                  : words == 3 ? k_onesweep<3> : words == 4 ? k_onesweep<4> : k_onesweep<0>;
-        hipLaunchKernelGGL(kern, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
+    const dim3 g = dim3(uint32_t(tiles)), b = dim3(use_pre(words) ? kPreNT : kWG);
+    if (!use_pre(words)) {
+        hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
         return;
     }
     switch (words) {
-        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 8>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        default: hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags); break;
+        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        default: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
     }
 }
 
@@ -503,7 +514,7 @@ Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t r
     make_passes(words, nbits, d, rid_bits, ps);
     Layout l{};
     l.npass = uint32_t(ps.size());
-    l.tiles = (n + pass_tile(words, false) - 1) / pass_tile(words, false);
+    l.tiles = (n + pass_tile(words) - 1) / pass_tile(words);
     size_t off = 0;
     l.alt_keys = off; off += align256(size_t(words) * n * 8);
     l.alt_rid = off;  off += align256(size_t(n) * 4);
@@ -521,7 +532,7 @@ struct AuxLayout {
 
 AuxLayout aux_layout(uint32_t words, uint64_t n) {
     AuxLayout l{};
-    l.tiles = (n + pass_tile(words, true) - 1) / pass_tile(words, true);
+    l.tiles = (n + pass_tile(words) - 1) / pass_tile(words);
     size_t off = 0;
     l.alt_keys = off; off += align256(size_t(words) * n * 8);
     l.alt_rid = off;  off += align256(size_t(n) * 4);
@@ -598,7 +609,7 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t 
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         const int pr_ = prof_begin(st, "bucket_pass");
-        launch_pass(words, true, l.tiles, p == 0 ? first : second, n, ps[p], hist + p * kRadixMax, lookback,
+        launch_pass(words, l.tiles, p == 0 ? first : second, n, ps[p], hist + p * kRadixMax, lookback,
                     counters + p, flags, st);
         prof_end(st, pr_);
         CKEY_TRY(launch_status());
@@ -670,7 +681,7 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
             const int pr_ = prof_begin(st, "onesweep");
-            launch_pass(words, false, l.tiles, cur, n, ps[p], hist + p * kRadixMax, lookback, counters + p,
+            launch_pass(words, l.tiles, cur, n, ps[p], hist + p * kRadixMax, lookback, counters + p,
                         flags, st);
             prof_end(st, pr_);
         }
