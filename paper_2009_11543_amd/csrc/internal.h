@@ -189,14 +189,17 @@ ckey_status model_bucket(const void *model, uint32_t b_log2, int mode, const uin
 
 namespace ckey {
 
-// Inclusive scan across a wave64.
+// Inclusive scan across a wave64 by DPP moves (no LDS, no lane addresses):
+// shifts right by 1, 2, 4, 8 lanes within each 16-lane row (lanes shifted in
+// from outside the row read 0), then lane 15's total is added to row 1 and
+// row 3 (row_bcast:15) and lane 31's to rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xF, 0xF, true));  // row_shr:1
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xF, 0xF, true));  // row_shr:2
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xF, 0xF, true));  // row_shr:4
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xF, 0xF, true));  // row_shr:8
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xA, 0xF, false)); // row_bcast:15
+    v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xC, 0xF, false)); // row_bcast:31
     return v;
 }
 

@@ -15,10 +15,10 @@
 //
 // Sort: assign buckets (+ histogram) -> scan -> group rows by bucket (a
 // stable sort on the bucket id: two one-sweep passes) -> one workgroup per
-// bucket sorts it in place in LDS by the bits of the first word below the
-// bucket's common prefix (stable 8-bit LSD passes with wave ballots, skipping
-// digits constant in the bucket), then orders runs of equal first words by the
-// remaining words and the row id.  Buckets larger than the LDS capacity, or
+// bucket sorts it in place in LDS by the offset of the first word from the
+// bucket's lower threshold (a counting pass over its top bits, then a rank of
+// each group of equal top bits by the whole offset), then orders runs of equal
+// first words by the remaining words and the row id.  Buckets larger than the LDS capacity, or
 // with a run of equal first words longer than kRunCap, are left in place and
 // finished by the radix sort (row-id digits first, so ties still end in row-id
 // order).
@@ -288,20 +288,27 @@ __device__ __forceinline__ void run_carries(uint32_t cnt, uint32_t starts, uint3
 
 // One workgroup per bucket, in place on rows [starts[b], starts[b+1]) of ck/rid
 // (the rows are already grouped by bucket).  Every first word x in bucket b
-// lies in [T[b], T[b+1]), so all share the common prefix (cp bits) of that
-// range; the LDS sort key is x << cp, whose equal values are equal first words.
+// lies in [T[b], T[b+1]); the LDS sort key is the offset x - T[b], whose order
+// and equal values are those of the first words.
 //
-// 1. Order by the local key: LSD over its top three varying 8-bit digits (the
-//    first pass unstable, by LDS atomics -- the starting order is arbitrary;
-//    later passes stable, ranked with wave ballots), then every run of equal
-//    top digits is ranked in parallel by the whole local key.  A run longer
-//    than kTieCap instead redoes the LSD over every varying digit.
-// 2. Runs of equal local keys (equal first words) are ordered by the remaining
+// 1. Order by the offset: a counting pass over its top kG bits (kG = 12 for
+//    1024 threads, 11 for 512; unstable -- the starting order is arbitrary)
+//    puts the offsets in groups of equal top bits; a second counting pass
+//    splits every group of g offsets over g counters by the next kG bits
+//    (keys whose top bits carry little information, such as 3-bit codes of
+//    4 letters, still end in small ranges); each offset then counts the
+//    members of its range below it and equal to it, which gives its final
+//    position and the run of equal offsets it belongs to.  A range larger
+//    than kTieCap instead sends the bucket through an LSD over every varying
+//    8-bit digit (the first pass unstable by LDS atomics, later ones stable by
+//    wave ballots), after which runs are found by comparing neighbours.
+// 2. Runs of equal offsets (equal first words) are ordered by the remaining
 //    words and the row id: each array is staged in LDS and the members of
 //    every run are ranked by it in parallel, stably (an LSD within the runs,
 //    row ids first, then words w-1 .. 1).
-// 3. The first words are written from LDS; the other arrays are staged in LDS
-//    (coalesced load) and written back in sorted order (coalesced store).
+// 3. The first words are written once the order is final; the other arrays
+//    are staged in LDS (coalesced load) and written back in sorted order
+//    (coalesced store).
 template <int WC, int kCap, int kSortWG>
 __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict__ ck,
                                                          uint32_t *__restrict__ rid, uint64_t n,
@@ -311,18 +318,23 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                                                          uint32_t *__restrict__ ovf) {
     constexpr int NW = kSortWG / 64;
     constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
-    constexpr uint32_t kTieCap = 64;
-    static_assert(kCap <= 8192 && ((kCap + kSortWG - 1) / kSortWG) * 64 <= 512,
-                  "packed ids and ranks need 13 and 9 bits");
-    __shared__ uint32_t s_k[2][kCap];    // [0]: high, [1]: low half of the local key;
-                                         // afterwards 8-byte staging of the other arrays
-    __shared__ uint16_t s_idx[2][kCap];  // element order, ping-pong
-    __shared__ uint16_t s_run[kCap];     // start of the run of equal local keys at each position
-    __shared__ uint16_t s_wc[NW][256];   // per-wave digit counts, then offsets (< kCap)
-    __shared__ uint32_t s_red[NW][4];
+    constexpr uint32_t kTieCap = 256;
+    static_assert(NW == 8 || NW == 16, "512 or 1024 threads");
+    constexpr int kG = NW == 16 ? 12 : 11;  // counting-pass digit bits: 2^kG = 4 per thread
+    static_assert(kCap <= 8192 && PER * 64 <= 512, "packed ids and ranks need 13 and 9 bits");
+    __shared__ uint64_t s_kg[kCap];      // offsets in group order (final order after an LSD);
+                                         // afterwards staging of the other arrays
+    __shared__ uint16_t s_idx[2][kCap];  // [1]: row of each group position, [0]: row of each
+                                         // final position; then ping-pong
+    __shared__ uint16_t s_run[kCap];     // second-pass counters, then the start of the run of
+                                         // equal offsets at each position
+    __shared__ uint16_t s_wc[NW][256];   // 2^kG packed 16-bit group counters, then starts;
+                                         // per-wave digit counts of the LSD
+    __shared__ uint32_t s_vary[4];       // AND, AND, OR, OR of the offsets' high and low halves
     __shared__ uint32_t s_tmp[NW];
-    __shared__ uint32_t s_flag[2];       // [0]: some run needs ordering / redo, [1]: run too long
-    __shared__ int32_t s_rb[2 * NW];     // run_bounds exchange
+    __shared__ uint32_t s_flag[3];       // some run of equal offsets / a run longer than
+                                         // kRunCap / a group larger than kTieCap
+    __shared__ int32_t s_rb[2 * NW];     // run_carries exchange
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t b = blockIdx.x;
@@ -338,30 +350,33 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         return;
     }
     const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
-    const uint32_t cp = lo == hi ? 64u : uint32_t(__clzll(lo ^ hi));
-    const uint64_t pre = cp == 0 ? 0ull : cp >= 64 ? lo : (lo & ~(~0ull >> cp));  // shared prefix
+    const uint64_t span = hi - lo;  // every offset is <= span
+    const uint32_t gsh = (span >> kG) == 0 ? 0u : uint32_t(64 - __clzll(span)) - uint32_t(kG);
+    uint32_t *gcnt = reinterpret_cast<uint32_t *>(&s_wc[0][0]);  // 2^kG packed 16-bit counters
+    for (int t = tid; t < (1 << kG) / 2; t += kSortWG) gcnt[t] = 0u;
+    for (int t = tid; t < kCap / 2; t += kSortWG) reinterpret_cast<uint32_t *>(s_run)[t] = 0u;
+    if (tid < 4) s_vary[tid] = tid < 2 ? ~0u : 0u;
+    if (tid < 3) s_flag[tid] = 0u;
     uint32_t a_and[2] = {~0u, ~0u}, a_or[2] = {0u, 0u};
-    {
-        uint64_t xs[PER];
+    uint64_t xs[PER];
+    uint32_t dg[PER];  // counting-pass digit << 16 | rank within the digit
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {  // all loads first: PER in flight per thread
-            const uint32_t j = tid + u * kSortWG;
-            xs[u] = j < cnt ? ck[start + j] : 0ull;
-        }
+    for (int u = 0; u < PER; ++u) {  // all loads first: PER in flight per thread
+        const uint32_t j = tid + u * kSortWG;
+        xs[u] = j < cnt ? ck[start + j] : 0ull;
+    }
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t j = tid + u * kSortWG;
-            if (j < cnt) {
-                const uint64_t l64 = cp < 64 ? xs[u] << cp : 0ull;
-                const uint32_t h32 = uint32_t(l64 >> 32), l32 = uint32_t(l64);
-                s_k[0][j] = h32;
-                s_k[1][j] = l32;
-                s_idx[0][j] = uint16_t(j);
-                a_and[0] &= h32;
-                a_or[0] |= h32;
-                a_and[1] &= l32;
-                a_or[1] |= l32;
-            }
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t j = tid + u * kSortWG;
+        dg[u] = 0u;
+        if (j < cnt) {
+            xs[u] -= lo;
+            const uint32_t h32 = uint32_t(xs[u] >> 32), l32 = uint32_t(xs[u]);
+            dg[u] = uint32_t(min<uint64_t>(xs[u] >> gsh, (1u << kG) - 1u)) << 16;  // x in [lo, hi]: no clamp
+            a_and[0] &= h32;
+            a_or[0] |= h32;
+            a_and[1] &= l32;
+            a_or[1] |= l32;
         }
     }
 #pragma unroll
@@ -371,57 +386,195 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
         a_or[0] |= __shfl_xor(a_or[0], off, 64);
         a_or[1] |= __shfl_xor(a_or[1], off, 64);
     }
-    if (lane == 0) {
-        s_red[wave][0] = a_and[0];
-        s_red[wave][1] = a_and[1];
-        s_red[wave][2] = a_or[0];
-        s_red[wave][3] = a_or[1];
-    }
-    if (tid < 2) s_flag[tid] = 0u;
     __syncthreads();
-    uint32_t vary[2] = {0u, 0u};
-    {
-        uint32_t g_and[2] = {~0u, ~0u}, g_or[2] = {0u, 0u};
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            g_and[0] &= s_red[w][0];
-            g_and[1] &= s_red[w][1];
-            g_or[0] |= s_red[w][2];
-            g_or[1] |= s_red[w][3];
-        }
-        vary[0] = g_and[0] ^ g_or[0];
-        vary[1] = g_and[1] ^ g_or[1];
+    if (lane == 0) {
+        atomicAnd(&s_vary[0], a_and[0]);
+        atomicAnd(&s_vary[1], a_and[1]);
+        atomicOr(&s_vary[2], a_or[0]);
+        atomicOr(&s_vary[3], a_or[1]);
     }
-    auto lkey = [&](uint32_t id) { return (uint64_t(s_k[0][id]) << 32) | s_k[1][id]; };
-    // Digits of the 64-bit local key, 0 = least significant; d < 4 is in the low half.
-    auto digit_varies = [&](int d) { return ((vary[d < 4 ? 1 : 0] >> (8 * (d & 3))) & 0xFFu) != 0; };
-    int dmin = 8, nvar = 0, nall = 0;
-    for (int d = 7; d >= 0; --d)
-        if (digit_varies(d)) {
-            ++nall;
-            if (nvar < 3) { dmin = d; ++nvar; }
+    // Counting pass: rank within the digit (LDS atomics), scan, place.
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t j = tid + u * kSortWG;
+        if (j < cnt) {
+            const uint32_t d = dg[u] >> 16, h = 16u * (d & 1u);
+            dg[u] |= (atomicAdd(&gcnt[d >> 1], 1u << h) >> h) & 0xFFFFu;
         }
-    int cur = 0;
-    // Each wave ranks a contiguous slice of Q elements (Q a multiple of 64) in
-    // order, at most kRounds rounds of 64.
-    constexpr int kRounds = (kCap + kSortWG - 1) / kSortWG;
-    const uint32_t Q = ((cnt + NW * 64 - 1) / (NW * 64)) * 64;
-    const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
-    const uint64_t lane_lt = (1ull << lane) - 1ull;
-    uint32_t *cnt32 = reinterpret_cast<uint32_t *>(&s_wc[0][0]);  // 256 counters (unstable pass)
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        const int dlo = attempt == 0 ? dmin : 0;
+    }
+    __syncthreads();
+    {
+        const uint32_t w0 = gcnt[2 * tid], w1 = gcnt[2 * tid + 1];
+        const uint32_t c0 = w0 & 0xFFFFu, c1 = w0 >> 16, c2 = w1 & 0xFFFFu, c3 = w1 >> 16;
+        uint32_t all;
+        const uint32_t ex = block_excl_scan_n<kSortWG>(c0 + c1 + c2 + c3, s_tmp, all);
+        gcnt[2 * tid] = ex | ((ex + c0) << 16);
+        gcnt[2 * tid + 1] = (ex + c0 + c1) | ((ex + c0 + c1 + c2) << 16);
+    }
+    __syncthreads();
+    auto gstart = [&](uint32_t d) { return (gcnt[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu; };
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t j = tid + u * kSortWG;
+        if (j < cnt) {
+            const uint32_t pos = gstart(dg[u] >> 16) + (dg[u] & 0xFFFFu);
+            s_kg[pos] = xs[u];
+            s_idx[1][pos] = uint16_t(j);
+        }
+    }
+    __syncthreads();
+    // Second counting pass, within the groups: a group of g offsets starting
+    // at gs gets counters gs .. gs+g-1, and an offset goes to counter
+    // gs + (its next kG bits * g >> kG) -- order-preserving, and about one
+    // offset per counter when those bits are spread.
+    uint32_t *cnt2 = reinterpret_cast<uint32_t *>(s_run);  // kCap packed 16-bit counters
+    uint64_t kv[PER];
+    uint32_t ip[PER], sb[PER];  // row | counter << 16 (then | position << 16); rank, then start | count << 16
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t p = tid + u * kSortWG;
+        if (p >= cnt) continue;
+        kv[u] = s_kg[p];
+        const uint32_t d = uint32_t(min<uint64_t>(kv[u] >> gsh, (1u << kG) - 1u));
+        const uint32_t gs = gstart(d), g = (d + 1 < (1u << kG) ? gstart(d + 1) : cnt) - gs;
+        const uint64_t low = kv[u] & ((1ull << gsh) - 1ull);
+        const uint32_t nx = gsh >= uint32_t(kG) ? uint32_t(low >> (gsh - kG)) : uint32_t(low << (kG - gsh));
+        const uint32_t c = gs + ((nx * g) >> kG);
+        const uint32_t h = 16u * (c & 1u);
+        sb[u] = (atomicAdd(&cnt2[c >> 1], 1u << h) >> h) & 0xFFFFu;
+        ip[u] = uint32_t(s_idx[1][p]) | (c << 16);
+    }
+    __syncthreads();
+    {
+        constexpr int W = (kCap / 2 + kSortWG - 1) / kSortWG;  // packed words per thread
+        uint32_t v[W], c[2 * W], sum = 0;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const uint32_t t = tid * W + i;
+            v[i] = t < uint32_t(kCap / 2) ? cnt2[t] : 0u;
+            c[2 * i] = v[i] & 0xFFFFu;
+            c[2 * i + 1] = v[i] >> 16;
+            sum += c[2 * i] + c[2 * i + 1];
+        }
+        uint32_t all;
+        uint32_t ex = block_excl_scan_n<kSortWG>(sum, s_tmp, all);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const uint32_t t = tid * W + i;
+            const uint32_t e0 = ex, e1 = ex + c[2 * i];
+            ex = e1 + c[2 * i + 1];
+            if (t < uint32_t(kCap / 2)) cnt2[t] = e0 | (e1 << 16);
+        }
+    }
+    __syncthreads();
+    auto start2 = [&](uint32_t c) { return (cnt2[c >> 1] >> (16u * (c & 1u))) & 0xFFFFu; };
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t p = tid + u * kSortWG;
+        if (p >= cnt) continue;
+        const uint32_t c = ip[u] >> 16;
+        const uint32_t s2 = start2(c), e2 = c + 1 < cnt ? start2(c + 1) : cnt;
+        const uint32_t pos = s2 + sb[u];
+        s_kg[pos] = kv[u];  // every read of the group order was before the barrier
+        s_idx[1][pos] = uint16_t(ip[u]);
+        ip[u] = (ip[u] & 0xFFFFu) | (pos << 16);
+        sb[u] = s2 | ((e2 - s2) << 16);
+    }
+    __syncthreads();
+    // Each offset counts the members of its counter's range below it and
+    // equal to it: its final position and the run of equal offsets it is in.
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t p = tid + u * kSortWG;
+        if (p >= cnt) continue;
+        const uint32_t gs = sb[u] & 0xFFFFu, len = sb[u] >> 16, pos = ip[u] >> 16;
+        uint32_t lt = 0, eq = 1, eqb = 0;
+        if (len > kTieCap) {
+            s_flag[2] = 1u;
+        } else if (len > 1) {
+            eq = 0;
+            for (uint32_t q = gs; q < gs + len; ++q) {
+                const uint64_t kq = s_kg[q];
+                lt += kq < kv[u] ? 1u : 0u;
+                eq += kq == kv[u] ? 1u : 0u;
+                eqb += (kq == kv[u] && q < pos) ? 1u : 0u;
+            }
+        }
+        const uint32_t fp = gs + lt + eqb;
+        sb[u] = fp;
+        s_idx[0][fp] = uint16_t(ip[u]);
+        s_run[fp] = uint16_t(gs + lt);  // the counters were read before the barrier
+        if (eq > 1) s_flag[0] = 1u;
+        if (eq > uint32_t(kRunCap)) s_flag[1] = 1u;
+    }
+    __syncthreads();
+    if (s_flag[2] == 0u) {  // offsets to final order
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (tid + u * kSortWG < cnt) s_kg[sb[u]] = kv[u];
+    }
+    __syncthreads();
+    // With a fixed word count, the row ids and words 1..WC-1 are loaded into
+    // registers once, all loads in flight together (before the first words
+    // are stored: loads and stores retire in order).
+    constexpr int NR = WC > 1 ? WC - 1 : 1;
+    uint32_t rv[PER];
+    uint64_t wv[NR][PER];
+    auto load_rest = [&]() {
+        if constexpr (WC > 0) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                const bool ok = j < cnt;
+                rv[u] = ok ? rid[start + j] : 0u;
+#pragma unroll
+                for (int k = 0; k < WC - 1; ++k) wv[k][u] = ok ? ck[uint64_t(k + 1) * n + start + j] : 0ull;
+            }
+        }
+    };
+    auto overflow = [&]() {  // a run longer than kRunCap: leave the bucket for the radix fallback
+        if (tid == 0) {
+            const uint32_t slot = atomicAdd(&ovf[0], 1u);
+            ovf[1 + 2 * slot] = start;
+            ovf[2 + 2 * slot] = cnt;
+        }
+    };
+    if (s_flag[2] == 0u) {
+        if (s_flag[1]) {
+            overflow();
+            return;
+        }
+        load_rest();
+        // First words (equal within a run of equal offsets, so already final).
+        for (uint32_t j = tid; j < cnt; j += kSortWG) ck[start + j] = lo + s_kg[j];
+    } else {
+        // LSD over every varying 8-bit digit of the offset, on group positions
+        // (ping-pong s_idx[0] <-> s_run), then everything moved to final order.
+        const uint32_t vary[2] = {s_vary[0] ^ s_vary[2], s_vary[1] ^ s_vary[3]};
+        // Digits of the 64-bit offset, 0 = least significant; d < 4 is in the low half.
+        auto digit_varies = [&](int d) { return ((vary[d < 4 ? 1 : 0] >> (8 * (d & 3))) & 0xFFu) != 0; };
+        for (uint32_t j = tid; j < cnt; j += kSortWG) s_idx[0][j] = uint16_t(j);  // if nothing varies
+        __syncthreads();
+        // Each wave ranks a contiguous slice of Q elements (Q a multiple of 64) in
+        // order, at most kRounds rounds of 64.
+        constexpr int kRounds = PER;
+        const uint32_t Q = ((cnt + NW * 64 - 1) / (NW * 64)) * 64;
+        const uint32_t e0 = wave * Q, e1 = min(cnt, e0 + Q);
+        const uint64_t lane_lt = (1ull << lane) - 1ull;
+        uint32_t *cnt32 = reinterpret_cast<uint32_t *>(&s_wc[0][0]);  // 256 counters (unstable pass)
+        int cur = 0;  // 0: s_idx[0], 1: s_run
         bool first = true;
-        for (int d = dlo; d < 8; ++d) {  // LSD over the chosen digits
+        for (int d = 0; d < 8; ++d) {
             if (!digit_varies(d)) continue;
-            const uint32_t *key = s_k[d < 4 ? 1 : 0];
-            const uint32_t shift = 8 * (d & 3);
+            const uint32_t shift = 8 * uint32_t(d);
+            uint16_t *src = cur ? s_run : s_idx[0];
+            uint16_t *dst = cur ? s_idx[0] : s_run;
             if (first) {
-                // Unstable counting pass straight from the load order.
+                // Unstable counting pass straight from the group order.
                 first = false;
                 if (tid < 256) cnt32[tid] = 0u;
                 __syncthreads();
-                for (uint32_t j = tid; j < cnt; j += kSortWG) atomicAdd(&cnt32[(key[j] >> shift) & 0xFFu], 1u);
+                for (uint32_t j = tid; j < cnt; j += kSortWG) atomicAdd(&cnt32[uint32_t(s_kg[j] >> shift) & 0xFFu], 1u);
                 __syncthreads();
                 const uint32_t c = tid < 256 ? cnt32[tid] : 0u;
                 uint32_t all;
@@ -429,8 +582,8 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 if (tid < 256) cnt32[tid] = ex;
                 __syncthreads();
                 for (uint32_t j = tid; j < cnt; j += kSortWG) {
-                    const uint32_t pos = atomicAdd(&cnt32[(key[j] >> shift) & 0xFFu], 1u);
-                    s_idx[1][pos] = uint16_t(j);
+                    const uint32_t pos = atomicAdd(&cnt32[uint32_t(s_kg[j] >> shift) & 0xFFu], 1u);
+                    s_run[pos] = uint16_t(j);
                 }
                 __syncthreads();
                 cur = 1;
@@ -444,8 +597,8 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
             for (int u = 0; u < kRounds; ++u) {
                 const uint32_t e = e0 + 64 * u + lane;
                 const bool valid = e < e1;
-                const uint32_t id = valid ? s_idx[cur][e] : 0u;
-                const uint32_t dig = valid ? (key[id] >> shift) & 0xFFu : 0u;
+                const uint32_t id = valid ? src[e] : 0u;
+                const uint32_t dig = valid ? uint32_t(s_kg[id] >> shift) & 0xFFu : 0u;
                 uint64_t peers = __ballot(valid);
 #pragma unroll
                 for (int bit = 0; bit < 8; ++bit) {
@@ -480,124 +633,195 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 #pragma unroll
             for (int u = 0; u < kRounds; ++u) {
                 const uint32_t e = e0 + 64 * u + lane;
-                if (e < e1) s_idx[cur ^ 1][s_wc[wave][(pk[u] >> 9) & 0xFFu] + (pk[u] & 0x1FFu)] = uint16_t(pk[u] >> 17);
+                if (e < e1) dst[s_wc[wave][(pk[u] >> 9) & 0xFFu] + (pk[u] & 0x1FFu)] = uint16_t(pk[u] >> 17);
             }
             __syncthreads();
             cur ^= 1;
         }
-        if (attempt == 1 || nall <= 3) break;  // every varying digit is sorted
-        // Runs of equal top digits: rank each member by the whole local key.
-        // Each thread takes PER consecutive positions; run bounds come from
-        // block scans, so a long run costs its members one pass over it.
-        const uint32_t sh = 8 * uint32_t(dmin);  // bits below the sorted digits
-        const uint16_t *ordr = s_idx[cur];
-        uint16_t *dst = s_idx[cur ^ 1];
         {
-            const uint32_t j0 = PER * uint32_t(tid);
-            uint32_t starts = 0;
-            uint64_t prevt = (j0 > 0 && j0 - 1 < cnt) ? lkey(ordr[j0 - 1]) >> sh : 0ull;
+            const uint16_t *fin = cur ? s_run : s_idx[0];
+            uint64_t kf[PER];
+            uint32_t idf[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const uint32_t j = j0 + u;
+                const uint32_t j = tid + u * kSortWG;
                 if (j < cnt) {
-                    const uint64_t t = lkey(ordr[j]) >> sh;
-                    if (j == 0 || t != prevt) starts |= 1u << u;
-                    prevt = t;
+                    const uint32_t g = fin[j];
+                    kf[u] = s_kg[g];
+                    idf[u] = s_idx[1][g];
                 }
             }
-            uint32_t cs, ce;
-            run_carries<PER, kSortWG>(cnt, starts, &cs, &ce, s_rb);
+            __syncthreads();
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
-                const uint32_t j = j0 + u;
-                if (j >= cnt) break;
-                if ((starts >> u) & 1u) cs = j;
-                const uint32_t later = starts >> (u + 1);
-                const uint32_t re = later ? j + uint32_t(__ffs(later)) : ce;
-                const uint32_t len = re - cs;
-                const uint16_t id = ordr[j];
-                if (len > kTieCap) {  // redo with every digit (dst is discarded)
-                    s_flag[0] = 1u;
-                    continue;
+                const uint32_t j = tid + u * kSortWG;
+                if (j < cnt) {
+                    s_kg[j] = kf[u];
+                    s_idx[0][j] = uint16_t(idf[u]);
                 }
-                if (len == 1) {
-                    dst[j] = id;
-                    continue;
-                }
-                const uint64_t kv = lkey(id);
-                uint32_t r = 0;
-                for (uint32_t q = cs; q < re; ++q) {
-                    const uint64_t kq = lkey(ordr[q]);
-                    r += (kq < kv || (kq == kv && q < j)) ? 1u : 0u;
-                }
-                dst[cs + r] = id;  // cs + r < re <= cnt
             }
+            __syncthreads();
         }
-        __syncthreads();
-        if (!s_flag[0]) {
-            cur ^= 1;
-            break;
-        }
-        __syncthreads();  // every thread has read the flag
-        if (tid == 0) s_flag[0] = 0u;
-    }
-    // Runs of equal local keys (equal first words): record each position's run
-    // start; a run longer than kRunCap sends the bucket to the radix fallback.
-    const uint16_t *ord0 = s_idx[cur];
-    {
+        // Runs of equal offsets from neighbour comparisons.
         const uint32_t j0 = PER * uint32_t(tid);
-        uint32_t starts = 0;
-        uint64_t prevk = (j0 > 0 && j0 - 1 < cnt) ? lkey(ord0[j0 - 1]) : 0ull;
+        uint32_t rs = 0;
+        uint64_t prevk = (j0 > 0 && j0 - 1 < cnt) ? s_kg[j0 - 1] : 0ull;
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const uint32_t j = j0 + u;
             if (j < cnt) {
-                const uint64_t k = lkey(ord0[j]);
-                if (j == 0 || k != prevk) starts |= 1u << u;
+                const uint64_t k = s_kg[j];
+                if (j == 0 || k != prevk) rs |= 1u << u;
                 prevk = k;
             }
         }
         uint32_t cs, ce;
-        run_carries<PER, kSortWG>(cnt, starts, &cs, &ce, s_rb);
+        run_carries<PER, kSortWG>(cnt, rs, &cs, &ce, s_rb);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const uint32_t j = j0 + u;
             if (j >= cnt) break;
-            if ((starts >> u) & 1u) cs = j;
-            const uint32_t later = starts >> (u + 1);
+            if ((rs >> u) & 1u) cs = j;
+            const uint32_t later = rs >> (u + 1);
             const uint32_t len = (later ? j + uint32_t(__ffs(later)) : ce) - cs;
             if (len > uint32_t(kRunCap)) s_flag[1] = 1u;
             if (len > 1) s_flag[0] = 1u;
             s_run[j] = uint16_t(cs);
         }
-    }
-    __syncthreads();
-    if (s_flag[1]) {  // leave the bucket as it is for the radix fallback
-        if (tid == 0) {
-            const uint32_t slot = atomicAdd(&ovf[0], 1u);
-            ovf[1 + 2 * slot] = start;
-            ovf[2 + 2 * slot] = cnt;
+        __syncthreads();
+        if (s_flag[1]) {
+            overflow();
+            return;
         }
-        return;
-    }
-    // First words, from the local keys (equal within a run, so already final).
-    for (uint32_t j = tid; j < cnt; j += kSortWG) {
-        const uint64_t l = lkey(ord0[j]);
-        ck[start + j] = cp >= 64 ? lo : (pre | (l >> cp));
+        load_rest();
+        for (uint32_t j = tid; j < cnt; j += kSortWG) ck[start + j] = lo + s_kg[j];
     }
     const bool fixup = s_flag[0] != 0u;
-    __syncthreads();  // local keys are dead from here on
-    uint64_t *stg = reinterpret_cast<uint64_t *>(&s_k[0][0]);  // 8*kCap bytes
-    int done_arr = 0;  // arrays already written: 0 (first words), then -1 (row ids) or a word
-    if (fixup) {
-        for (int k = -1; k < int(words); ++k) {
-            if (k == 0) continue;  // first words are equal within a run
-            const int a = k < 0 ? -1 : int(words) - k;  // -1: row ids, then words w-1 .. 1
+    int cur = 0;
+    __syncthreads();  // offsets are dead from here on
+    uint64_t *stg = s_kg;  // 8*kCap bytes
+    // Rank the members of every run of equal offsets by the staged array,
+    // stably: s_idx[cur] -> s_idx[cur ^ 1].
+    auto rank_runs = [&]() {
+        const uint16_t *ord = s_idx[cur];
+        uint16_t *dst = s_idx[cur ^ 1];
+        for (uint32_t j = tid; j < cnt; j += kSortWG) {
+            const uint16_t id = ord[j];
+            const uint32_t s = s_run[j];
+            const bool alone = s == j && (j + 1 == cnt || s_run[j + 1] != j);
+            if (alone) {
+                dst[j] = id;
+                continue;
+            }
+            const uint64_t x = stg[id];
+            uint32_t r = 0;
+            for (uint32_t q = s; q < cnt && s_run[q] == s; ++q) {
+                const uint64_t xq = stg[ord[q]];
+                r += (xq < x || (xq == x && q < j)) ? 1u : 0u;  // stable
+            }
+            dst[s + r] = id;
+        }
+    };
+    if constexpr (WC > 0) {
+        // Arrays from registers: a = -1 row ids, else word a.
+        auto stage = [&](int a) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                if (j < cnt) stg[j] = a < 0 ? uint64_t(rv[u]) : wv[a < 1 ? 0 : a - 1][u];
+            }
+        };
+        auto put = [&](int a) {  // write the staged array a in sorted order
+            const uint16_t *ord = s_idx[cur];
+            if (a < 0) {
+                for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[ord[j]]);
+            } else {
+                uint64_t *wk = ck + uint64_t(a) * n + start;
+                for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
+            }
+        };
+        if (fixup) {
+            // LSD within the runs: row ids, then words WC-1 .. 1; the last one
+            // staged is written straight away.
+#pragma unroll
+            for (int k = -1; k < WC; ++k) {
+                if (k == 0) continue;
+                const int a = k < 0 ? -1 : WC - k;
+                stage(a);
+                __syncthreads();
+                rank_runs();
+                __syncthreads();
+                cur ^= 1;
+            }
+            put(WC > 1 ? 1 : -1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 1; a < WC; ++a) {
+            if (fixup && a == 1) continue;
+            stage(a);
+            __syncthreads();
+            put(a);
+            __syncthreads();
+        }
+        if (fixup && WC == 1) return;
+        uint32_t *stage32 = reinterpret_cast<uint32_t *>(s_kg);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const uint32_t j = tid + u * kSortWG;
+            if (j < cnt) stage32[j] = rv[u];
+        }
+        __syncthreads();
+        const uint16_t *ord = s_idx[cur];
+        for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = stage32[ord[j]];
+        return;
+    } else {
+        // Wider keys: each array is loaded when it is needed.
+        int done_arr = 0;  // arrays already written: 0 (first words), then -1 (row ids) or a word
+        if (fixup) {
+            for (int k = -1; k < int(words); ++k) {
+                if (k == 0) continue;  // first words are equal within a run
+                const int a = k < 0 ? -1 : int(words) - k;  // -1: row ids, then words w-1 .. 1
+                uint64_t v[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t j = tid + u * kSortWG;
+                    v[u] = j >= cnt ? 0ull : a < 0 ? uint64_t(rid[start + j]) : ck[uint64_t(a) * n + start + j];
+                }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t j = tid + u * kSortWG;
+                    if (j < cnt) stg[j] = v[u];
+                }
+                __syncthreads();
+                rank_runs();
+                __syncthreads();
+                cur ^= 1;
+                if (k == (words == 1 ? -1 : int(words) - 1)) {  // order final: write this array out
+                    const uint16_t *fin = s_idx[cur];
+                    if (a < 0) {
+                        for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[fin[j]]);
+                    } else {
+                        uint64_t *wk = ck + uint64_t(a) * n + start;
+                        for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[fin[j]];
+                    }
+                    done_arr = a;
+                    __syncthreads();
+                }
+            }
+        }
+        // Permute the remaining arrays in place: stage each bucket slice in LDS
+        // (coalesced load, all of a thread's loads in flight at once), then
+        // write it back in sorted order (coalesced store).
+        const uint16_t *ord = s_idx[cur];
+        for (uint32_t k = 1; k < words; ++k) {
+            if (int(k) == done_arr) continue;
+            uint64_t *wk = ck + uint64_t(k) * n + start;
             uint64_t v[PER];
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
                 const uint32_t j = tid + u * kSortWG;
-                v[u] = j >= cnt ? 0ull : a < 0 ? uint64_t(rid[start + j]) : ck[uint64_t(a) * n + start + j];
+                v[u] = j < cnt ? wk[j] : 0ull;
             }
 #pragma unroll
             for (int u = 0; u < PER; ++u) {
@@ -605,79 +829,28 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 if (j < cnt) stg[j] = v[u];
             }
             __syncthreads();
-            const uint16_t *ord = s_idx[cur];
-            uint16_t *dst = s_idx[cur ^ 1];
-            for (uint32_t j = tid; j < cnt; j += kSortWG) {
-                const uint16_t id = ord[j];
-                const uint32_t s = s_run[j];
-                const bool alone = s == j && (j + 1 == cnt || s_run[j + 1] != j);
-                if (alone) {
-                    dst[j] = id;
-                    continue;
-                }
-                const uint64_t x = stg[id];
-                uint32_t r = 0;
-                for (uint32_t q = s; q < cnt && s_run[q] == s; ++q) {
-                    const uint64_t xq = stg[ord[q]];
-                    r += (xq < x || (xq == x && q < j)) ? 1u : 0u;  // stable
-                }
-                dst[s + r] = id;
-            }
+            for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
             __syncthreads();
-            cur ^= 1;
-            if (k == (words == 1 ? -1 : int(words) - 1)) {  // order final: write this array out
-                const uint16_t *fin = s_idx[cur];
-                if (a < 0) {
-                    for (uint32_t j = tid; j < cnt; j += kSortWG) rid[start + j] = uint32_t(stg[fin[j]]);
-                } else {
-                    uint64_t *wk = ck + uint64_t(a) * n + start;
-                    for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[fin[j]];
-                }
-                done_arr = a;
-                __syncthreads();
+        }
+        if (done_arr == -1) return;
+        uint32_t *stage32 = reinterpret_cast<uint32_t *>(s_kg);
+        uint32_t *rk = rid + start;
+        {
+            uint32_t v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                v[u] = j < cnt ? rk[j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const uint32_t j = tid + u * kSortWG;
+                if (j < cnt) stage32[j] = v[u];
             }
         }
-    }
-    // Permute the remaining arrays in place: stage each bucket slice in LDS
-    // (coalesced load, all of a thread's loads in flight at once), then write
-    // it back in sorted order (coalesced store).
-    const uint16_t *ord = s_idx[cur];
-    for (uint32_t k = 1; k < words; ++k) {
-        if (int(k) == done_arr) continue;
-        uint64_t *wk = ck + uint64_t(k) * n + start;
-        uint64_t v[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t j = tid + u * kSortWG;
-            v[u] = j < cnt ? wk[j] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t j = tid + u * kSortWG;
-            if (j < cnt) stg[j] = v[u];
-        }
         __syncthreads();
-        for (uint32_t j = tid; j < cnt; j += kSortWG) wk[j] = stg[ord[j]];
-        __syncthreads();
+        for (uint32_t j = tid; j < cnt; j += kSortWG) rk[j] = stage32[ord[j]];
     }
-    if (done_arr == -1) return;
-    uint32_t *stage32 = &s_k[0][0];
-    uint32_t *rk = rid + start;
-    {
-        uint32_t v[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t j = tid + u * kSortWG;
-            v[u] = j < cnt ? rk[j] : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const uint32_t j = tid + u * kSortWG;
-            if (j < cnt) stage32[j] = v[u];
-        }
-    }
-    __syncthreads();
-    for (uint32_t j = tid; j < cnt; j += kSortWG) rk[j] = stage32[ord[j]];
 }
 
 struct LLayout {

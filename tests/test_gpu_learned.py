@@ -288,3 +288,42 @@ def test_compress_sort_entry(ck, method, layout):
     ckd, rid = ck.ckey_compress_sort(dk, d, **opts)
     np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
     np.testing.assert_array_equal(ck.as_u64(ckd), cko[:, perm])
+
+
+@pytest.mark.parametrize("words", [1, 2, 3, 5])
+@pytest.mark.parametrize("per_bucket", [1024, 2048])
+def test_bucket_sort_group_paths(ck, words, per_bucket):
+    """Direct word strings under evenly spaced thresholds (T[b] = b * 2^56):
+    uniform first words (groups of equal top offset bits ranked in place),
+    dense clusters of ~600 first words (a group beyond the in-place limit:
+    the all-digit LSD), and repeated first words with differing later words
+    (runs ordered by the later words and row ids).  1024 rows per bucket use
+    the 512-thread kernel, 2048 the 1024-thread one; 5 words the kernel
+    without a fixed word count.  Expected order: lexicographic by
+    (w0, ..., w_{k-1}, row id)."""
+    import torch
+    B = 256
+    n = per_bucket * B + 77
+    rng = np.random.default_rng(words * 10 + per_bucket)
+    w = rng.integers(0, 1 << 63, (words, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    w += rng.integers(0, 2, (words, n), dtype=np.int64).astype(np.uint64)
+    # clusters: 8 centres, 600 rows each, spread below 2^20
+    centres = rng.integers(0, 1 << 63, 8, dtype=np.int64).astype(np.uint64)
+    for c in range(8):
+        idx = rng.choice(n, 600, replace=False)
+        w[0, idx] = centres[c] + rng.integers(0, 1 << 20, 600, dtype=np.int64).astype(np.uint64)
+    # repeated first words: runs of 2..12 rows
+    src = rng.choice(n, n // 20, replace=False)
+    for s in src[: n // 40]:
+        w[0, rng.integers(0, n, int(rng.integers(1, 12)))] = w[0, s]
+    T = (np.arange(B, dtype=np.uint64) << np.uint64(56))
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    model.thresholds().copy_(to_dev(T))
+    ckd = to_dev(w).reshape(words, n).contiguous()
+    rid = torch.arange(n, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, 64 * words, rid, method=ck.CKEY_SORT_SPLITTER, model=model, flags=flags)
+    order = np.lexsort(tuple([np.arange(n)] + [w[k] for k in range(words - 1, -1, -1)]))
+    np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
+    np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
+    assert int(flags.item()) & ck.CKEY_FLAG_SPIN_LIMIT == 0
