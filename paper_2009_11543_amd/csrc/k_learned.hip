@@ -741,30 +741,106 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
             }
         };
         if (fixup) {
-            // LSD within the runs: row ids, then words WC-1 .. 1; the last one
-            // staged is written straight away.
+            // Members of runs get compact indices (by final position); their
+            // later words and row ids are staged compactly, and each member is
+            // ranked within its run by (word 1, .., word WC-1, row id) at once.
+            constexpr int C = (kCap * 8) / (8 * (WC - 1) + 4);  // members staged at once
+            uint16_t *map = s_idx[1];  // row -> compact index, 0xFFFF outside runs
+            const uint16_t *ord = s_idx[0];
+            uint32_t tot;
+            {
+                const uint32_t f0 = PER * uint32_t(tid);
+                uint32_t mem = 0, nm = 0;
 #pragma unroll
-            for (int k = -1; k < WC; ++k) {
-                if (k == 0) continue;
-                const int a = k < 0 ? -1 : WC - k;
-                stage(a);
-                __syncthreads();
-                rank_runs();
-                __syncthreads();
-                cur ^= 1;
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t f = f0 + u;
+                    if (f < cnt) {
+                        const uint32_t rs = s_run[f];
+                        const bool alone = rs == f && (f + 1 == cnt || s_run[f + 1] != f);
+                        if (!alone) {
+                            mem |= 1u << u;
+                            ++nm;
+                        }
+                    }
+                }
+                uint32_t c = block_excl_scan_n<kSortWG>(nm, s_tmp, tot);
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t f = f0 + u;
+                    if (f < cnt) map[ord[f]] = ((mem >> u) & 1u) ? uint16_t(c++) : uint16_t(0xFFFFu);
+                }
             }
-            put(WC > 1 ? 1 : -1);
             __syncthreads();
+            if (tot <= uint32_t(C)) {
+                uint64_t *cw = s_kg;                                           // [WC-1][C] words
+                uint32_t *cr = reinterpret_cast<uint32_t *>(s_kg + (WC - 1) * C);  // [C] row ids
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t j = tid + u * kSortWG;
+                    if (j < cnt) {
+                        const uint32_t m = map[j];
+                        if (m != 0xFFFFu) {
+#pragma unroll
+                            for (int k = 0; k < WC - 1; ++k) cw[k * C + m] = wv[k][u];
+                            cr[m] = rv[u];
+                        }
+                    }
+                }
+                __syncthreads();
+                uint32_t np[PER];  // new position | row << 16
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const uint32_t f = tid + u * kSortWG;
+                    np[u] = ~0u;
+                    if (f >= cnt) continue;
+                    const uint32_t id = ord[f], c = map[id];
+                    if (c == 0xFFFFu) continue;
+                    uint64_t a[NR];
+#pragma unroll
+                    for (int k = 0; k < WC - 1; ++k) a[k] = cw[k * C + c];
+                    const uint32_t ar = cr[c], rs = s_run[f];
+                    uint32_t r = 0;
+                    for (uint32_t q = rs; q < cnt && s_run[q] == rs; ++q) {
+                        const uint32_t cq = map[ord[q]];
+                        int cmp = 0;  // -1: member q orders first
+#pragma unroll
+                        for (int k = 0; k < WC - 1; ++k) {
+                            if (cmp == 0) {
+                                const uint64_t x = cw[k * C + cq];
+                                cmp = x < a[k] ? -1 : x > a[k] ? 1 : 0;
+                            }
+                        }
+                        if (cmp == 0) cmp = cr[cq] < ar ? -1 : 0;
+                        r += cmp < 0 ? 1u : 0u;
+                    }
+                    np[u] = (rs + r) | (id << 16);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < PER; ++u)
+                    if (np[u] != ~0u) s_idx[0][np[u] & 0xFFFFu] = uint16_t(np[u] >> 16);
+                __syncthreads();
+            } else {
+                // Too many members to stage at once: LSD within the runs,
+                // row ids, then words WC-1 .. 1.
+#pragma unroll
+                for (int k = -1; k < WC; ++k) {
+                    if (k == 0) continue;
+                    stage(k < 0 ? -1 : WC - k);
+                    __syncthreads();
+                    rank_runs();
+                    __syncthreads();
+                    cur ^= 1;
+                }
+            }
         }
 #pragma unroll
         for (int a = 1; a < WC; ++a) {
-            if (fixup && a == 1) continue;
             stage(a);
             __syncthreads();
             put(a);
             __syncthreads();
         }
-        if (fixup && WC == 1) return;
         uint32_t *stage32 = reinterpret_cast<uint32_t *>(s_kg);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {

@@ -292,19 +292,22 @@ def test_compress_sort_entry(ck, method, layout):
 
 @pytest.mark.parametrize("words", [1, 2, 3, 5])
 @pytest.mark.parametrize("per_bucket", [1024, 2048])
-def test_bucket_sort_group_paths(ck, words, per_bucket):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_bucket_sort_group_paths(ck, words, per_bucket, pairs):
     """Direct word strings under evenly spaced thresholds (T[b] = b * 2^56):
     uniform first words (groups of equal top offset bits ranked in place),
     dense clusters of ~600 first words (a group beyond the in-place limit:
     the all-digit LSD), and repeated first words with differing later words
     (runs ordered by the later words and row ids).  1024 rows per bucket use
     the 512-thread kernel, 2048 the 1024-thread one; 5 words the kernel
-    without a fixed word count.  Expected order: lexicographic by
+    without a fixed word count.  With `pairs`, every first word appears
+    twice, so run members exceed what is staged at once and runs are
+    ordered array by array.  Expected order: lexicographic by
     (w0, ..., w_{k-1}, row id)."""
     import torch
     B = 256
     n = per_bucket * B + 77
-    rng = np.random.default_rng(words * 10 + per_bucket)
+    rng = np.random.default_rng(words * 10 + per_bucket + int(pairs))
     w = rng.integers(0, 1 << 63, (words, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
     w += rng.integers(0, 2, (words, n), dtype=np.int64).astype(np.uint64)
     # clusters: 8 centres, 600 rows each, spread below 2^20
@@ -316,6 +319,8 @@ def test_bucket_sort_group_paths(ck, words, per_bucket):
     src = rng.choice(n, n // 20, replace=False)
     for s in src[: n // 40]:
         w[0, rng.integers(0, n, int(rng.integers(1, 12)))] = w[0, s]
+    if pairs:
+        w[0, 1::2] = w[0, 0:n - 1:2]
     T = (np.arange(B, dtype=np.uint64) << np.uint64(56))
     model = ck.CdfModel(bucket_log2=8, seed=1)
     model.thresholds().copy_(to_dev(T))
