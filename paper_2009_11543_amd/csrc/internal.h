@@ -145,13 +145,15 @@ ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nb
 
 // Stable sort of rows [0, n) by a 16-bit aux key of aux_bits bits (two
 // one-sweep passes; the aux array is read, not reordered), moving the words
-// and row ids; the result is back in ck/rid.
+// and row ids; the result is back in ck/rid.  rid_identity: the row ids are
+// 0..n-1 in order and are generated by the first pass instead of read (rid
+// is then only written).
 size_t aux_sort_workspace(uint32_t words, uint64_t n);
 // aux_full_hist (optional): histogram over all 2^aux_bits values, from which
 // the passes' histograms are derived instead of re-reading aux.
-ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
-                     uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags, void *ws,
-                     hipStream_t st);
+ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint16_t *aux, uint64_t n,
+                     uint32_t words, uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags,
+                     void *ws, hipStream_t st);
 
 // OR a value into a device flags word (a kernel, so it is stream-ordered).
 ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st);

@@ -994,16 +994,17 @@ LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
 }
 
 // From bucket ids and the bucket histogram: group by bucket, sort each bucket,
-// finish overflowing buckets with the radix sort.
-ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
-                          const void *model, uint32_t b_log2, const LPtrs &q, const LLayout &l,
+// finish overflowing buckets with the radix sort.  rid_identity: rid holds
+// nothing yet and the row ids are 0..n-1 (generated by the first pass).
+ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid,
+                          bool rid_identity, uint64_t n, const void *model, uint32_t b_log2, const LPtrs &q, const LLayout &l,
                           uint32_t *flags, void *ws, hipStream_t st) {
     const uint32_t B = 1u << b_log2;
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, q.hist, B, q.starts, q.cursor);
     CKEY_TRY(launch_status());
     // Group rows by bucket: a stable sort by the bucket id (two one-sweep passes).
-    CKEY_TRY(aux_sort(ck, rid, q.bid, n, words, b_log2, q.hist, flags, w8 + l.sortws, st));
+    CKEY_TRY(aux_sort(ck, rid, rid_identity, q.bid, n, words, b_log2, q.hist, flags, w8 + l.sortws, st));
     const uint64_t *T = thresholds_of(model);
     {
         const int pr = prof_begin(st, "bucket_sort");
@@ -1055,7 +1056,7 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     CKEY_TRY(fill_u32(q.hist, B, 0, st));
     CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
     CKEY_TRY(assign_launch(mode, ck, n, bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), nullptr, st));
-    return bucket_finish(ck, words, nbits, rid, n, model, b_log2, q, l, flags, ws, st);
+    return bucket_finish(ck, words, nbits, rid, false, n, model, b_log2, q, l, flags, ws, st);
 }
 
 ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
@@ -1067,10 +1068,11 @@ ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *
     const LPtrs q = lptrs(ws, words, n, B, l);
     CKEY_TRY(fill_u32(q.hist, B, 0, st));
     CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
-    CKEY_TRY(compress_bucket_launch(k, bm, ck, words, rid, flags, mode,
+    // The row ids start as 0..n-1: the first grouping pass generates them.
+    CKEY_TRY(compress_bucket_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, mode,
                                     bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), st));
     if (n < 2) return CKEY_OK;
-    return bucket_finish(ck, words, nbits, rid, n, model, b_log2, q, l, flags, ws, st);
+    return bucket_finish(ck, words, nbits, rid, true, n, model, b_log2, q, l, flags, ws, st);
 }
 
 // ------------------------------------------------------------- model API --

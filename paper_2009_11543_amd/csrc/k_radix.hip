@@ -133,7 +133,8 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     for (int m = 0; m < kKPT; ++m) {
         const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
         xv[m] = li < cnt ? (word_pass ? dsrc[li]
-                            : rid_pass ? uint64_t(src_rid[base + li]) : uint64_t(bf.src_aux[base + li]))
+                            : rid_pass ? uint64_t(src_rid ? src_rid[base + li] : uint32_t(base + li))
+                                       : uint64_t(bf.src_aux[base + li]))
                          : 0ull;
         dig[m] = uint32_t(xv[m] >> ps.shift) & dmask;
     }
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 #pragma unroll
         for (int m = 0; m < kKPT; ++m) {
             const uint32_t li = wave * (kKPT * 64) + m * 64 + lane;
-            rv[m] = li < cnt ? src_rid[base + li] : 0u;
+            rv[m] = li < cnt ? (src_rid ? src_rid[base + li] : uint32_t(base + li)) : 0u;
         }
         uint32_t *s_buf32 = reinterpret_cast<uint32_t *>(s_buf);
         __syncthreads();
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
         const bool valid = li < cnt;
 #pragma unroll
         for (int k = 0; k < WC; ++k) wv[k][m] = valid ? bf.src[uint64_t(k) * bf.src_ld + base + li] : 0ull;
-        rv[m] = valid ? bf.src_rid[base + li] : 0u;
+        rv[m] = valid ? (bf.src_rid ? bf.src_rid[base + li] : uint32_t(base + li)) : 0u;
         av[m] = (valid && aux_pass) ? uint32_t(bf.src_aux[base + li]) : 0u;
     }
 #pragma unroll
@@ -566,9 +567,9 @@ __global__ __launch_bounds__(kWG) void k_aux_hist(const uint32_t *__restrict__ f
     }
 }
 
-ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t n, uint32_t words,
-                     uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags, void *ws,
-                     hipStream_t st) {
+ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint16_t *aux, uint64_t n,
+                     uint32_t words, uint32_t aux_bits, const uint32_t *aux_full_hist, uint32_t *flags,
+                     void *ws, hipStream_t st) {
     if (n < 2 || aux_bits == 0) return CKEY_OK;
     const AuxLayout l = aux_layout(words, n);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
@@ -604,7 +605,7 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, const uint16_t *aux, uint64_t 
     hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist);
     CKEY_TRY(launch_status());
     // With two passes: caller -> workspace (moving aux) -> caller.
-    Bufs first{ck, rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
+    Bufs first{ck, rid_identity ? nullptr : rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
     Bufs second{alt, alt_rid, ck, rid, n, n, alt_aux, nullptr};
     for (size_t p = 0; p < ps.size(); ++p) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
