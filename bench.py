@@ -522,10 +522,13 @@ def main():
     # Algorithmic bytes per key of each kernel.
     key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
     rec = 8 * w + 4
-    per_key = {"compress": key_bytes_read + rec, "compress_bucket": key_bytes_read + rec + 2,
+    # compress_bucket writes words + bucket id (the first bucket pass generates
+    # the record IDs); the two bucket passes move rec + 2 bytes in and out,
+    # less the record IDs pass 1 does not read, plus pass 1's bucket-id copy.
+    per_key = {"compress": key_bytes_read + rec, "compress_bucket": key_bytes_read + 8 * w + 2,
                "hist": 8 * w, "onesweep": 2 * rec,
-               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_pass": 2 * rec + 3,
-               "bucket_sort": 8 + 2 * rec}
+               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_pass": 2 * rec + 1,
+               "bucket_sort": 2 * rec}
     step_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     dom_bytes = per_key[dom] * n
