@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "compress+sort keys/s & HBM GB/s at 2^26 keys vs plain GPU full-key sort"
 KERNEL_BYTES = ("compress", "compress_bucket", "hist", "onesweep", "assign_learned",
-                "assign_splitter", "bucket_pass", "bucket_sort")
+                "assign_splitter", "tile_counts", "bucket_pass", "bucket_sort")
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -527,7 +527,8 @@ def main():
     # less the record IDs pass 1 does not read, plus pass 1's bucket-id copy.
     per_key = {"compress": key_bytes_read + rec, "compress_bucket": key_bytes_read + 8 * w + 2,
                "hist": 8 * w, "onesweep": 2 * rec,
-               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "bucket_pass": 2 * rec + 1,
+               "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "tile_counts": 2,
+               "bucket_pass": 2 * rec + 1,
                "bucket_sort": 2 * rec}
     step_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])

@@ -278,10 +278,13 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 // more words, to fit the registers); each slot's digit is kept in LDS to find
 // its destination.  NT threads: larger tiles make each bucket's run per tile
 // longer, so the scattered writes come in longer pieces.
+//
+// offs (optional): each tile's global start per digit, offs[d * ntiles + tile],
+// from k_tile_counts + k_tile_scan; the tile then needs no look-back.
 template <int WC, int KPT, int NT>
 __global__ __launch_bounds__(NT) void k_onesweep_pre(
     Bufs bf, uint64_t n, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback,
-    uint32_t *tile_counter, uint32_t *flags) {
+    uint32_t *tile_counter, uint32_t *flags, const uint32_t *__restrict__ offs, uint32_t ntiles) {
     constexpr int TILE = NT * KPT;
     constexpr int NW = NT / 64;
     __shared__ uint32_t s_tile;
@@ -357,7 +360,10 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
         }
         uint32_t all;
         const uint32_t tstart = block_excl_scan_n<NT>(tot, s_tmp, all);
-        if (tid < kRadixMax) {
+        if (tid < kRadixMax && offs) {
+            s_tstart[tid] = tstart;
+            s_gbase[tid] = (tid < (1 << ps.bits) ? offs[uint64_t(tid) * ntiles + tile] : 0u) - tstart;
+        } else if (tid < kRadixMax) {
             s_tstart[tid] = tstart;
             uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
             __hip_atomic_store(lb, (tile == 0 ? kFlagInc : kFlagAgg) | tot, __ATOMIC_RELAXED,
@@ -447,6 +453,57 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
     }
 }
 
+// Per-tile digit counts of a 16-bit aux key for one pass (cnt[d * ntiles + t]):
+// one workgroup per tile, 8 keys per thread per load.
+__global__ __launch_bounds__(1024) void k_tile_counts(const uint16_t *__restrict__ aux, uint64_t n,
+                                                      uint32_t tile_keys, Pass ps, uint32_t ntiles,
+                                                      uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_c[kRadixMax];
+    const uint32_t t = blockIdx.x;
+    for (int i = threadIdx.x; i < kRadixMax; i += 1024) s_c[i] = 0u;
+    __syncthreads();
+    const uint64_t base = uint64_t(t) * tile_keys;
+    const uint32_t m = uint32_t(min<uint64_t>(tile_keys, n - base));
+    const uint32_t mask = (1u << ps.bits) - 1u;
+    for (uint32_t i = 8 * threadIdx.x; i < m; i += 8 * 1024) {
+        if (i + 8 <= m) {  // base is a multiple of 1024: 16-byte aligned
+            const uint4 v = *reinterpret_cast<const uint4 *>(aux + base + i);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                atomicAdd(&s_c[((w[k] & 0xFFFFu) >> ps.shift) & mask], 1u);
+                atomicAdd(&s_c[((w[k] >> 16) >> ps.shift) & mask], 1u);
+            }
+        } else {
+            for (uint32_t k = i; k < m; ++k) atomicAdd(&s_c[(uint32_t(aux[base + k]) >> ps.shift) & mask], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d <= mask; d += 1024) cnt[uint64_t(d) * ntiles + t] = s_c[d];
+}
+
+// Each digit's per-tile counts -> the tiles' global starts (exclusive scan
+// over the tiles plus the digit's start), in place; one workgroup per digit.
+__global__ __launch_bounds__(1024) void k_tile_scan(uint32_t *__restrict__ cnt, uint32_t ntiles,
+                                                    const uint32_t *__restrict__ bstart) {
+    __shared__ uint32_t s_tmp[16];
+    const uint32_t d = blockIdx.x;
+    uint32_t *row = cnt + uint64_t(d) * ntiles;
+    const uint32_t per = (ntiles + 1023) / 1024;
+    const uint32_t t0 = threadIdx.x * per;
+    uint32_t sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (t0 + q < ntiles) sum += row[t0 + q];
+    uint32_t tot;
+    uint32_t run = block_excl_scan_n<1024>(sum, s_tmp, tot) + bstart[d];
+    for (uint32_t q = 0; q < per; ++q)
+        if (t0 + q < ntiles) {
+            const uint32_t c = row[t0 + q];
+            row[t0 + q] = run;
+            run += c;
+        }
+}
+
 // Keys per thread of the load-first pass kernel for a word count, and the
 // tile each pass kernel uses (the load-first kernel moves the bucket-id
 // passes; the radix passes keep the 4096-key tiles, measured faster there).
@@ -460,17 +517,18 @@ inline uint64_t pass_tile(uint32_t words) {
 
 void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
                  const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
-                 hipStream_t st) {
+                 hipStream_t st, const uint32_t *offs = nullptr) {
+    const uint32_t nt = uint32_t(tiles);
     const dim3 g = dim3(uint32_t(tiles)), b = dim3(use_pre(words) ? kPreNT : kWG);
     if (!use_pre(words)) {
         hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
         return;
     }
     switch (words) {
-        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
-        default: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags); break;
+        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        default: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
     }
 }
 
@@ -608,10 +666,25 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
     Bufs first{ck, rid_identity ? nullptr : rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
     Bufs second{alt, alt_rid, ck, rid, n, n, alt_aux, nullptr};
     for (size_t p = 0; p < ps.size(); ++p) {
-        CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
+        const Bufs &bf = p == 0 ? first : second;
+        const uint32_t *offs = nullptr;
+        if (use_pre(words)) {
+            // Tile starts from per-tile counts of the pass's digit (a read of
+            // the 2-byte aux key) instead of a look-back chain across tiles.
+            const int pc_ = prof_begin(st, "tile_counts");
+            hipLaunchKernelGGL(k_tile_counts, dim3(uint32_t(l.tiles)), dim3(1024), 0, st, bf.src_aux, n,
+                               uint32_t(pass_tile(words)), ps[p], uint32_t(l.tiles), lookback);
+            hipLaunchKernelGGL(k_tile_scan, dim3(1u << ps[p].bits), dim3(1024), 0, st, lookback,
+                               uint32_t(l.tiles), hist + p * kRadixMax);
+            prof_end(st, pc_);
+            offs = lookback;
+        } else {
+            CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
+        }
+        CKEY_TRY(launch_status());
         const int pr_ = prof_begin(st, "bucket_pass");
-        launch_pass(words, l.tiles, p == 0 ? first : second, n, ps[p], hist + p * kRadixMax, lookback,
-                    counters + p, flags, st);
+        launch_pass(words, l.tiles, bf, n, ps[p], hist + p * kRadixMax, lookback, counters + p, flags, st,
+                    offs);
         prof_end(st, pr_);
         CKEY_TRY(launch_status());
     }
