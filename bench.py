@@ -122,6 +122,24 @@ def cpu_rowcol(rows_all, n_sample, d, perm_ref):
                       f"(C = {t['cache_bytes']} B per thread)"}
 
 
+def cpu_gnu(rows_all, n_sample, d, perm_ref):
+    """The GCC parallel-mode sort on the host cores, same sample: of the full
+    keys (memcmp, record-ID ties), and of the compressed records after the
+    same compression."""
+    from paper_2009_11543_amd import rowcol
+    rows = np.ascontiguousarray(rows_all[:n_sample])
+    threads = min(16, os.cpu_count() or 1)
+    pf, sf = rowcol.gnu_full_sort(rows, rows.shape[1], threads=threads)
+    assert np.array_equal(pf, perm_ref), "full-key parallel sort order differs from the oracle's"
+    pc, _, t = rowcol.gnu_compress_sort(rows, d, threads=threads)
+    assert np.array_equal(pc, perm_ref), "compressed parallel sort order differs from the oracle's"
+    dt = t["compress_s"] + t["sort_s"]
+    return {"full_keys": {"value": n_sample / sf, "unit": "keys/s", "seconds": sf},
+            "compressed": {"value": n_sample / dt, "unit": "keys/s", "compress_s": t["compress_s"],
+                           "sort_s": t["sort_s"]},
+            "cores": threads, "kind": "__gnu_parallel::sort (OpenMP)", "sample": f"first {n_sample} rows"}
+
+
 def bench_table(args, torch, ckey, prof, dev):
     """Rebuild of all eight indexes of a 2^24-row table (refresh with the
     current D-bitmaps; radix sorts): eight separate calls, one batched call
@@ -590,6 +608,10 @@ def main():
         out["cpu_baseline"], d_s, perm_s = cpu_baseline(rows, min(args.cpu_sample, n))
         out["cpu_rowcol"] = cpu_rowcol(rows, min(args.cpu_sample, n), d_s, perm_s)
         log(f"cpu row-column: {out['cpu_rowcol']['value'] / 1e6:.1f} M keys/s on {out['cpu_rowcol']['cores']} threads")
+        out["cpu_gnu_parallel"] = cpu_gnu(rows, min(args.cpu_sample, n), d_s, perm_s)
+        g = out["cpu_gnu_parallel"]
+        log(f"cpu gnu parallel sort: full keys {g['full_keys']['value'] / 1e6:.1f}, compressed "
+            f"{g['compressed']['value'] / 1e6:.1f} M keys/s")
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,7 @@
-"""Host-side baseline: PEXT compression (Sec. 5.1) and the row-column sort
-(Appendix A) on the host cores, built from ``rowcol.cpp`` with g++.  Used to
-set the paper's own CPU pipeline beside the GPU path; the GPU library never
+"""Host-side baselines: PEXT compression (Sec. 5.1) and the row-column sort
+(Appendix A) on the host cores, and the GCC parallel-mode sort of the same
+records or of the full keys, built from ``rowcol.cpp`` with g++ (OpenMP).  Used
+to set the paper's own CPU pipeline beside the GPU path; the GPU library never
 calls it."""
 import ctypes
 import os
@@ -15,7 +16,7 @@ _lib = None
 
 
 def build():
-    subprocess.check_call(["g++", "-O3", "-std=c++17", "-Wall", "-shared", "-fPIC", "-pthread",
+    subprocess.check_call(["g++", "-O3", "-std=c++17", "-Wall", "-shared", "-fPIC", "-pthread", "-fopenmp",
                            "-o", _LIB, _SRC])
 
 
@@ -28,6 +29,10 @@ def _load():
         P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
         lib.rowcol_compress_sort.argtypes = [P, U64, U32, U32, P, U32, ctypes.c_int, U64, P, P, P]
         lib.rowcol_compress_sort.restype = ctypes.c_int
+        lib.gnu_compress_sort.argtypes = [P, U64, U32, U32, P, U32, ctypes.c_int, P, P, P]
+        lib.gnu_compress_sort.restype = ctypes.c_int
+        lib.gnu_full_sort.argtypes = [P, U64, U32, U32, ctypes.c_int, P, P]
+        lib.gnu_full_sort.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -73,3 +78,37 @@ def compress_sort(rows, bitmap, threads=None, cache_bytes=None, want_ckeys=False
     return perm, ck, {"compress_s": t[0], "sort_s": t[1], "phase_block_sort_s": t[2],
                       "phase_split_s": t[3], "phase_merge_s": t[4], "threads": threads,
                       "cache_bytes": cache_bytes}
+
+
+def gnu_compress_sort(rows, bitmap, threads=None, want_ckeys=False):
+    """Compression as compress_sort, then __gnu_parallel::sort of the
+    (compressed key, record ID) records.  Returns (perm, ckeys or None, times)."""
+    rows = np.ascontiguousarray(rows, np.uint8)
+    bm = np.ascontiguousarray(bitmap, np.uint8)
+    n, stride = rows.shape
+    threads = threads or min(16, os.cpu_count() or 1)
+    words = max(1, -(-int(np.unpackbits(bm).sum()) // 64))
+    perm = np.zeros(n, np.uint32)
+    ck = np.zeros((words, n), np.uint64) if want_ckeys else None
+    t = np.zeros(5, np.float64)
+    rc = _load().gnu_compress_sort(rows.ctypes.data if n else None, n, len(bm), stride, bm.ctypes.data, words,
+                                   threads, perm.ctypes.data, None if ck is None else ck.ctypes.data,
+                                   t.ctypes.data)
+    if rc != 0:
+        raise ValueError("gnu_compress_sort: bad arguments")
+    return perm, ck, {"compress_s": t[0], "sort_s": t[1], "threads": threads}
+
+
+def gnu_full_sort(rows, key_bytes, threads=None):
+    """__gnu_parallel::sort of record IDs by memcmp of the first key_bytes
+    bytes of each row, ties by record ID.  Returns (perm, seconds)."""
+    rows = np.ascontiguousarray(rows, np.uint8)
+    n, stride = rows.shape
+    threads = threads or min(16, os.cpu_count() or 1)
+    perm = np.zeros(n, np.uint32)
+    sec = ctypes.c_double()
+    rc = _load().gnu_full_sort(rows.ctypes.data if n else None, n, key_bytes, stride, threads,
+                               perm.ctypes.data, ctypes.byref(sec))
+    if rc != 0:
+        raise ValueError("gnu_full_sort: bad arguments")
+    return perm, sec.value

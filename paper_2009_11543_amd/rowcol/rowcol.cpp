@@ -15,11 +15,18 @@
 // block are among the i*n/p smallest), which together form the perfect
 // p-partition.  (3) Thread i merges the i-th parts of all sorted blocks with a
 // tournament tree into the i-th final block (first array).
+//
+// Beside it, the GCC parallel-mode sort (__gnu_parallel::sort, OpenMP) of the
+// same (compressed key, record ID) records, and of (full key, record ID) by
+// memcmp: the library sort the paper sets its row-column sort against.
 #include <stdint.h>
 #include <string.h>
 
+#include <omp.h>
+
 #include <algorithm>
 #include <chrono>
+#include <parallel/algorithm>
 #include <cmath>
 #include <thread>
 #include <vector>
@@ -284,9 +291,10 @@ void compress_rows(const uint8_t *keys, size_t r0, size_t r1, uint32_t L, uint32
     }
 }
 
+// sorter 0: row-column sort; 1: __gnu_parallel::sort on p OpenMP threads.
 template <int W>
 int run(const uint8_t *keys, uint64_t n, uint32_t L, uint32_t stride, const uint8_t *bitmap, int p,
-        uint64_t cache_bytes, uint32_t *perm, uint64_t *ck_out, double *times) {
+        uint64_t cache_bytes, uint32_t *perm, uint64_t *ck_out, double *times, int sorter = 0) {
     using clk = std::chrono::steady_clock;
     std::vector<Elem<W>> key(n), temp(n);
     const std::vector<Window> win = windows_of(bitmap, L);
@@ -298,7 +306,12 @@ int run(const uint8_t *keys, uint64_t n, uint32_t L, uint32_t stride, const uint
     });
     auto t1 = clk::now();
     double ph[3] = {0, 0, 0};
-    row_column_sort<W>(key.data(), temp.data(), n, p, cache_bytes, ph);
+    if (sorter == 0) {
+        row_column_sort<W>(key.data(), temp.data(), n, p, cache_bytes, ph);
+    } else {
+        omp_set_num_threads(p);
+        __gnu_parallel::sort(key.begin(), key.end(), [](const Elem<W> &a, const Elem<W> &b) { return less<W>(a, b); });
+    }
     auto t2 = clk::now();
     for (size_t i = 0; i < n; ++i) {
         perm[i] = uint32_t(key[i].rid);
@@ -345,6 +358,48 @@ int rowcol_compress_sort(const uint8_t *keys, uint64_t n, uint32_t L, uint32_t s
         case 8: return run<8>(keys, n, L, stride, bitmap, p, cache_bytes, perm, ck_out, times);
         default: return -1;
     }
+}
+
+// The same compression, then __gnu_parallel::sort of the (compressed key,
+// record ID) records on p threads; arguments as rowcol_compress_sort (times[2..4]
+// are 0).
+int gnu_compress_sort(const uint8_t *keys, uint64_t n, uint32_t L, uint32_t stride,
+                      const uint8_t *bitmap, uint32_t words, int p, uint32_t *perm, uint64_t *ck_out,
+                      double *times) {
+    if ((!keys && n) || !bitmap || L == 0 || stride < L || p < 1 || (!perm && n)) return -1;
+    uint32_t nbits = 0;
+    for (uint32_t j = 0; j < L; ++j) nbits += uint32_t(__builtin_popcount(bitmap[j]));
+    const uint32_t need = nbits ? (nbits + 63) / 64 : 1;
+    if (words != need) return -1;
+    switch (words) {
+        case 1: return run<1>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 2: return run<2>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 3: return run<3>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 4: return run<4>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 5: return run<5>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 6: return run<6>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 7: return run<7>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        case 8: return run<8>(keys, n, L, stride, bitmap, p, 0, perm, ck_out, times, 1);
+        default: return -1;
+    }
+}
+
+// __gnu_parallel::sort of the full keys: record IDs ordered by memcmp of the
+// L key bytes, ties by record ID, on p threads.  perm (uint32[n]) receives
+// the order; *seconds (or NULL) the sort time.  Returns 0, or -1 on bad
+// arguments.
+int gnu_full_sort(const uint8_t *keys, uint64_t n, uint32_t L, uint32_t stride, int p, uint32_t *perm,
+                  double *seconds) {
+    if ((!keys && n) || L == 0 || stride < L || p < 1 || (!perm && n)) return -1;
+    for (uint64_t i = 0; i < n; ++i) perm[i] = uint32_t(i);
+    auto t0 = std::chrono::steady_clock::now();
+    omp_set_num_threads(p);
+    __gnu_parallel::sort(perm, perm + n, [&](uint32_t a, uint32_t b) {
+        const int c = memcmp(keys + size_t(a) * stride, keys + size_t(b) * stride, L);
+        return c < 0 || (c == 0 && a < b);
+    });
+    if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return 0;
 }
 
 }  // extern "C"

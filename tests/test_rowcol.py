@@ -51,3 +51,21 @@ def test_stride_wider_than_key():
 def test_rejects_bad_words():
     with pytest.raises(ValueError):
         rowcol.compress_sort(np.zeros((4, 80), np.uint8), np.full(80, 0xFF, np.uint8))  # 640 bits: > 8 words
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_gnu_parallel_sorts_match_oracle(case):
+    """The GCC parallel-mode baselines: compressed records and full keys give
+    the oracle's full-key order (ties by record ID)."""
+    n, L, p, _, alphabet = case
+    rows = datagen.random_small_keys(n, L, n + L + p, alphabet)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm) if n else (np.zeros(L, np.uint8), 0)
+    bm = d if d.any() else np.full(L, 0xFF, np.uint8)
+    got, ck, _ = rowcol.gnu_compress_sort(rows, bm, threads=p, want_ckeys=True)
+    np.testing.assert_array_equal(got, perm)
+    if n:
+        np.testing.assert_array_equal(ck, O.compress(k, bm)[:, perm])
+    full, _ = rowcol.gnu_full_sort(rows, L, threads=p)
+    np.testing.assert_array_equal(full, perm)
