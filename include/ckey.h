@@ -109,7 +109,10 @@ typedef struct {
     uint32_t method;      /* ckey_sort_method                                          */
     uint32_t digit_bits;  /* radix digit width, 1..8; 0 = 8                           */
     uint32_t bucket_log2; /* learned/splitter: log2 of the model's bucket count, 8..16 */
-    uint32_t reserved;
+    uint32_t skip_trivial; /* radix, ckey_sort / ckey_compress_sort only: 1 = read the
+                            * digit histograms back (one stream synchronization) and
+                            * skip every pass whose digit is equal for all rows; the
+                            * index-rebuild entry points ignore it                   */
     const void *model;    /* learned/splitter: device model memory (ckey_cdf_*)        */
     uint32_t *flags;      /* device flags word or NULL                                 */
 } ckey_sort_opts;

@@ -72,11 +72,15 @@ size_t sort_workspace(const ckey_sort_opts *o, uint32_t words, uint32_t nbits, u
     return learned_workspace(words, nbits, n, o->bucket_log2);
 }
 
+// skip_ok: the caller allows the radix sort's trivial-pass skip (a stream
+// synchronization), i.e. it is ckey_sort / ckey_compress_sort, not a rebuild.
 ckey_status sort_dispatch(const ckey_sort_opts *o, uint64_t *ck, uint32_t words, uint32_t nbits,
-                          uint32_t *rid, uint64_t n, uint32_t *flags, void *ws, hipStream_t st) {
+                          uint32_t *rid, uint64_t n, uint32_t *flags, void *ws, hipStream_t st,
+                          bool skip_ok = false) {
     const uint32_t m = method_of(o);
     if (m == CKEY_SORT_RADIX)
-        return radix_sort(ck, n, words, nbits, rid, n, digit_bits_of(o), 0, flags, ws, st);
+        return radix_sort(ck, n, words, nbits, rid, n, digit_bits_of(o), 0, flags, ws, st,
+                          skip_ok && o && o->skip_trivial);
     return learned_sort(ck, words, nbits, rid, n, m == CKEY_SORT_LEARNED ? 1 : 0, o->model,
                         o->bucket_log2, flags, ws, st);
 }
@@ -85,7 +89,7 @@ ckey_status sort_dispatch(const ckey_sort_opts *o, uint64_t *ck, uint32_t words,
 // found while it is compressed when the keys allow the fused kernel.
 ckey_status compress_sort_dispatch(const ckey_sort_opts *o, const KeySrc &k, const uint8_t *bm,
                                    uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid,
-                                   uint32_t *flags, void *ws, hipStream_t st) {
+                                   uint32_t *flags, void *ws, hipStream_t st, bool skip_ok = false) {
     const uint32_t m = method_of(o);
     if (m != CKEY_SORT_RADIX) {
         const ckey_status s = compress_learned_sort(k, bm, ck, words, nbits, rid,
@@ -94,7 +98,7 @@ ckey_status compress_sort_dispatch(const ckey_sort_opts *o, const KeySrc &k, con
         if (s != CKEY_ERR_UNSUPPORTED) return s;
     }
     CKEY_TRY(compress_launch(k, bm, ck, words, rid, flags, st));
-    return sort_dispatch(o, ck, words, nbits, rid, k.n, flags, ws, st);
+    return sort_dispatch(o, ck, words, nbits, rid, k.n, flags, ws, st, skip_ok);
 }
 
 struct IndexPlan {
@@ -402,7 +406,7 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
     if (query) return CKEY_OK;
     if (n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
     return sort_dispatch(opts, ckeys, words, nbits, rowids, n, opts ? opts->flags : nullptr, ws,
-                         as_stream(stream));
+                         as_stream(stream), true);
 }
 
 ckey_status ckey_compress_sort(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
@@ -418,7 +422,7 @@ ckey_status ckey_compress_sort(const ckey_keys *keys, const uint8_t *bitmap, uin
     if (query) return CKEY_OK;
     if (keys->n > 0 && (!ckeys || !rowids)) return CKEY_ERR_INVALID;
     return compress_sort_dispatch(opts, key_src(keys), bitmap, ckeys, words, nbits, rowids,
-                                  opts ? opts->flags : nullptr, ws, as_stream(stream));
+                                  opts ? opts->flags : nullptr, ws, as_stream(stream), true);
 }
 
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,

@@ -139,9 +139,11 @@ ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
 // so that ties end up in row-id order whatever the input order.
 size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits,
                        uint32_t rid_bits = 0);
+// skip_trivial: read the pass histograms back (one stream synchronization)
+// and skip every pass whose digit is the same for all n rows.
 ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nbits,
                        uint32_t *rowids, uint64_t n, uint32_t digit_bits, uint32_t rid_bits,
-                       uint32_t *flags, void *ws, hipStream_t st);
+                       uint32_t *flags, void *ws, hipStream_t st, bool skip_trivial = false);
 
 // Stable sort of rows [0, n) by a 16-bit aux key of aux_bits bits (two
 // one-sweep passes; the aux array is read, not reordered), moving the words

@@ -704,7 +704,7 @@ size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, u
 
 ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits, uint32_t *rid,
                        uint64_t n, uint32_t d, uint32_t rid_bits, uint32_t *flags, void *ws,
-                       hipStream_t st) {
+                       hipStream_t st, bool skip_trivial) {
     if (n < 2 || (nbits == 0 && rid_bits == 0)) return CKEY_OK;
     std::vector<Pass> ps;
     make_passes(words, nbits, d, rid_bits, ps);
@@ -745,13 +745,27 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         CKEY_TRY(launch_status());
         p0 = p;
     }
+    std::vector<size_t> run;  // passes to run
+    if (skip_trivial) {
+        // A pass whose digit is the same for every row leaves the order as it is.
+        std::vector<uint32_t> h(size_t(l.npass) * kRadixMax);
+        CKEY_HIP_TRY(hipMemcpyAsync(h.data(), hist, h.size() * 4, hipMemcpyDeviceToHost, st));
+        CKEY_HIP_TRY(hipStreamSynchronize(st));
+        for (size_t p = 0; p < ps.size(); ++p) {
+            bool trivial = false;
+            for (int b = 0; b < kRadixMax; ++b) trivial |= h[p * kRadixMax + b] == n;
+            if (!trivial) run.push_back(p);
+        }
+    } else {
+        for (size_t p = 0; p < ps.size(); ++p) run.push_back(p);
+    }
     hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist);
     CKEY_TRY(launch_status());
 
     // Ping-pong between the caller's arrays (leading dimension ld) and the
     // workspace copy (leading dimension n).
     Bufs cur{ck, rid, alt, alt_rid, ld, n, nullptr, nullptr};
-    for (size_t p = 0; p < ps.size(); ++p) {
+    for (size_t p : run) {
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
             const int pr_ = prof_begin(st, "onesweep");

@@ -190,6 +190,41 @@ def test_sort_digit_widths(ck, digit_bits):
     np.testing.assert_array_equal(u32(rid), ref)
 
 
+@pytest.mark.parametrize("n", [1, 5000, 70001])
+def test_sort_skip_trivial_passes(ck, n):
+    """skip_trivial drops exactly the passes whose digit is equal for every
+    row (here the 6 constant leading bytes of 16-byte keys, sorted over all
+    128 bits, and the zero low byte of every word) and keeps the order."""
+    import ctypes
+    import torch
+    rows = datagen.random_small_keys(n, 16, 11, None)
+    rows[:, :6] = np.frombuffer(b"\x07\x00\x41\xff\x10\x02", np.uint8)
+    rows[:, 15] = 0
+    k = O.Keys(rows)
+    ref = O.full_sort(k)
+    bm = np.full(16, 0xFF, np.uint8)
+    lib = ck._lib
+    outs, launches = [], []
+    for skip in (False, True):
+        ckd, rid = ck.ckey_compress(dev_keys(ck, rows), bm)
+        lib.ckey_profile_reset()
+        lib.ckey_profile_enable(1)
+        ck.ckey_sort(ckd, 128, rid, skip_trivial=skip)
+        torch.cuda.synchronize()
+        ms, c = ctypes.c_double(), ctypes.c_uint64()
+        lib.ckey_profile_read(b"onesweep", ctypes.byref(ms), ctypes.byref(c))
+        lib.ckey_profile_enable(0)
+        launches.append(int(c.value))
+        outs.append((u32(rid).copy(), ck.as_u64(ckd).copy()))
+    for r, c in outs:
+        np.testing.assert_array_equal(r, ref)
+        np.testing.assert_array_equal(c, O.compress(k, bm)[:, ref])
+    if n > 1:
+        assert launches == [16, 9]
+    else:
+        assert launches == [0, 0]
+
+
 # ---------------------------------------------------------------- rebuild --
 
 def check_rebuild(ck, k, dk, bm, want_ck=True):
