@@ -219,35 +219,48 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     }
 }
 
-// Exclusive scan of B counters by one 1024-thread workgroup -> starts[0..B], cursors.
+// Exclusive scan of B counters by one 1024-thread workgroup -> starts[0..B].
+// Thread t owns B/1024 consecutive counters (16-byte loads when that is a
+// multiple of 4, i.e. B >= 4096).
 __global__ __launch_bounds__(1024) void k_bucket_scan(const uint32_t *__restrict__ hist, uint32_t B,
-                                                      uint32_t *__restrict__ starts,
-                                                      uint32_t *__restrict__ cursor) {
+                                                      uint32_t *__restrict__ starts) {
     __shared__ uint32_t s_w[16];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x;
     const uint32_t per = (B + 1023) / 1024;
     const uint32_t b0 = tid * per;
+    const bool vec = (per & 3u) == 0;
     uint32_t sum = 0;
-    for (uint32_t q = 0; q < per; ++q)
-        if (b0 + q < B) sum += hist[b0 + q];
-    const uint32_t incl = wave_incl_scan(sum);
-    if (lane == 63) s_w[wave] = incl;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-        off += w < wave ? s_w[w] : 0u;
-        tot += s_w[w];
-    }
-    uint32_t run = off + incl - sum;
-    for (uint32_t q = 0; q < per; ++q)
-        if (b0 + q < B) {
-            starts[b0 + q] = run;
-            cursor[b0 + q] = run;
-            run += hist[b0 + q];
+    if (vec) {
+        for (uint32_t q = 0; q < per; q += 4) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b0 + q);
+            sum += v.x + v.y + v.z + v.w;
         }
+    } else {
+        for (uint32_t q = 0; q < per; ++q)
+            if (b0 + q < B) sum += hist[b0 + q];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan_n<1024>(sum, s_w, tot);
+    if (vec) {
+        for (uint32_t q = 0; q < per; q += 4) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(hist + b0 + q);
+            uint4 o;
+            o.x = run;
+            o.y = o.x + v.x;
+            o.z = o.y + v.y;
+            o.w = o.z + v.z;
+            run = o.w + v.w;
+            *reinterpret_cast<uint4 *>(starts + b0 + q) = o;
+        }
+    } else {
+        for (uint32_t q = 0; q < per; ++q)
+            if (b0 + q < B) {
+                starts[b0 + q] = run;
+                run += hist[b0 + q];
+            }
+    }
     if (tid == 0) starts[B] = tot;
 }
-
 
 // Runs over positions [0, cnt) held thread-contiguously: thread t owns
 // positions [P*t, P*t + P), and bit u of `starts` says that owned position u
@@ -930,7 +943,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 }
 
 struct LLayout {
-    size_t bid, hist, starts, cursor, ovf, stats, sortws, total;
+    size_t bid, hist, starts, ovf, stats, sortws, total;
 };
 
 LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
@@ -939,7 +952,6 @@ LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
     l.bid = off;      off += align256(size_t(n) * 2);
     l.hist = off;     off += align256(size_t(B) * 4);
     l.starts = off;   off += align256(size_t(B + 1) * 4);
-    l.cursor = off;   off += align256(size_t(B) * 4);
     l.ovf = off;      off += align256(size_t(2 * B + 1) * 4);
     l.stats = off;    off += align256(2 * 8);
     l.sortws = off;   off += aux_sort_workspace(words, n);
@@ -982,14 +994,14 @@ namespace {
 
 struct LPtrs {
     uint16_t *bid;
-    uint32_t *hist, *starts, *cursor, *ovf;
+    uint32_t *hist, *starts, *ovf;
 };
 
 LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
     l = llayout(words, n, B);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     return LPtrs{reinterpret_cast<uint16_t *>(w8 + l.bid), reinterpret_cast<uint32_t *>(w8 + l.hist),
-                 reinterpret_cast<uint32_t *>(w8 + l.starts), reinterpret_cast<uint32_t *>(w8 + l.cursor),
+                 reinterpret_cast<uint32_t *>(w8 + l.starts),
                  reinterpret_cast<uint32_t *>(w8 + l.ovf)};
 }
 
@@ -1001,7 +1013,7 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
                           uint32_t *flags, void *ws, hipStream_t st) {
     const uint32_t B = 1u << b_log2;
     uint8_t *w8 = static_cast<uint8_t *>(ws);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, q.hist, B, q.starts, q.cursor);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, q.hist, B, q.starts);
     CKEY_TRY(launch_status());
     // Group rows by bucket: a stable sort by the bucket id (two one-sweep passes).
     CKEY_TRY(aux_sort(ck, rid, rid_identity, q.bid, n, words, b_log2, q.hist, flags, w8 + l.sortws, st));

@@ -608,20 +608,40 @@ AuxLayout aux_layout(uint32_t words, uint64_t n) {
 size_t aux_sort_workspace(uint32_t words, uint64_t n) { return aux_layout(words, n).total; }
 
 // Pass histograms of the two aux digits from a histogram over all 2^aux_bits
-// aux values (thread d owns digit value d of both passes).
-__global__ __launch_bounds__(kWG) void k_aux_hist(const uint32_t *__restrict__ full, uint32_t aux_bits,
-                                                  uint32_t lo, uint32_t *__restrict__ hist) {
-    const uint32_t d = threadIdx.x, hi = aux_bits - lo;
-    uint32_t s0 = 0, s1 = 0;
-    if (lo && d < (1u << lo))
-        for (uint32_t h = 0; h < (1u << hi); ++h) s0 += full[(h << lo) | d];
-    if (d < (1u << hi))
-        for (uint32_t l = 0; l < (1u << lo); ++l) s1 += full[(d << lo) | l];
-    if (lo) {
-        hist[d] = s0;
-        hist[kRadixMax + d] = s1;
-    } else {
-        hist[d] = s1;
+// aux values: thread d sums digit value d of the low pass and thread 256 + d
+// of the high one.  LDS: the histogram is staged in LDS first (16-byte
+// loads; 2^aux_bits <= 2^15), else the sums read it from global memory.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_aux_hist(const uint32_t *__restrict__ full, uint32_t aux_bits,
+                                                   uint32_t lo, uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t s_full[];
+    const uint32_t tid = threadIdx.x, hi = aux_bits - lo, m = 1u << aux_bits;
+    const uint32_t *src = full;
+    if (LDS) {
+        for (uint32_t i = 4 * tid; i < m; i += 4 * 1024) {
+            if (i + 4 <= m) {
+                *reinterpret_cast<uint4 *>(s_full + i) = *reinterpret_cast<const uint4 *>(full + i);
+            } else {
+                for (uint32_t k = i; k < m; ++k) s_full[k] = full[k];
+            }
+        }
+        __syncthreads();
+        src = s_full;
+    }
+    if (tid < kRadixMax) {
+        const uint32_t d = tid;
+        if (lo) {
+            uint32_t s0 = 0;
+            if (d < (1u << lo))
+                for (uint32_t h = 0; h < (1u << hi); ++h) s0 += src[(h << lo) | d];
+            hist[d] = s0;
+        }
+    } else if (tid < 2 * kRadixMax) {
+        const uint32_t d = tid - kRadixMax;
+        uint32_t s1 = 0;
+        if (d < (1u << hi))
+            for (uint32_t l = 0; l < (1u << lo); ++l) s1 += src[(d << lo) | l];
+        hist[(lo ? kRadixMax : 0) + d] = s1;
     }
 }
 
@@ -651,7 +671,14 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
     }
     ha.npass = uint32_t(ps.size());
     if (aux_full_hist) {
-        hipLaunchKernelGGL(k_aux_hist, dim3(1), dim3(kWG), 0, st, aux_full_hist, aux_bits, lo, hist);
+        if (aux_bits <= 15) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_aux_hist<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            hipLaunchKernelGGL(k_aux_hist<true>, dim3(1), dim3(1024), size_t(4) << aux_bits, st, aux_full_hist,
+                               aux_bits, lo, hist);
+        } else {
+            hipLaunchKernelGGL(k_aux_hist<false>, dim3(1), dim3(1024), 0, st, aux_full_hist, aux_bits, lo, hist);
+        }
     } else {
         uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
         if (hblocks > 2048) hblocks = 2048;

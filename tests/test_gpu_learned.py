@@ -332,3 +332,24 @@ def test_bucket_sort_group_paths(ck, words, per_bucket, pairs):
     np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
     np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
     assert int(flags.item()) & ck.CKEY_FLAG_SPIN_LIMIT == 0
+
+
+@pytest.mark.parametrize("bucket_log2", [12, 15, 16])
+def test_bucket_counts_many_buckets(ck, bucket_log2):
+    """2^12 .. 2^16 evenly spaced thresholds: the bucket-start scan with
+    16-byte loads and both forms of the pass histograms (staged in LDS up to
+    2^15 buckets, read from global memory at 2^16)."""
+    import torch
+    n = (1 << 20) + 5
+    rng = np.random.default_rng(bucket_log2)
+    w = rng.integers(0, 1 << 63, (2, n), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    B = 1 << bucket_log2
+    T = np.arange(B, dtype=np.uint64) << np.uint64(64 - bucket_log2)
+    model = ck.CdfModel(bucket_log2=bucket_log2, seed=1)
+    model.thresholds().copy_(to_dev(T))
+    ckd = to_dev(w).reshape(2, n).contiguous()
+    rid = torch.arange(n, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, 128, rid, method=ck.CKEY_SORT_SPLITTER, model=model)
+    order = np.lexsort((np.arange(n), w[1], w[0]))
+    np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
+    np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
