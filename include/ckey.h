@@ -125,8 +125,13 @@ typedef struct {
  * row ids arrive ascending, as ckey_compress writes them); the bucketing
  * methods compare row ids explicitly.  opts may be NULL (radix, 8-bit
  * digits).  The bucketing methods synchronize `stream` once to learn whether
- * a bucket overflowed the in-LDS sort (those buckets are finished by the radix
- * sort and raise CKEY_FLAG_BUCKET_OVERFLOW).  Needs a workspace. */
+ * a bucket overflowed the in-LDS sort (5120 rows; 2560 when the mean bucket
+ * holds at most 1600): such buckets are sorted again in LDS with a 10240-row
+ * capacity (a second synchronization), and those still left (larger, or with
+ * a run of more than 32 equal first words) are finished by the radix sort and
+ * raise CKEY_FLAG_BUCKET_OVERFLOW; so does a widespread overflow (more than
+ * 64 buckets or an eighth of the rows), which radix-sorts everything.  Needs
+ * a workspace. */
 ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
                       uint64_t n, const ckey_sort_opts *opts, void *workspace,
                       size_t *workspace_bytes, void *stream);

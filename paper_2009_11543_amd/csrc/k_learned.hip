@@ -39,6 +39,7 @@ constexpr int kLoss = kNP;       // index of the loss in a partial-sum row
 constexpr size_t kOffParams = 0, kOffM = 2048, kOffV = 4096, kOffT = 8192;
 constexpr int kCapLarge = 5120;  // max bucket size sorted in LDS (large-bucket kernel)
 constexpr int kCapSmall = 2560;  // (small-bucket kernel, for <= 1600 rows per bucket on average)
+constexpr int kCapHuge = 10240;  // second chance for buckets over those (one workgroup per CU)
 constexpr int kRunCap = 32;      // max run of equal first words sorted in place
 constexpr int kAssignWG = 1024;
 constexpr uint32_t kKeysPerAssignWG = 65535;  // keeps the packed 16-bit LDS counters exact
@@ -322,19 +323,25 @@ __device__ __forceinline__ void run_carries(uint32_t cnt, uint32_t starts, uint3
 // 3. The first words are written once the order is final; the other arrays
 //    are staged in LDS (coalesced load) and written back in sorted order
 //    (coalesced store).
+//
+// list (optional): the buckets to sort are list[1 + 3 i] for workgroup i (an
+// overflow list of the smaller kernels), else bucket = workgroup.  Buckets it
+// cannot sort go to ovf as (bucket, start, count) triples after ovf[0].
 template <int WC, int kCap, int kSortWG>
-__global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict__ ck,
-                                                         uint32_t *__restrict__ rid, uint64_t n,
-                                                         uint32_t words_rt,
-                                                         const uint32_t *__restrict__ starts,
-                                                         const uint64_t *__restrict__ T, uint32_t B,
-                                                         uint32_t *__restrict__ ovf) {
+__global__ __launch_bounds__(kSortWG, (kCap > 5120 ? 4 : 8)) void k_bucket_sort(
+    uint64_t *__restrict__ ck, uint32_t *__restrict__ rid, uint64_t n, uint32_t words_rt,
+    const uint32_t *__restrict__ starts, const uint64_t *__restrict__ T, uint32_t B,
+    uint32_t *__restrict__ ovf, const uint32_t *__restrict__ list) {
     constexpr int NW = kSortWG / 64;
     constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
     constexpr uint32_t kTieCap = 256;
     static_assert(NW == 8 || NW == 16, "512 or 1024 threads");
     constexpr int kG = NW == 16 ? 12 : 11;  // counting-pass digit bits: 2^kG = 4 per thread
-    static_assert(kCap <= 8192 && PER * 64 <= 512, "packed ids and ranks need 13 and 9 bits");
+    // LSD fallback packing: row (kIdB bits) | digit (8) | rank in the wave's slice (kRkB bits)
+    constexpr int kRkB = PER * 64 <= 512 ? 9 : PER * 64 <= 1024 ? 10 : 11;
+    constexpr int kIdB = 32 - 8 - kRkB;
+    static_assert(kCap <= (1 << kIdB) && kCap < 65535 && PER * 64 <= (1 << kRkB),
+                  "packed rows, ranks and 16-bit positions");
     __shared__ uint64_t s_kg[kCap];      // offsets in group order (final order after an LSD);
                                          // afterwards staging of the other arrays
     __shared__ uint16_t s_idx[2][kCap];  // [1]: row of each group position, [0]: row of each
@@ -350,16 +357,20 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
     __shared__ int32_t s_rb[2 * NW];     // run_carries exchange
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint32_t b = blockIdx.x;
+    const uint32_t b = list ? list[1 + 3 * blockIdx.x] : blockIdx.x;
     const uint32_t start = starts[b];
     const uint32_t cnt = starts[b + 1] - start;
-    if (cnt < 2) return;
-    if (cnt > uint32_t(kCap)) {
+    auto overflow = [&]() {  // leave the bucket for the radix sort
         if (tid == 0) {
             const uint32_t slot = atomicAdd(&ovf[0], 1u);
-            ovf[1 + 2 * slot] = start;
-            ovf[2 + 2 * slot] = cnt;
+            ovf[1 + 3 * slot] = b;
+            ovf[2 + 3 * slot] = start;
+            ovf[3 + 3 * slot] = cnt;
         }
+    };
+    if (cnt < 2) return;
+    if (cnt > uint32_t(kCap)) {
+        overflow();
         return;
     }
     const uint64_t lo = T[b], hi = (b + 1 < B) ? T[b + 1] - 1 : ~0ull;
@@ -545,13 +556,6 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
             }
         }
     };
-    auto overflow = [&]() {  // a run longer than kRunCap: leave the bucket for the radix fallback
-        if (tid == 0) {
-            const uint32_t slot = atomicAdd(&ovf[0], 1u);
-            ovf[1 + 2 * slot] = start;
-            ovf[2 + 2 * slot] = cnt;
-        }
-    };
     if (s_flag[2] == 0u) {
         if (s_flag[1]) {
             overflow();
@@ -604,7 +608,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
             }
             for (int t = tid; t < NW * 256; t += kSortWG) (&s_wc[0][0])[t] = 0;
             __syncthreads();
-            // per element: id (13 bits) << 17 | digit << 9 | rank within the wave's slice (< 512)
+            // per element: id << (8 + kRkB) | digit << kRkB | rank within the wave's slice
             uint32_t pk[kRounds];
 #pragma unroll
             for (int u = 0; u < kRounds; ++u) {
@@ -623,7 +627,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
                 uint32_t old = 0;
                 if (valid) old = s_wc[wave][dig];
                 if (valid && below == 0) s_wc[wave][dig] = uint16_t(old + uint32_t(__popcll(peers)));
-                pk[u] = (id << 17) | (dig << 9) | (old + below);
+                pk[u] = (id << (8 + kRkB)) | (dig << kRkB) | (old + below);
             }
             __syncthreads();
             {
@@ -646,7 +650,9 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 #pragma unroll
             for (int u = 0; u < kRounds; ++u) {
                 const uint32_t e = e0 + 64 * u + lane;
-                if (e < e1) dst[s_wc[wave][(pk[u] >> 9) & 0xFFu] + (pk[u] & 0x1FFu)] = uint16_t(pk[u] >> 17);
+                if (e < e1)
+                    dst[s_wc[wave][(pk[u] >> kRkB) & 0xFFu] + (pk[u] & ((1u << kRkB) - 1u))] =
+                        uint16_t(pk[u] >> (8 + kRkB));
             }
             __syncthreads();
             cur ^= 1;
@@ -943,7 +949,7 @@ __global__ __launch_bounds__(kSortWG, 8) void k_bucket_sort(uint64_t *__restrict
 }
 
 struct LLayout {
-    size_t bid, hist, starts, ovf, stats, sortws, total;
+    size_t bid, hist, starts, ovf, ovf2, stats, sortws, total;
 };
 
 LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
@@ -952,7 +958,8 @@ LLayout llayout(uint32_t words, uint64_t n, uint32_t B) {
     l.bid = off;      off += align256(size_t(n) * 2);
     l.hist = off;     off += align256(size_t(B) * 4);
     l.starts = off;   off += align256(size_t(B + 1) * 4);
-    l.ovf = off;      off += align256(size_t(2 * B + 1) * 4);
+    l.ovf = off;      off += align256(size_t(3 * B + 1) * 4);
+    l.ovf2 = off;     off += align256(size_t(3 * B + 1) * 4);
     l.stats = off;    off += align256(2 * 8);
     l.sortws = off;   off += aux_sort_workspace(words, n);
     l.total = off;
@@ -994,7 +1001,7 @@ namespace {
 
 struct LPtrs {
     uint16_t *bid;
-    uint32_t *hist, *starts, *ovf;
+    uint32_t *hist, *starts, *ovf, *ovf2;
 };
 
 LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
@@ -1002,7 +1009,7 @@ LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     return LPtrs{reinterpret_cast<uint16_t *>(w8 + l.bid), reinterpret_cast<uint32_t *>(w8 + l.hist),
                  reinterpret_cast<uint32_t *>(w8 + l.starts),
-                 reinterpret_cast<uint32_t *>(w8 + l.ovf)};
+                 reinterpret_cast<uint32_t *>(w8 + l.ovf), reinterpret_cast<uint32_t *>(w8 + l.ovf2)};
 }
 
 // From bucket ids and the bucket histogram: group by bucket, sort each bucket,
@@ -1023,34 +1030,56 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
         if (n / B <= 1600) {  // small buckets: 2560-row capacity, 512 threads, 4 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapSmall, 512> : words == 2 ? k_bucket_sort<2, kCapSmall, 512>
                     : words == 3 ? k_bucket_sort<3, kCapSmall, 512> : k_bucket_sort<0, kCapSmall, 512>;
-            hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf);
+            hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
         } else {
             auto kb = words == 1 ? k_bucket_sort<1, kCapLarge, 1024> : words == 2 ? k_bucket_sort<2, kCapLarge, 1024>
                     : words == 3 ? k_bucket_sort<3, kCapLarge, 1024> : k_bucket_sort<0, kCapLarge, 1024>;
-            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf);
+            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
         }
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());
-    // Overflowing buckets: read their ranges back and finish them with the radix sort.
-    uint32_t novf = 0;
-    CKEY_HIP_TRY(hipMemcpyAsync(&novf, q.ovf, 4, hipMemcpyDeviceToHost, st));
-    CKEY_HIP_TRY(hipStreamSynchronize(st));
+    // Overflowing buckets (count, then (bucket, start, rows) triples).
+    auto read_list = [&](const uint32_t *dev, std::vector<uint32_t> &v) -> ckey_status {
+        uint32_t c = 0;
+        CKEY_HIP_TRY(hipMemcpyAsync(&c, dev, 4, hipMemcpyDeviceToHost, st));
+        CKEY_HIP_TRY(hipStreamSynchronize(st));
+        v.assign(3 * size_t(c), 0u);
+        if (c) {
+            CKEY_HIP_TRY(hipMemcpyAsync(v.data(), dev + 1, v.size() * 4, hipMemcpyDeviceToHost, st));
+            CKEY_HIP_TRY(hipStreamSynchronize(st));
+        }
+        return CKEY_OK;
+    };
+    std::vector<uint32_t> ov;
+    CKEY_TRY(read_list(q.ovf, ov));
+    uint32_t novf = uint32_t(ov.size() / 3);
     if (novf == 0) return CKEY_OK;
-    std::vector<uint32_t> ranges(2 * size_t(novf));
-    CKEY_HIP_TRY(hipMemcpyAsync(ranges.data(), q.ovf + 1, ranges.size() * 4, hipMemcpyDeviceToHost, st));
-    CKEY_HIP_TRY(hipStreamSynchronize(st));
     uint64_t rows = 0;
-    for (uint32_t i = 0; i < novf; ++i) rows += ranges[2 * i + 1];
+    for (uint32_t i = 0; i < novf; ++i) rows += ov[3 * i + 2];
     if (novf > 64 || rows > n / 8) {
         // Widespread overflow (data the thresholds do not split): one radix
         // sort of everything by (key, row id) -- exact from any arrangement.
         CKEY_TRY(radix_sort(ck, n, words, nbits, rid, n, 8, 32, flags, ws, st));
-    } else {
-        for (uint32_t i = 0; i < novf; ++i) {
-            const uint32_t s0 = ranges[2 * i], c = ranges[2 * i + 1];
-            CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
-        }
+        if (flags) CKEY_TRY(fill_flag_or(flags, CKEY_FLAG_BUCKET_OVERFLOW, st));
+        return CKEY_OK;
+    }
+    // Second chance: the 10240-row in-LDS sort over the listed buckets.
+    CKEY_TRY(fill_u32(q.ovf2, 1, 0, st));
+    {
+        auto kh = words == 1 ? k_bucket_sort<1, kCapHuge, 1024> : words == 2 ? k_bucket_sort<2, kCapHuge, 1024>
+                : words == 3 ? k_bucket_sort<3, kCapHuge, 1024> : k_bucket_sort<0, kCapHuge, 1024>;
+        const int pr = prof_begin(st, "bucket_sort_large");
+        hipLaunchKernelGGL(kh, dim3(novf), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf2, q.ovf);
+        prof_end(st, pr);
+        CKEY_TRY(launch_status());
+    }
+    CKEY_TRY(read_list(q.ovf2, ov));
+    novf = uint32_t(ov.size() / 3);
+    if (novf == 0) return CKEY_OK;
+    for (uint32_t i = 0; i < novf; ++i) {
+        const uint32_t s0 = ov[3 * i + 1], c = ov[3 * i + 2];
+        CKEY_TRY(radix_sort(ck + s0, n, words, nbits, rid + s0, c, 8, 32, flags, ws, st));
     }
     if (flags) CKEY_TRY(fill_flag_or(flags, CKEY_FLAG_BUCKET_OVERFLOW, st));
     return CKEY_OK;

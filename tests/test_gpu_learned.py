@@ -353,3 +353,35 @@ def test_bucket_counts_many_buckets(ck, bucket_log2):
     order = np.lexsort((np.arange(n), w[1], w[0]))
     np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
     np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
+
+
+@pytest.mark.parametrize("words", [1, 3])
+@pytest.mark.parametrize("too_big", [False, True])
+def test_bucket_second_chance(ck, words, too_big):
+    """Buckets beyond 5120 rows are sorted again by the 10240-row kernel (no
+    overflow flag); one beyond 10240 rows goes on to the radix sort (flag)."""
+    import torch
+    B, per = 256, 4096
+    n0 = B * per
+    rng = np.random.default_rng(40 + words + 2 * int(too_big))
+    w = rng.integers(0, 1 << 63, (words, n0), dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    extra = [(5, 3000), (200, 1500)] + ([(9, 7000)] if too_big else [])
+    parts = [w]
+    for b, m in extra:
+        e = rng.integers(0, 1 << 63, (words, m), dtype=np.int64).astype(np.uint64)
+        e[0] = (np.uint64(b) << np.uint64(56)) | (e[0] >> np.uint64(8))
+        parts.append(e)
+    w = np.concatenate(parts, axis=1)
+    n = w.shape[1]
+    w = w[:, rng.permutation(n)]
+    T = np.arange(B, dtype=np.uint64) << np.uint64(56)
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    model.thresholds().copy_(to_dev(T))
+    ckd = to_dev(w).reshape(words, n).contiguous()
+    rid = torch.arange(n, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, 64 * words, rid, method=ck.CKEY_SORT_SPLITTER, model=model, flags=flags)
+    order = np.lexsort(tuple([np.arange(n)] + [w[k] for k in range(words - 1, -1, -1)]))
+    np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
+    np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
+    assert bool(int(flags.item()) & ck.CKEY_FLAG_BUCKET_OVERFLOW) == too_big
