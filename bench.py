@@ -474,6 +474,13 @@ def main():
     if full_skip is not None:
         log(f"full-key sort skipping trivial passes: {full_skip * 1e3:.1f} ms")
     d_bitmap = ckey.ckey_distinction_bits(keys, order=ridf).cpu().numpy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ckey.ckey_distinction_bits(keys, order=ridf)
+    torch.cuda.synchronize()
+    dbits_ms = (time.perf_counter() - t0) / 3 * 1e3
+    log(f"D-bitmap from the full-key order: {dbits_ms:.2f} ms")
     del ckf, wsf
     plan = ckey.ckey_plan_query(d_bitmap)
     nbits, w = plan["nbits"], plan["words"]
@@ -588,6 +595,7 @@ def main():
                      "ms_per_launch": kern[dom]["ms_per_launch"], "copy_probe_gbps": copy_gbps},
         "kernels": kern,
         "methods_ms_per_step": {m: results[m][0] for m in results},
+        "distinction_bits_ms": dbits_ms,
         "training": None if model is None else {"rows": args.train_rows, "seed": 2,
                                                 "steps": args.train_steps, "batch": 1 << 16,
                                                 "seconds": train_s, "loss_first": float(trace[0]),

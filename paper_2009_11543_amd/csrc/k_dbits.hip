@@ -1,7 +1,8 @@
 // Distinction bits of adjacent sorted keys (Sec. 3.1, Theorem 1).
 //
 // One thread per adjacent pair (i-1, i): the keys are compared as big-endian
-// 32-bit words; the first differing word gives the pair's D-bit as
+// 32-bit words (read 16 bytes at a time when rows are 16-byte aligned); the
+// first differing word gives the pair's D-bit as
 // 32*j + clz(x xor y).  The position is OR-ed into a workgroup bitmap in LDS
 // (one u32 per 4 bitmap bytes), and each workgroup OR-s its non-zero words into
 // the global accumulator once.  A pair whose earlier key has a 1 at its D-bit
@@ -45,6 +46,38 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
             pa = k.bytes + ra * k.stride;
             pb = k.bytes + rb * k.stride;
             la = lb = k.L;
+        }
+        if (MODE == kLoad16) {
+            // 16 bytes of both keys per step (rows are 16-byte aligned and
+            // the stride a multiple of 16, so a chunk starting inside the key
+            // stays inside the row); bytes at or past L read as zero.
+            for (uint32_t c = 0; 16 * c < k.L; ++c) {
+                const uint4 va = *reinterpret_cast<const uint4 *>(pa + 16 * c);
+                const uint4 vb = *reinterpret_cast<const uint4 *>(pb + 16 * c);
+                const uint32_t xa[4] = {va.x, va.y, va.z, va.w}, xb[4] = {vb.x, vb.y, vb.z, vb.w};
+                bool done = false;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t j = 4 * c + uint32_t(q);
+                    if (done || j >= nw) continue;
+                    uint32_t x = __builtin_bswap32(xa[q]), y = __builtin_bswap32(xb[q]);
+                    const uint32_t have = k.L - 4 * j;
+                    if (have < 4) {
+                        const uint32_t m = ~(0xFFFFFFFFu >> (8 * have));
+                        x &= m;
+                        y &= m;
+                    }
+                    if (x != y) {
+                        const uint32_t lz = __clz(x ^ y);
+                        const uint32_t p = 32 * j + lz;
+                        desc |= ((x >> (31 - lz)) & 1u) != 0;
+                        atomicOr(&s_bm[p >> 5], bitmap_word_bit(p));
+                        done = true;
+                    }
+                }
+                if (done) break;
+            }
+            continue;
         }
         for (uint32_t j = 0; j < nw; ++j) {
             uint32_t x = load_key_word<MODE>(k, ra, j, pa, la);
@@ -108,6 +141,14 @@ ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc, 
             {
                 const int pr_ = prof_begin(st, "dbits");
                 hipLaunchKernelGGL(k_dbits<kLoadBytes>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
+                                   order, acc, flags);
+                prof_end(st, pr_);
+            }
+            break;
+        case kLoad16:
+            {
+                const int pr_ = prof_begin(st, "dbits");
+                hipLaunchKernelGGL(k_dbits<kLoad16>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
                                    order, acc, flags);
                 prof_end(st, pr_);
             }

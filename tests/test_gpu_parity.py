@@ -84,6 +84,22 @@ def test_distinction_bits_stride_and_varlen(ck):
     np.testing.assert_array_equal(got.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("L,pad", [(37, 11), (64, 0), (100, 12)])
+def test_distinction_bits_wide_aligned_rows(ck, L, pad):
+    """16-byte aligned rows (16 bytes of both keys per step), key lengths that
+    end inside a 16-byte chunk, junk bytes past the key in the stride."""
+    import torch
+    n = 20000
+    rows = datagen.random_small_keys(n, L, L + pad, [0x41, 0x43, 0x47, 0x54])
+    rows[:, : L // 3] = 0x41  # long shared prefixes: the first difference lies late
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    ref, _ = O.dbits(k, perm)
+    order = torch.from_numpy(perm.view(np.int32)).cuda()
+    got = ck.ckey_distinction_bits(dev_keys(ck, rows, L=L, stride_pad=pad), order=order)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+
+
 # --------------------------------------------------------------- compress --
 
 def bitmaps_for(rows, seed):
