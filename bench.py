@@ -523,7 +523,8 @@ def main():
                                 **method_opts[m])
 
     def timed(m, steps):
-        prof.on()
+        # The step time with the per-kernel event timing off; then the same
+        # steps again with it on, for the per-kernel times.
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
@@ -532,6 +533,10 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        prof.on()
+        for _ in range(steps):
+            step(m)
+        torch.cuda.synchronize()
         kern = {}
         for name in KERNEL_BYTES:
             t, c = prof.read(name)

@@ -316,18 +316,21 @@ def ckey_compress_sort(keys, bitmap, out=None, rowids=None, words=None, workspac
     """Compress and sort in one call: (sorted compressed keys (words, n) int64,
     row ids in full-key order int32)."""
     bm, p = _host_bitmap(bitmap)
-    plan = ckey_plan_query(bm)
-    w = plan["words"] if words is None else words
+    if words is None:
+        words = out.shape[0] if out is not None else ckey_plan_query(bm)["words"]
+    w = words
     dev = keys.data.device
     ck = torch.empty((w, keys.n), dtype=torch.int64, device=dev) if out is None else out
     rid = torch.empty(keys.n, dtype=torch.int32, device=dev) if rowids is None else rowids
     ks = keys.c_struct()
     o = _opts(**opts)
-    need = ctypes.c_size_t(0)
-    _check("ckey_compress_sort", _lib.ckey_compress_sort(ctypes.byref(ks), p, None, w, None,
-                                                         ctypes.byref(o), None, ctypes.byref(need),
-                                                         None))
-    ws = _workspace(need.value, dev) if workspace is None else workspace
+    if workspace is None:  # size query; a caller's workspace is checked by the library
+        need = ctypes.c_size_t(0)
+        _check("ckey_compress_sort", _lib.ckey_compress_sort(ctypes.byref(ks), p, None, w, None,
+                                                             ctypes.byref(o), None, ctypes.byref(need),
+                                                             None))
+        workspace = _workspace(need.value, dev)
+    ws = workspace
     need = ctypes.c_size_t(ws.numel())
     _check("ckey_compress_sort", _lib.ckey_compress_sort(ctypes.byref(ks), p, _ptr(ck), w, _ptr(rid),
                                                          ctypes.byref(o), _ptr(ws), ctypes.byref(need),

@@ -42,11 +42,6 @@ inline size_t bucket_lds_bytes(const BucketArgs &a, int amode) {
     return bucket_sample_words(a, amode) * 4 + (a.hist ? size_t(a.B / 2) * 4 : 0);
 }
 
-// Dynamic LDS above 64 KB (B = 2^16) needs the kernel attribute raised once.
-inline void set_bucket_lds_limit(const void *fn) {
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-}
-
 __device__ __forceinline__ void mlp_features(uint64_t x, float f[4]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) f[j] = float(uint32_t(x >> (48 - 16 * j)) & 0xFFFFu) * (1.0f / 65536.0f);

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "../../include/ckey.h"
 
 namespace ckey {
@@ -76,6 +80,18 @@ __device__ __forceinline__ uint32_t key_word_aligned(const uint8_t *p, uint32_t 
 // (bitmap byte p/8 is byte (p/8)%4 of word p/32; the position is bit 7-p%8 of that byte).
 __device__ __forceinline__ uint32_t bitmap_word_bit(uint32_t p) {
     return 1u << (8 * ((p >> 3) & 3) + (7 - (p & 7)));
+}
+
+// Dynamic LDS above 64 KB needs the kernel attribute raised: once per
+// (device, kernel), remembered so that later calls pay nothing.
+inline void raise_lds_limit(const void *fn) {
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    if (done.insert({dev, fn}).second)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 // Event timing around a launch when profiling is enabled (profiler.hip).

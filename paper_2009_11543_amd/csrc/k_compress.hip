@@ -382,14 +382,14 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
     const size_t lds = bucket_lds_bytes(ba, amode);
     constexpr int kKPI = 4;  // keys per thread per iteration
     const bool multi = mode == kLoad16 && cidx <= 4;
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, kKPI>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0, 1>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, kKPI>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1, 1>));
     const int pr_ = prof_begin(st, "compress_bucket");
 #define CKEY_LAUNCH_CB(M, KPI)                                                                         \
     if (amode)                                                                                         \

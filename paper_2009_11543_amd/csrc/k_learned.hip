@@ -976,8 +976,8 @@ ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const Bucket
     if (n == 0) return CKEY_OK;
     const size_t lds = bucket_lds_bytes(ba, mode);
     const uint64_t blocks = (n + kBucketKeysPerWG - 1) / kBucketKeysPerWG;
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<0>));
-    set_bucket_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<0>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<1>));
     const int pr = prof_begin(st, mode ? "assign_learned" : "assign_splitter");
     if (mode)
         hipLaunchKernelGGL(k_bucket_assign<1>, dim3(uint32_t(blocks)), dim3(kBucketWG), lds, st, w0, n, ba, stats);

@@ -672,8 +672,7 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
     ha.npass = uint32_t(ps.size());
     if (aux_full_hist) {
         if (aux_bits <= 15) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_aux_hist<true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            raise_lds_limit(reinterpret_cast<const void *>(k_aux_hist<true>));
             hipLaunchKernelGGL(k_aux_hist<true>, dim3(1), dim3(1024), size_t(4) << aux_bits, st, aux_full_hist,
                                aux_bits, lo, hist);
         } else {
