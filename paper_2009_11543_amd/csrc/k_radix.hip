@@ -14,8 +14,8 @@
 //               predecessor tiles' published counts (decoupled look-back), and
 //               scatters every word and the row id through an LDS reorder
 //               buffer so each bucket's run is written contiguously.
-//               Keys of 1..4 words take k_onesweep_pre (1024 threads, every
-//               array loaded before any work, 6144..12288-key tiles: longer
+//               Keys of 1..8 words take k_onesweep_pre (1024 threads, every
+//               array loaded before any work, 4096..12288-key tiles: longer
 //               runs per bucket and tile); wider keys take 4096-key tiles.
 //
 // The look-back waits only on tiles whose workgroups started earlier (tile
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist) {
     h[threadIdx.x] = e;
 }
 
-// Pass over keys wider than 4 words.  WC: a fixed word count to unroll, or 0
+// Pass over keys wider than 8 words.  WC: a fixed word count to unroll, or 0
 // (runtime `words`).
 template <int WC>
 __global__ __launch_bounds__(kWG) void k_onesweep(
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     }
 }
 
-// The same pass for WC = 1..4 words with every array of the tile loaded into
+// The same pass for WC = 1..8 words with every array of the tile loaded into
 // registers before any work: one memory round trip per tile instead of one per
 // array, so the loads of all arrays overlap.  KPT keys per thread (fewer for
 // more words, to fit the registers); each slot's digit is kept in LDS to find
@@ -507,10 +507,12 @@ __global__ __launch_bounds__(1024) void k_tile_scan(uint32_t *__restrict__ cnt, 
 // Keys per thread of the load-first pass kernel for a word count, and the
 // tile each pass kernel uses (the load-first kernel moves the bucket-id
 // passes; the radix passes keep the 4096-key tiles, measured faster there).
-inline int pre_kpt(uint32_t words) { return words == 1 ? 12 : words == 2 ? 10 : words == 3 ? 8 : 6; }
+inline int pre_kpt(uint32_t words) {
+    return words == 1 ? 12 : words == 2 ? 10 : words == 3 ? 8 : words <= 5 ? 6 : words == 6 ? 5 : 4;
+}
 constexpr int kPreNT = 1024;  // threads of the load-first kernel
-// Passes over 1..4 words take the load-first kernel, wider keys the 256-thread one.
-inline bool use_pre(uint32_t words) { return words >= 1 && words <= 4; }
+// Passes over 1..8 words take the load-first kernel, wider keys the 256-thread one.
+inline bool use_pre(uint32_t words) { return words >= 1 && words <= 8; }
 inline uint64_t pass_tile(uint32_t words) {
     return use_pre(words) ? uint64_t(kPreNT) * pre_kpt(words) : uint64_t(kTile);
 }
@@ -528,7 +530,11 @@ void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, con
         case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
         case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
         case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        default: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 5: hipLaunchKernelGGL((k_onesweep_pre<5, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 6: hipLaunchKernelGGL((k_onesweep_pre<6, 5, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 7: hipLaunchKernelGGL((k_onesweep_pre<7, 4, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        default: hipLaunchKernelGGL((k_onesweep_pre<8, 4, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
     }
 }
 

@@ -171,7 +171,9 @@ def test_compress_key_too_long_flag(ck):
                                             (4096, 1, 40, 2), (4097, 1, 41, 3),
                                             (50000, 3, 192, 4), (12345, 2, 70, 5),
                                             (30000, 1, 1, 6), (70001, 1, 64, 7),
-                                            (9000, 4, 256, 8)])
+                                            (9000, 4, 256, 8), (20000, 5, 300, 9),
+                                            (7001, 6, 350, 10), (5000, 7, 420, 11),
+                                            (12345, 8, 512, 12), (3000, 9, 560, 13)])
 def test_sort_radix(ck, n, w, nbits, seed):
     import torch
     rng = np.random.default_rng(seed)
