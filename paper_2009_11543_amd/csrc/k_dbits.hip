@@ -50,10 +50,20 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
         if (MODE == kLoad16) {
             // 16 bytes of both keys per step (rows are 16-byte aligned and
             // the stride a multiple of 16, so a chunk starting inside the key
-            // stays inside the row); bytes at or past L read as zero.
+            // stays inside the row); bytes at or past L read as zero.  The
+            // first key's first chunk is the second key's of the pair one lane
+            // down (pairs are consecutive across lanes), so each row's first
+            // 16 bytes are read once; lane 0 reads its own.
+            const uint4 vb0 = *reinterpret_cast<const uint4 *>(pb);
+            uint4 va0;
+            va0.x = __shfl_up(vb0.x, 1, 64);
+            va0.y = __shfl_up(vb0.y, 1, 64);
+            va0.z = __shfl_up(vb0.z, 1, 64);
+            va0.w = __shfl_up(vb0.w, 1, 64);
+            if ((threadIdx.x & 63) == 0) va0 = *reinterpret_cast<const uint4 *>(pa);
             for (uint32_t c = 0; 16 * c < k.L; ++c) {
-                const uint4 va = *reinterpret_cast<const uint4 *>(pa + 16 * c);
-                const uint4 vb = *reinterpret_cast<const uint4 *>(pb + 16 * c);
+                const uint4 va = c == 0 ? va0 : *reinterpret_cast<const uint4 *>(pa + 16 * c);
+                const uint4 vb = c == 0 ? vb0 : *reinterpret_cast<const uint4 *>(pb + 16 * c);
                 const uint32_t xa[4] = {va.x, va.y, va.z, va.w}, xb[4] = {vb.x, vb.y, vb.z, vb.w};
                 bool done = false;
 #pragma unroll
