@@ -343,8 +343,10 @@ ckey_status ckey_cdf_grad(const void *model, const uint64_t *prefix, const float
  * uint32[n]) with method CKEY_SORT_LEARNED or CKEY_SORT_SPLITTER; predicted
  * (device uint32[n] or NULL, learned only) gets the network's raw guess;
  * stats (device uint64[2] or NULL, accumulated) gets the number of threshold
- * probes read from global memory (none for the splitter with up to 2^14
- * buckets: it holds every threshold in LDS) and the summed |bucket - guess|. */
+ * probes after the first guess (learned: the exact search from the network's
+ * guess, in LDS up to 2^14 buckets, else in global memory; splitter: the
+ * global search below its LDS sample, none up to 2^14 buckets, where every
+ * threshold is in LDS) and the summed |bucket - guess|. */
 ckey_status ckey_cdf_bucket(const void *model, uint32_t bucket_log2, uint32_t method,
                             const uint64_t *prefix, uint64_t n, uint32_t *bucket,
                             uint32_t *predicted, uint64_t *stats, void *stream);

@@ -4,6 +4,7 @@
 //   splitter: binary search of a 1-in-S sample of T held in LDS, then of T;
 //   learned:  a 4 -> 64 -> 1 ReLU MLP guesses b, then an exponential-then-
 //             binary search of T from the guess finds it exactly.
+// Up to 2^14 buckets (S == 1) all of T is held in LDS for both methods.
 #pragma once
 
 #include "internal.h"
@@ -34,7 +35,7 @@ inline uint32_t splitter_stride(uint32_t B) {
 // LDS layout: (splitter) the threshold sample, then (if a.hist) B/2 packed
 // 16-bit counters.
 inline size_t bucket_sample_words(const BucketArgs &a, int amode) {
-    if (amode != 0) return 0;
+    if (amode != 0) return a.S == 1 ? size_t(a.B) * 2 : 0;  // learned: all of T, or none
     return a.S == 1 ? size_t(a.B) * 2 : size_t(a.B / a.S) * 2;
 }
 
@@ -68,6 +69,39 @@ __device__ __forceinline__ uint32_t predict_bucket(const float *__restrict__ p, 
     if (!(y > 0.0f)) return 0;  // also maps NaN to 0
     if (y >= float(B)) return B - 1;
     return uint32_t(y);
+}
+
+// The network's guesses for N keys at once: each parameter is read once for
+// all N keys; every key's arithmetic is in the same order as mlp_eval's, so
+// the guesses equal predict_bucket's.
+template <int N>
+__device__ __forceinline__ void predict_bucket_n(const float *__restrict__ p, const uint64_t *x, uint32_t B,
+                                                 uint32_t *guess) {
+    float f[N][4], y[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        mlp_features(x[q], f[q]);
+        y[q] = p[6 * kH];
+    }
+#pragma unroll 8
+    for (int k = 0; k < kH; ++k) {
+        const float w0 = p[4 * k + 0], w1 = p[4 * k + 1], w2 = p[4 * k + 2], w3 = p[4 * k + 3];
+        const float b1 = p[4 * kH + k], v = p[5 * kH + k];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            float a = b1;
+            a = fmaf(w0, f[q][0], a);
+            a = fmaf(w1, f[q][1], a);
+            a = fmaf(w2, f[q][2], a);
+            a = fmaf(w3, f[q][3], a);
+            y[q] = fmaf(v, fmaxf(a, 0.0f), y[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const float t = y[q] * float(B);
+        guess[q] = !(t > 0.0f) ? 0u : t >= float(B) ? B - 1 : uint32_t(t);
+    }
 }
 
 // Exact bucket from a start guess: exponential search outward, then binary.
@@ -106,7 +140,7 @@ __device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ 
 
 template <int AMODE>
 __device__ __forceinline__ uint32_t *bucket_counters(const BucketArgs &a, uint32_t *s) {
-    return s + (AMODE == 0 ? (a.S == 1 ? 2 * a.B : (a.B / a.S) * 2) : 0);
+    return s + (a.S == 1 ? 2 * a.B : AMODE == 0 ? (a.B / a.S) * 2 : 0);
 }
 
 template <int AMODE>
@@ -115,14 +149,12 @@ __device__ __forceinline__ void bucket_lds_init(const BucketArgs &a, uint32_t *s
         uint32_t *h = bucket_counters<AMODE>(a, s);
         for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) h[t] = 0;
     }
-    if (AMODE == 0) {
-        if (a.S == 1) {
-            uint64_t *th = reinterpret_cast<uint64_t *>(s);
-            for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = a.T[t];
-        } else {
-            uint64_t *ts = reinterpret_cast<uint64_t *>(s);
-            for (uint32_t t = threadIdx.x; t < a.B / a.S; t += blockDim.x) ts[t] = a.T[uint64_t(t) * a.S];
-        }
+    if (a.S == 1) {  // every threshold (both methods)
+        uint64_t *th = reinterpret_cast<uint64_t *>(s);
+        for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = a.T[t];
+    } else if (AMODE == 0) {  // the splitter's 1-in-S sample
+        uint64_t *ts = reinterpret_cast<uint64_t *>(s);
+        for (uint32_t t = threadIdx.x; t < a.B / a.S; t += blockDim.x) ts[t] = a.T[uint64_t(t) * a.S];
     }
 }
 
@@ -131,6 +163,7 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
                                               uint32_t &probes, uint32_t &guess) {
     if (AMODE == 1) {
         guess = predict_bucket(a.p, x, a.B);
+        if (a.S == 1) return correct_bucket(reinterpret_cast<const uint64_t *>(s), a.B, x, guess, probes);
         return correct_bucket(a.T, a.B, x, guess, probes);
     }
     if (a.S == 1) {  // every threshold in LDS

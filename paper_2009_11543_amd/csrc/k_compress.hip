@@ -315,6 +315,16 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
                     const uint64_t r = base + uint64_t(q) * kBucketWG;
                     if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
                 }
+            } else if (AMODE == 1 && ba.S == 1) {  // the keys' networks together, searches in LDS
+                uint32_t g[KPI];
+                predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
+#pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    uint32_t probes = 0;
+                    const uint32_t b = correct_bucket(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q], probes);
+                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < KPI; ++q) {
