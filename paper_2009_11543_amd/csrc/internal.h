@@ -82,16 +82,20 @@ __device__ __forceinline__ uint32_t bitmap_word_bit(uint32_t p) {
     return 1u << (8 * ((p >> 3) & 3) + (7 - (p & 7)));
 }
 
-// Dynamic LDS above 64 KB needs the kernel attribute raised: once per
-// (device, kernel), remembered so that later calls pay nothing.
+// Dynamic LDS above 64 KB needs the kernel attribute raised, to the 160 KB
+// of a CU less the kernel's static LDS: once per (device, kernel), remembered
+// so that later calls pay nothing.
 inline void raise_lds_limit(const void *fn) {
     static std::mutex mu;
     static std::set<std::pair<int, const void *>> done;
     int dev = 0;
     (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> g(mu);
-    if (done.insert({dev, fn}).second)
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (done.insert({dev, fn}).second) {
+        hipFuncAttributes at{};
+        const size_t stat = hipFuncGetAttributes(&at, fn) == hipSuccess ? at.sharedSizeBytes : 0;
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(160 * 1024 - stat));
+    }
 }
 
 // Event timing around a launch when profiling is enabled (profiler.hip).

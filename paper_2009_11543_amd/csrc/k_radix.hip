@@ -613,14 +613,18 @@ AuxLayout aux_layout(uint32_t words, uint64_t n) {
 
 size_t aux_sort_workspace(uint32_t words, uint64_t n) { return aux_layout(words, n).total; }
 
-// Pass histograms of the two aux digits from a histogram over all 2^aux_bits
-// aux values: thread d sums digit value d of the low pass and thread 256 + d
-// of the high one.  LDS: the histogram is staged in LDS first (16-byte
-// loads; 2^aux_bits <= 2^15), else the sums read it from global memory.
+// Pass starts of the two aux digits from a histogram over all 2^aux_bits aux
+// values: thread d sums digit value d of the low pass and thread 256 + d of
+// the high one, then each pass's 256 sums are scanned (exclusive) in place of
+// a separate histogram + scan; the passes' tile counters are cleared too.
+// LDS: the histogram is staged in LDS first (16-byte loads; 2^aux_bits <=
+// 2^15), else the sums read it from global memory.
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_aux_hist(const uint32_t *__restrict__ full, uint32_t aux_bits,
-                                                   uint32_t lo, uint32_t *__restrict__ hist) {
+                                                   uint32_t lo, uint32_t *__restrict__ hist,
+                                                   uint32_t *__restrict__ counters) {
     extern __shared__ uint32_t s_full[];
+    __shared__ uint32_t s_tot[8];
     const uint32_t tid = threadIdx.x, hi = aux_bits - lo, m = 1u << aux_bits;
     const uint32_t *src = full;
     if (LDS) {
@@ -634,21 +638,26 @@ __global__ __launch_bounds__(1024) void k_aux_hist(const uint32_t *__restrict__ 
         __syncthreads();
         src = s_full;
     }
-    if (tid < kRadixMax) {
-        const uint32_t d = tid;
-        if (lo) {
-            uint32_t s0 = 0;
-            if (d < (1u << lo))
-                for (uint32_t h = 0; h < (1u << hi); ++h) s0 += src[(h << lo) | d];
-            hist[d] = s0;
-        }
-    } else if (tid < 2 * kRadixMax) {
-        const uint32_t d = tid - kRadixMax;
-        uint32_t s1 = 0;
-        if (d < (1u << hi))
-            for (uint32_t l = 0; l < (1u << lo); ++l) s1 += src[(d << lo) | l];
-        hist[(lo ? kRadixMax : 0) + d] = s1;
+    const uint32_t pass = tid >> 8, d = tid & 255u;  // pass 0: low digit, 1: high digit
+    uint32_t v = 0;
+    if (pass == 0 && lo && d < (1u << lo))
+        for (uint32_t h = 0; h < (1u << hi); ++h) v += src[(h << lo) | d];
+    if (pass == 1 && d < (1u << hi))
+        for (uint32_t l = 0; l < (1u << lo); ++l) v += src[(d << lo) | l];
+    const uint32_t incl = wave_incl_scan(v);
+    const uint32_t wave = tid >> 6, lane = tid & 63u;
+    if (lane == 63 && wave < 8) s_tot[wave] = incl;
+    __syncthreads();
+    if (pass < 2) {
+        uint32_t off = 0;
+        for (uint32_t w = 4 * pass; w < wave; ++w) off += s_tot[w];
+        const uint32_t ex = off + incl - v;
+        if (lo)
+            hist[pass * kRadixMax + d] = ex;
+        else if (pass == 1)
+            hist[d] = ex;
     }
+    if (tid < 2) counters[tid] = 0u;
 }
 
 ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint16_t *aux, uint64_t n,
@@ -667,8 +676,6 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
     std::vector<Pass> ps;
     if (lo) ps.push_back({kAuxWord, 0, lo});
     ps.push_back({kAuxWord, lo, hi});
-    CKEY_TRY(fill_u32(hist, 2 * kRadixMax, 0, st));
-    CKEY_TRY(fill_u32(counters, 2, 0, st));
     HistArgs ha{};
     for (size_t p = 0; p < ps.size(); ++p) {
         ha.shift[p] = ps[p].shift;
@@ -676,24 +683,28 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
         ha.out[p] = uint32_t(p);
     }
     ha.npass = uint32_t(ps.size());
-    if (aux_full_hist) {
+    if (aux_full_hist) {  // pass starts and cleared counters in one launch
         if (aux_bits <= 15) {
             raise_lds_limit(reinterpret_cast<const void *>(k_aux_hist<true>));
             hipLaunchKernelGGL(k_aux_hist<true>, dim3(1), dim3(1024), size_t(4) << aux_bits, st, aux_full_hist,
-                               aux_bits, lo, hist);
+                               aux_bits, lo, hist, counters);
         } else {
-            hipLaunchKernelGGL(k_aux_hist<false>, dim3(1), dim3(1024), 0, st, aux_full_hist, aux_bits, lo, hist);
+            hipLaunchKernelGGL(k_aux_hist<false>, dim3(1), dim3(1024), 0, st, aux_full_hist, aux_bits, lo, hist,
+                               counters);
         }
+        CKEY_TRY(launch_status());
     } else {
+        CKEY_TRY(fill_u32(hist, 2 * kRadixMax, 0, st));
+        CKEY_TRY(fill_u32(counters, 2, 0, st));
         uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
         if (hblocks > 2048) hblocks = 2048;
         const int pr_ = prof_begin(st, "hist");
         hipLaunchKernelGGL(k_hist<uint16_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, aux, n, ha, hist);
         prof_end(st, pr_);
+        CKEY_TRY(launch_status());
+        hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist);
+        CKEY_TRY(launch_status());
     }
-    CKEY_TRY(launch_status());
-    hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist);
-    CKEY_TRY(launch_status());
     // With two passes: caller -> workspace (moving aux) -> caller.
     Bufs first{ck, rid_identity ? nullptr : rid, alt, alt_rid, n, n, aux, ps.size() == 2 ? alt_aux : nullptr};
     Bufs second{alt, alt_rid, ck, rid, n, n, alt_aux, nullptr};
