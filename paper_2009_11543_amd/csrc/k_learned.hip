@@ -1031,9 +1031,13 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
             auto kb = words == 1 ? k_bucket_sort<1, kCapSmall, 512> : words == 2 ? k_bucket_sort<2, kCapSmall, 512>
                     : words == 3 ? k_bucket_sort<3, kCapSmall, 512> : k_bucket_sort<0, kCapSmall, 512>;
             hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
-        } else {
+        } else if (n / B <= 4400) {  // 5120-row capacity, 1024 threads, 2 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapLarge, 1024> : words == 2 ? k_bucket_sort<2, kCapLarge, 1024>
                     : words == 3 ? k_bucket_sort<3, kCapLarge, 1024> : k_bucket_sort<0, kCapLarge, 1024>;
+            hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
+        } else {  // 10240-row capacity, 1 per CU (mean buckets beyond 4400 rows)
+            auto kb = words == 1 ? k_bucket_sort<1, kCapHuge, 1024> : words == 2 ? k_bucket_sort<2, kCapHuge, 1024>
+                    : words == 3 ? k_bucket_sort<3, kCapHuge, 1024> : k_bucket_sort<0, kCapHuge, 1024>;
             hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
         }
         prof_end(st, pr);
