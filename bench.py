@@ -46,6 +46,8 @@ def training_rows(name, n, seed=2):
         return datagen.uniform_keys(n, seed=seed)
     if name == "cluster32_2p28":
         return datagen.cluster_keys(n, seed=seed)
+    if name == "url128_2p24":  # zero-padded rows compress to the same words as the varchar form
+        return datagen.url_keys(n, seed=seed)[0]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -59,6 +61,9 @@ def workload(name):
         return datagen.uniform_keys(1 << 28, seed=1), "2^28 x 32 uniform bytes, seed 1"
     if name == "cluster32_2p28":
         return datagen.cluster_keys(1 << 28, seed=1), "2^28 x 32 bytes, 2^16 stems + uniform last byte, seed 1"
+    if name == "url128_2p24":  # (zero-padded rows, lengths): the device gets flat bytes + offsets
+        return datagen.url_keys(1 << 24, seed=1), ("2^24 URL-like keys of 20-120 bytes (mean 70), "
+                                                   "zero-padded to 128, as flat bytes + offsets, seed 1")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -417,8 +422,17 @@ def main():
         return bench_zipf(args, torch, ckey, dev)
     log(f"generating workload {args.workload}")
     rows, desc = workload(args.workload)
+    lens = None
+    if isinstance(rows, tuple):  # varchar keys: the zero-padded rows serve the host baselines
+        rows, lens = rows
     n, L = rows.shape
-    keys = ckey.DeviceKeys(torch.from_numpy(rows).to(dev))
+    if lens is None:
+        keys = ckey.DeviceKeys(torch.from_numpy(rows).to(dev))
+    else:
+        from paper_2009_11543_amd import datagen
+        flat, offs = datagen.pack_varlen(rows, lens)
+        keys = ckey.DeviceKeys.from_numpy(flat, key_bytes=L, offsets=offs)
+        del flat, offs
     torch.cuda.synchronize()
     log(f"keys resident: n={n} L={L}")
     if args.bucket_log2 == 0:
@@ -565,6 +579,8 @@ def main():
 
     # Algorithmic bytes per key of each kernel.
     key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
+    if lens is not None:  # varchar keys are staged whole, with their 8-byte offsets
+        key_bytes_read = float(lens.mean()) + 8
     rec = 8 * w + 4
     # compress_bucket writes words + bucket id (the first bucket pass generates
     # the record IDs); the two bucket passes move rec + 2 bytes in and out,

@@ -200,6 +200,25 @@ struct LdsLoader {
     }
 };
 
+// A variable-length key read from the LDS tile (s non-null) or, for a
+// workgroup whose keys exceed the tile, byte by byte from global memory.
+struct VarLoader {
+    const uint32_t *s;
+    uint32_t o;
+    uint32_t len;
+    const uint8_t *p;
+    __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, int g, uint32_t *x) const {
+        if (s) {
+            LdsLoader{s, o, len}(plan, c, g, x);
+        } else {
+            const uint32_t cb = plan.chunk[c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (plan.op[4 * c + q].m) x[q] = key_word_bytes(p, 4 * cb + q, len);
+        }
+    }
+};
+
 __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan plan,
                                                       uint64_t *__restrict__ ck,
                                                       uint32_t *__restrict__ rowids,
@@ -244,13 +263,10 @@ __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan pla
     const uint64_t o0 = k.offsets[i], o1 = k.offsets[i + 1];
     uint32_t len = uint32_t(min<uint64_t>(o1 - o0, k.L));
     if (o1 - o0 > k.L && flags) atomicOr(flags, CKEY_FLAG_KEY_TOO_LONG);
-    if (fits) {
-        LdsLoader ld{s_tile, uint32_t(base + o0 - a0), len};
-        compress_key(plan, ld, ck, k.n, i);
-    } else {
-        GlobalLoader<kLoadBytes> ld{k.bytes + o0, len};
-        compress_key(plan, ld, ck, k.n, i);
-    }
+    // One loader for both cases (one compress_key instance keeps the plan in
+    // the kernel-argument segment instead of a per-lane copy).
+    VarLoader ld{fits ? s_tile : nullptr, uint32_t(fits ? base + o0 - a0 : 0), len, k.bytes + o0};
+    compress_key(plan, ld, ck, k.n, i);
     if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
 }
 

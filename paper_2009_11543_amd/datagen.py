@@ -170,6 +170,36 @@ def pack_varlen(rows, lengths):
     return np.ascontiguousarray(rows[mask]), offsets
 
 
+_HOST_CHARS = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz.", np.uint8).copy()
+_PATH_CHARS = np.frombuffer(b"abcdefghijklmnopqrstuvwxyz0123456789", np.uint8).copy()
+
+
+def url_keys(n=1 << 24, seed=1, width=128, min_len=20, max_len=120, hosts=256, host_s=1.1):
+    """URL-like varchar keys.  256 seeded host prefixes of 10-30 chars over
+    [a-z.]; each key takes one (Zipf s = 1.1 over the hosts) and appends 1-6
+    path segments of 3-12 chars over [a-z0-9], each after a '/'.  The key's
+    length is drawn uniformly in [20, 120]: the host + segments string is cut
+    there, or its last segment is extended with more [a-z0-9] chars to reach
+    it.  Returns (rows (n, width) zero-padded, lengths); pack_varlen gives the
+    flat bytes + offsets of the variable-length form."""
+    rng = rng_for(seed)
+    hl = rng.integers(10, 31, hosts)
+    host_rows = _HOST_CHARS[rng.integers(0, len(_HOST_CHARS), (hosts, 30))]
+    h = zipf_sampler(rng, host_s, hosts, n)
+    lens = rng.integers(min_len, max_len + 1, n)
+    rows = _PATH_CHARS[rng.integers(0, len(_PATH_CHARS), (n, width), dtype=np.uint8)]
+    rows[:, :30] = np.where(np.arange(30)[None, :] < hl[h][:, None], host_rows[h], rows[:, :30])
+    nseg = rng.integers(1, 7, n)
+    seg = rng.integers(3, 13, (n, 6))
+    pos = hl[h][:, None] + np.arange(6)[None, :] + np.concatenate(
+        [np.zeros((n, 1), np.int64), np.cumsum(seg, axis=1)[:, :-1]], axis=1)  # '/' before segment j
+    ok = (np.arange(6)[None, :] < nseg[:, None]) & (pos < lens[:, None])
+    r, c = np.nonzero(ok)
+    rows[r, pos[r, c]] = ord("/")
+    rows[np.arange(width)[None, :] >= lens[:, None]] = 0
+    return rows, lens
+
+
 def _title_vocab(rng, size=50000):
     """Unique [a-z]{2..12} words, first letter capitalised: (size, 12) bytes + lengths."""
     out, lens, seen = [], [], set()
