@@ -385,3 +385,24 @@ def test_bucket_second_chance(ck, words, too_big):
     np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
     np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
     assert bool(int(flags.item()) & ck.CKEY_FLAG_BUCKET_OVERFLOW) == too_big
+
+
+@pytest.mark.parametrize("bucket_log2", [15, 16])
+def test_fused_compress_sort_sampled_thresholds(ck, bucket_log2):
+    """Beyond 2^14 buckets only a 1-in-S sample of the thresholds fits in LDS:
+    the fused compress + bucket kernel searches the sample, then T, for four
+    keys at once; the permutation equals the oracle's full-key order."""
+    rows = datagen.uniform_keys(1 << 19, seed=3, key_bytes=32)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    rows_t = datagen.uniform_keys(1 << 18, seed=4, key_bytes=32)
+    kt = ck.DeviceKeys.from_numpy(rows_t)
+    ckt, ridt = ck.ckey_compress(kt, d)
+    ck.ckey_sort(ckt, ck.ckey_plan_query(d)["nbits"], ridt)
+    model = ck.CdfModel(bucket_log2=bucket_log2, seed=1)
+    ck.ckey_cdf_fit(model, ckt[0].contiguous(), steps=20, batch=4096)
+    for meth in (ck.CKEY_SORT_SPLITTER, ck.CKEY_SORT_LEARNED):
+        ckd, rid = ck.ckey_compress_sort(ck.DeviceKeys.from_numpy(rows), d, method=meth, model=model)
+        np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+        np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, d)[:, perm])
