@@ -1,6 +1,7 @@
 """Full-size checks of the other configurations: URL-like varchar keys at
-2^24 rows (flat bytes + offsets) and 32-byte keys at 2^28 rows (uniform, and
-2^16 clusters that share a 31-byte stem).  As for the 2^26 DNA keys, the
+2^24 rows (flat bytes + offsets), 32-byte keys at 2^28 rows (uniform, and
+2^16 clusters that share a 31-byte stem) and the eight-index table at 2^24
+rows rebuilt in one call.  As for the 2^26 DNA keys, the
 oracle cannot sort these sizes in test time, so the checks are what holds at
 any size plus rows the oracle computes one by one:
   * the first build's permutation is a permutation whose adjacent rows are in
@@ -115,3 +116,20 @@ def test_cluster32_2p28(ck):
     rows = datagen.cluster_keys(1 << 28, seed=1)
     keys = ck.DeviceKeys(torch.from_numpy(rows).cuda())
     run_config(ck, keys, rows, None, 16, ["radix"])
+
+
+def test_table8_2p24_batched(ck):
+    """All eight indexes of the 2^24-row table rebuilt in one call (forked
+    streams): each index's permutation and D-bitmap by the same checks."""
+    import torch
+    tab = datagen.table_indexes(1 << 24, seed=1)
+    keys = {name: ck.DeviceKeys(torch.from_numpy(rows).cuda()) for name, rows in tab.items()}
+    outs = ck.ckey_rebuild_index([{"keys": k, "bitmap": None} for k in keys.values()])
+    for (name, rows), out in zip(tab.items(), outs):
+        n, L = rows.shape
+        W = (L + 7) // 8
+        padded = np.zeros((n, 8 * W), np.uint8)
+        padded[:, :L] = rows
+        perm = out["perm"].cpu().numpy().view(np.uint32)
+        d = out["bitmap"].cpu().numpy()
+        check_order_and_d(padded.view(">u8"), perm, np.concatenate([d, np.zeros(8 * W - L, np.uint8)]))
