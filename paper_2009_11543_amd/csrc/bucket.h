@@ -149,7 +149,23 @@ __device__ __forceinline__ void bucket_lds_init(const BucketArgs &a, uint32_t *s
         uint32_t *h = bucket_counters<AMODE>(a, s);
         for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) h[t] = 0;
     }
-    if (a.S == 1) {  // every threshold (both methods)
+    if (a.S == 1 && AMODE == 0) {
+        // Splitter: T[1..B) in breadth-first (Eytzinger) order, e[i] for node
+        // i of the perfect search tree of depth log2(B) -- node i at level k,
+        // position p in its level, holds T[(2p + 1) << (log2(B) - 1 - k)].
+        // The search's early levels then read neighbouring words (distinct
+        // LDS banks) instead of words a power of two apart (one bank).
+        uint64_t *e = reinterpret_cast<uint64_t *>(s);
+        const uint32_t d = 31u - uint32_t(__clz(a.B));
+        for (uint32_t i = threadIdx.x; i < a.B; i += blockDim.x) {
+            if (i == 0) {
+                e[0] = 0;
+                continue;
+            }
+            const uint32_t k = 31u - uint32_t(__clz(i)), p = i - (1u << k);
+            e[i] = a.T[(2 * p + 1) << (d - 1 - k)];
+        }
+    } else if (a.S == 1) {  // learned: T in sorted order (searched outward from a guess)
         uint64_t *th = reinterpret_cast<uint64_t *>(s);
         for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = a.T[t];
     } else if (AMODE == 0) {  // the splitter's 1-in-S sample
@@ -166,15 +182,12 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
         if (a.S == 1) return correct_bucket(reinterpret_cast<const uint64_t *>(s), a.B, x, guess, probes);
         return correct_bucket(a.T, a.B, x, guess, probes);
     }
-    if (a.S == 1) {  // every threshold in LDS
-        const uint64_t *th = reinterpret_cast<const uint64_t *>(s);
-        uint32_t lo = 0, hi = a.B;  // T[lo] <= x < T[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (th[mid] <= x) lo = mid; else hi = mid;
-        }
-        guess = lo;
-        return lo;
+    if (a.S == 1) {  // every threshold in LDS, breadth-first: descend log2(B) levels
+        const uint64_t *e = reinterpret_cast<const uint64_t *>(s);
+        uint32_t i = 1;
+        while (i < a.B) i = 2 * i + (e[i] <= x ? 1u : 0u);
+        guess = i - a.B;  // the number of T[1..B) at most x
+        return guess;
     }
     const uint64_t *ts = reinterpret_cast<const uint64_t *>(s);
     uint32_t lo = 0, hi = a.B / a.S;  // ts[lo] <= x < ts[hi]
@@ -192,23 +205,22 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
     return l2;
 }
 
-// Splitter search of several keys at once (every threshold in LDS, S == 1, B a
-// power of two): a fixed log2(B)-step lower bound per key, the keys' steps
-// interleaved so their LDS reads overlap.  b[q] = the largest b with
-// T[b] <= x[q] (T[0] = 0).
+// Splitter search of several keys at once (every threshold in LDS in
+// breadth-first order, S == 1, B a power of two): log2(B) levels per key, the
+// keys' steps interleaved so their LDS reads overlap.  b[q] = the largest b
+// with T[b] <= x[q] (T[0] = 0), i.e. the number of T[1..B) at most x[q].
 template <int N>
 __device__ __forceinline__ void splitter_search_n(const BucketArgs &a, const uint32_t *s,
                                                   const uint64_t *x, uint32_t *b) {
-    const uint64_t *th = reinterpret_cast<const uint64_t *>(s);
+    const uint64_t *e = reinterpret_cast<const uint64_t *>(s);
 #pragma unroll
-    for (int q = 0; q < N; ++q) b[q] = 0;
-    for (uint32_t step = a.B >> 1; step >= 1; step >>= 1) {
+    for (int q = 0; q < N; ++q) b[q] = 1;
+    for (uint32_t lv = a.B >> 1; lv >= 1; lv >>= 1) {
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
-            const uint32_t m = b[q] + step;
-            b[q] = th[m] <= x[q] ? m : b[q];
-        }
+        for (int q = 0; q < N; ++q) b[q] = 2 * b[q] + (e[b[q]] <= x[q] ? 1u : 0u);
     }
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] -= a.B;
 }
 
 template <int AMODE>
