@@ -18,6 +18,13 @@
 //               array loaded before any work, 4096..12288-key tiles: longer
 //               runs per bucket and tile); wider keys take 4096-key tiles.
 //
+// The grouping by a 16-bit aux key (the bucket ids of the bucketing sort,
+// aux_sort) uses the same pass kernels, but takes each tile's starts from a
+// table instead of the look-back: k_tile_counts counts the pass digit per
+// tile from the 2-byte aux key and k_tile_scan scans each digit's counts over
+// the tiles; k_aux_hist derives both passes' starts from the full bucket
+// histogram.
+//
 // The look-back waits only on tiles whose workgroups started earlier (tile
 // numbers are handed out in start order), so every wait ends; a spin bound
 // still guarantees termination and raises CKEY_FLAG_SPIN_LIMIT.
