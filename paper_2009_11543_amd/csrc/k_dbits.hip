@@ -17,6 +17,24 @@ __device__ __forceinline__ uint32_t load_key_word(const KeySrc &k, uint64_t row,
     return MODE == kLoadBytes ? key_word_bytes(p, j, len) : key_word_aligned(p, j, len);
 }
 
+// Word j of a key at any byte offset o of a 4-byte aligned buffer of `total`
+// bytes: the two aligned 32-bit words around it, funnel-shifted, when both lie
+// inside the buffer (else byte by byte); bytes at or past len read as zero.
+__device__ __forceinline__ uint32_t key_word_unaligned(const uint8_t *bytes, uint64_t total, uint64_t o,
+                                                       uint32_t j, uint32_t len) {
+    const int32_t have = int32_t(len) - int32_t(4 * j);
+    if (have <= 0) return 0u;
+    const uint64_t b = o + 4 * uint64_t(j);
+    const uint64_t wa = b >> 2;
+    if (4 * (wa + 2) > total) return key_word_bytes(bytes + o, j, len);
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(bytes);
+    const uint32_t lo = w[wa], hi = w[wa + 1];
+    const uint32_t sh = 8 * uint32_t(b & 3);
+    uint32_t v = __builtin_bswap32(sh ? (lo >> sh) | (hi << (32 - sh)) : lo);
+    if (have < 4) v &= ~(0xFFFFFFFFu >> (8 * have));
+    return v;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restrict__ order,
                                                uint32_t *__restrict__ acc,
@@ -29,6 +47,10 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
     bool desc = false;
     bool too_long = false;
     const uint64_t step = uint64_t(gridDim.x) * kWG;
+    // byte-addressed keys in a 4-byte aligned buffer: word reads (else 0: bytes)
+    const uint64_t total = (MODE == kLoadBytes && (reinterpret_cast<uintptr_t>(k.bytes) & 3u) == 0)
+                               ? (k.offsets ? k.offsets[k.n] : k.n * uint64_t(k.stride))
+                               : 0;
     for (uint64_t i = 1 + uint64_t(blockIdx.x) * kWG + threadIdx.x; i < k.n; i += step) {
         const uint64_t ra = order ? order[i - 1] : i - 1;
         const uint64_t rb = order ? order[i] : i;
@@ -90,8 +112,14 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
             continue;
         }
         for (uint32_t j = 0; j < nw; ++j) {
-            uint32_t x = load_key_word<MODE>(k, ra, j, pa, la);
-            uint32_t y = load_key_word<MODE>(k, rb, j, pb, lb);
+            uint32_t x, y;
+            if (MODE == kLoadBytes && total) {
+                x = key_word_unaligned(k.bytes, total, uint64_t(pa - k.bytes), j, la);
+                y = key_word_unaligned(k.bytes, total, uint64_t(pb - k.bytes), j, lb);
+            } else {
+                x = load_key_word<MODE>(k, ra, j, pa, la);
+                y = load_key_word<MODE>(k, rb, j, pb, lb);
+            }
             if (x != y) {
                 uint32_t lz = __clz(x ^ y);
                 uint32_t p = 32 * j + lz;
