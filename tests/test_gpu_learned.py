@@ -406,3 +406,24 @@ def test_fused_compress_sort_sampled_thresholds(ck, bucket_log2):
         ckd, rid = ck.ckey_compress_sort(ck.DeviceKeys.from_numpy(rows), d, method=meth, model=model)
         np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
         np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, d)[:, perm])
+
+
+def test_fused_compress_sort_wide_keys(ck):
+    """Keys of 80 bytes sorted over all 640 bits (10 words): the fused path's
+    grouping passes over more than 8 words, where the first pass generates
+    the record IDs in the 256-thread pass kernel."""
+    rng = np.random.default_rng(31)
+    n = (1 << 15) + 3
+    rows = rng.integers(0, 4, (n, 80), dtype=np.uint8) * np.uint8(0x40)  # few values: long shared prefixes
+    rows[:, 70:] = rng.integers(0, 256, (n, 10), dtype=np.uint8)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    bm = np.full(80, 0xFF, np.uint8)
+    ckt, ridt = ck.ckey_compress(ck.DeviceKeys.from_numpy(rows), bm)
+    ck.ckey_sort(ckt, 640, ridt)
+    model = ck.CdfModel(bucket_log2=8, seed=1)
+    ck.ckey_cdf_fit(model, ckt[0].contiguous(), steps=20, batch=4096)
+    ckd, rid = ck.ckey_compress_sort(ck.DeviceKeys.from_numpy(rows), bm, method=ck.CKEY_SORT_SPLITTER,
+                                     model=model)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, bm)[:, perm])
