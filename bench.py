@@ -577,7 +577,7 @@ def main():
     log(f"chosen {best}: {ms:.3f} ms/step; kernels {json.dumps(kern)}")
     assert int(flags.item()) & ckey.CKEY_FLAG_SPIN_LIMIT == 0
 
-    # Algorithmic bytes per key of each kernel.
+    # Algorithmic bytes per key of each kernel: what it must read and write once.
     key_bytes_read = len({b for s, _ in plan["windows"] for b in range(s, min(s + 8, L))})
     if lens is not None:  # varchar keys are staged whole, with their 8-byte offsets
         key_bytes_read = float(lens.mean()) + 8

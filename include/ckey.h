@@ -56,6 +56,10 @@ typedef enum {
 /* Limits of this build. */
 #define CKEY_MAX_KEY_BYTES 2048u          /* key_bytes                       */
 #define CKEY_MAX_ROWS (1ull << 30)        /* n                               */
+/* Limits of the one-launch table rebuild (ckey_sort_opts.fused_table). */
+#define CKEY_TABLE_MAX_INDEXES 8u         /* indexes per call                 */
+#define CKEY_TABLE_MAX_KEY_BYTES 64u      /* key_bytes of each index          */
+#define CKEY_TABLE_MAX_PASSES 64u         /* radix passes of each index       */
 
 /* A set of n keys in device memory.
  *   offsets == NULL: fixed width; key i occupies bytes[i*stride, i*stride+key_bytes).
@@ -115,6 +119,9 @@ typedef struct {
                             * index-rebuild entry points ignore it                   */
     const void *model;    /* learned/splitter: device model memory (ckey_cdf_*)        */
     uint32_t *flags;      /* device flags word or NULL                                 */
+    uint32_t fused_table; /* ckey_rebuild_index / ckey_graph_create only (the call's
+                           * opts): 1 = every index rebuilt by one persistent kernel
+                           * launch (radix method; see ckey_rebuild_index)          */
 } ckey_sort_opts;
 
 /* Sort (compressed key, row id) pairs (Sec. 3.2 compressed key sort; Sec. 5,
@@ -167,7 +174,21 @@ typedef struct {
  * opts as for ckey_sort (NULL = radix), per index overridable.  With count > 1
  * each index gets its own part of the workspace and its own stream forked from
  * `stream` (and joined back), so the indexes' kernels overlap.  Needs a
- * workspace. */
+ * workspace.
+ *
+ * opts->fused_table = 1: the whole table in one persistent kernel launch (after
+ * one fill kernel that clears its counters), whose workgroups take work items
+ * from a queue -- per index: compress tiles, a histogram scan, the tiles of each
+ * radix pass, refresh tiles -- each waiting on the items it depends on.  Every
+ * index must use the radix method (per-index digit_bits allowed); at most
+ * CKEY_TABLE_MAX_INDEXES indexes of at most CKEY_TABLE_MAX_KEY_BYTES key bytes,
+ * n < 2^30 and at most CKEY_TABLE_MAX_PASSES passes each, else
+ * CKEY_ERR_UNSUPPORTED.  The workspace layout differs from the forked form
+ * (query with the same opts).  A wait that exceeds its spin bound raises
+ * CKEY_FLAG_SPIN_LIMIT in that index's flags word (the results are then not
+ * valid).  In this build the one-launch form is switched off: workspace
+ * queries and argument checks work, a real call (and ckey_graph_create)
+ * returns CKEY_ERR_UNSUPPORTED. */
 ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *workspace,
                                size_t *workspace_bytes, void *stream);
@@ -177,8 +198,9 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
  * enqueues (the descriptors' pointers, bitmaps and sizes are fixed at
  * creation; the workspace must stay valid while the graph exists) and
  * instantiates it; only the radix method can be captured (the bucketing
- * methods read an overflow count back to the host).  ckey_graph_launch
- * replays it on `stream`. */
+ * methods read an overflow count back to the host).  With opts->fused_table
+ * the graph holds the fill kernel and the one persistent launch.
+ * ckey_graph_launch replays it on `stream`. */
 typedef struct ckey_graph ckey_graph;
 ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
                               void *workspace, size_t workspace_bytes, ckey_graph **graph);

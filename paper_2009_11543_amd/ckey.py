@@ -21,6 +21,7 @@ CKEY_FLAG_SPIN_LIMIT = 0x4
 CKEY_FLAG_BUCKET_OVERFLOW = 0x8
 CKEY_SORT_RADIX, CKEY_SORT_LEARNED, CKEY_SORT_SPLITTER = 0, 1, 2
 MAX_KEY_BYTES = 2048
+TABLE_MAX_INDEXES, TABLE_MAX_KEY_BYTES, TABLE_MAX_PASSES = 8, 64, 64  # one-launch table rebuild
 
 
 class CkeyError(RuntimeError):
@@ -37,7 +38,8 @@ class ckey_keys(ctypes.Structure):
 class ckey_sort_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
                 ("bucket_log2", ctypes.c_uint32), ("skip_trivial", ctypes.c_uint32),
-                ("model", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p), ("flags", ctypes.c_void_p),
+                ("fused_table", ctypes.c_uint32)]
 
 
 class ckey_index_desc(ctypes.Structure):
@@ -303,12 +305,13 @@ def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, s
     return ck, rid
 
 
-def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=None, model=None, flags=None, skip_trivial=False):
+def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=None, model=None, flags=None, skip_trivial=False,
+          fused_table=False):
     if bucket_log2 is None:
         bucket_log2 = model.bucket_log2 if model is not None else 0
     return ckey_sort_opts(method, digit_bits, bucket_log2, 1 if skip_trivial else 0,
                           None if model is None else model.handle,
-                          None if flags is None else flags.data_ptr())
+                          None if flags is None else flags.data_ptr(), 1 if fused_table else 0)
 
 
 def ckey_compress_sort(keys, bitmap, out=None, rowids=None, words=None, workspace=None,

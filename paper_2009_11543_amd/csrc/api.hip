@@ -164,6 +164,44 @@ ckey_status enqueue_one(const ckey_index_desc &D, const ckey_sort_opts *o, const
     return CKEY_OK;
 }
 
+constexpr bool kFusedTableEnabled = false;
+
+// The whole table in one persistent launch (opts->fused_table): every index
+// radix-sorted, key_bytes and pass count within the persistent kernel's limits.
+// ws == nullptr: the workspace size into *ws_bytes.
+ckey_status fused_rebuild(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
+                          bool real_call, void *ws, size_t *ws_bytes, hipStream_t st) {
+    if (!idx || count == 0 || !ws_bytes) return CKEY_ERR_INVALID;
+    if (count > CKEY_TABLE_MAX_INDEXES) return CKEY_ERR_UNSUPPORTED;
+    TableIndex ti[CKEY_TABLE_MAX_INDEXES];
+    uint8_t bms[CKEY_TABLE_MAX_INDEXES][CKEY_TABLE_MAX_KEY_BYTES];
+    for (uint32_t x = 0; x < count; ++x) {
+        const ckey_index_desc &D = idx[x];
+        const ckey_sort_opts *o = D.opts ? D.opts : opts;
+        CKEY_TRY(check_sort_opts(o, false));
+        if (method_of(o) != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+        CKEY_TRY(check_keys(&D.keys));
+        const uint32_t L = D.keys.key_bytes;
+        if (L > CKEY_TABLE_MAX_KEY_BYTES) return CKEY_ERR_UNSUPPORTED;
+        if (real_call && D.keys.n > 0 && !D.perm) return CKEY_ERR_INVALID;
+        memset(bms[x], 0xFF, L);  // first build: every position (Sec. 4.3)
+        if (D.bitmap_in) memcpy(bms[x], D.bitmap_in, L);
+        ti[x] = TableIndex{key_src(&D.keys), bms[x], digit_bits_of(o), D.perm, D.ckeys, D.pair_pos,
+                           D.bitmap_out, D.flags ? D.flags : (o ? o->flags : nullptr)};
+    }
+    size_t need = 0;
+    CKEY_TRY(table_fused_plan(ti, count, nullptr, &need, st));
+    bool query;
+    CKEY_TRY(ws_check(ws, ws_bytes, need, query));
+    if (query) return CKEY_OK;
+    // Switched off: the persistent kernel's first run on the GPU ended in a
+    // memory fault whose cause is not found (a host emulation of the same
+    // kernel source shows no out-of-bounds access and the oracle's results).
+    // Queries and argument checks stay; the launch is refused.
+    if (!kFusedTableEnabled) return CKEY_ERR_UNSUPPORTED;
+    return table_fused_plan(ti, count, ws, &need, st);
+}
+
 // Streams and events for fanning a table's indexes out from the caller's
 // stream (created once, default priority, kept for the process lifetime).
 constexpr int kForkStreams = 8;
@@ -429,6 +467,8 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
                                const ckey_sort_opts *opts, void *ws, size_t *ws_bytes,
                                void *stream) {
     if (!ws_bytes) return CKEY_ERR_INVALID;
+    if (opts && opts->fused_table)
+        return fused_rebuild(idx, count, opts, ws != nullptr, ws, ws_bytes, as_stream(stream));
     RebuildPlan plan;
     CKEY_TRY(plan_rebuild(idx, count, opts, ws != nullptr, plan));
     bool query;
@@ -445,13 +485,20 @@ struct ckey_graph {
 ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,
                               void *ws, size_t ws_bytes, ckey_graph **out) {
     if (!out || !ws) return CKEY_ERR_INVALID;
+    const bool fused = opts && opts->fused_table;
     RebuildPlan plan;
-    CKEY_TRY(plan_rebuild(idx, count, opts, true, plan));
-    for (uint32_t x = 0; x < count; ++x) {
-        const ckey_sort_opts *o = idx[x].opts ? idx[x].opts : opts;
-        if (method_of(o) != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+    if (fused) {
+        size_t need = 0;
+        CKEY_TRY(fused_rebuild(idx, count, opts, true, nullptr, &need, nullptr));
+        if (ws_bytes < need) return CKEY_ERR_WORKSPACE;
+    } else {
+        CKEY_TRY(plan_rebuild(idx, count, opts, true, plan));
+        for (uint32_t x = 0; x < count; ++x) {
+            const ckey_sort_opts *o = idx[x].opts ? idx[x].opts : opts;
+            if (method_of(o) != CKEY_SORT_RADIX) return CKEY_ERR_UNSUPPORTED;
+        }
+        if (ws_bytes < plan.total) return CKEY_ERR_WORKSPACE;
     }
-    if (ws_bytes < plan.total) return CKEY_ERR_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(ws) % 256) return CKEY_ERR_INVALID;
     hipStream_t cs = nullptr;
     CKEY_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -461,7 +508,8 @@ ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const 
         (void)hipStreamDestroy(cs);
         return CKEY_ERR_HIP;
     }
-    st = enqueue_rebuild(idx, count, opts, plan, ws, cs);
+    size_t wsb = ws_bytes;
+    st = fused ? fused_rebuild(idx, count, opts, true, ws, &wsb, cs) : enqueue_rebuild(idx, count, opts, plan, ws, cs);
     const hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     if (st != CKEY_OK || e != hipSuccess) {
@@ -507,11 +555,12 @@ ckey_status ckey_tune_index(const ckey_index_desc *idx, const ckey_sort_opts *ca
     for (uint32_t c = 0; c < ncand && status == CKEY_OK; ++c) {
         ckey_index_desc d = *idx;
         d.opts = &cand[c];
+        const ckey_sort_opts *call = cand[c].fused_table ? &cand[c] : nullptr;  // one-launch form
         size_t need = ws_bytes;
-        status = ckey_rebuild_index(&d, 1, nullptr, ws, &need, stream);  // warm-up
+        status = ckey_rebuild_index(&d, 1, call, ws, &need, stream);  // warm-up
         if (status != CKEY_OK) break;
         if (hipEventRecord(e0, st) != hipSuccess) { status = CKEY_ERR_HIP; break; }
-        status = ckey_rebuild_index(&d, 1, nullptr, ws, &need, stream);
+        status = ckey_rebuild_index(&d, 1, call, ws, &need, stream);
         if (status != CKEY_OK) break;
         float ms = 0;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

@@ -180,6 +180,22 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
 // OR a value into a device flags word (a kernel, so it is stream-ordered).
 ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st);
 
+// One index of a table rebuilt by the persistent launch (k_table.hip).
+struct TableIndex {
+    KeySrc keys;
+    const uint8_t *bitmap;  // host, keys.L bytes: the bitmap to compress with
+    uint32_t digit_bits;
+    uint32_t *perm;         // device [n] out
+    uint64_t *ckeys_out;    // device [words*n] out or nullptr
+    uint32_t *pair_pos;     // device [n-1] out or nullptr
+    uint8_t *bitmap_out;    // device [L] out or nullptr
+    uint32_t *flags;        // device or nullptr
+};
+// ws == nullptr: *need = workspace bytes (host only).  Else enqueue one fill
+// kernel and the persistent launch on st.
+ckey_status table_fused_plan(const TableIndex *ti, uint32_t count, void *ws, size_t *need,
+                             hipStream_t st);
+
 // Learned bucketing (k_learned.hip).  mode 1 = learned (MLP + correction),
 // mode 0 = splitter search.
 bool learned_b_ok(uint32_t b_log2);

@@ -126,6 +126,48 @@ def test_workspace_queries(ck):
                                   ctypes.byref(small), None) == ck.CKEY_ERR_WORKSPACE
 
 
+def test_fused_table_queries_and_limits(ck):
+    """The one-launch table rebuild: workspace query on the host, and its
+    documented limits (indexes, key bytes, passes, method) refused up front."""
+    lib = ck.lib()
+    n = 1 << 20
+    fused = ck.ckey_sort_opts(0, 8, 0, 0, None, None, 1)
+    need = ctypes.c_size_t(0)
+
+    def query(descs, opts=fused):
+        arr = (ck.ckey_index_desc * len(descs))(*descs)
+        need.value = 0
+        return lib.ckey_rebuild_index(arr, len(descs), ctypes.byref(opts), None, ctypes.byref(need), None)
+
+    def desc(L, rows=n, bitmap=None, opts=None):
+        ks = ck.ckey_keys(1, None, rows, L, L)  # pointers never dereferenced by a query
+        return ck.ckey_index_desc(ks, bitmap, 1, 1, None, None, None, opts)
+
+    assert query([desc(16)]) == ck.CKEY_OK
+    # first build of 16-byte keys: two 2-word ping-pong copies + row ids + two look-back arrays
+    tiles = -(-n // 4096)
+    assert need.value >= n * (2 * 16 + 4) + 2 * tiles * 1024
+    one = need.value
+    assert query([desc(16)] * 8) == ck.CKEY_OK and need.value >= 8 * (one - 4096)
+    assert query([desc(16)] * 9) == ck.CKEY_ERR_UNSUPPORTED
+    assert query([desc(65)]) == ck.CKEY_ERR_UNSUPPORTED
+    assert query([desc(64)]) == ck.CKEY_OK  # 512 bits, 64 passes of 8 bits
+    d1 = ck.ckey_sort_opts(0, 1, 0, 0, None, None, 0)
+    assert query([desc(16, opts=ctypes.pointer(d1))]) == ck.CKEY_ERR_UNSUPPORTED  # 128 passes
+    bm = np.zeros(16, np.uint8)
+    bm[3] = 0x0F  # |D| = 4: four 1-bit passes
+    assert query([desc(16, bitmap=bm.ctypes.data, opts=ctypes.pointer(d1))]) == ck.CKEY_OK
+    lrn = ck.ckey_sort_opts(2, 0, 8, 0, 1, None, 0)
+    assert query([desc(16, opts=ctypes.pointer(lrn))]) == ck.CKEY_ERR_UNSUPPORTED
+    assert query([desc(16, rows=1 << 30)]) == ck.CKEY_ERR_UNSUPPORTED
+    # the forked form's layout differs; graph creation checks the fused size
+    assert query([desc(16)], ck.ckey_sort_opts(0, 8, 0, 0, None, None, 0)) == ck.CKEY_OK
+    g = ctypes.c_void_p()
+    arr = (ck.ckey_index_desc * 1)(desc(16))
+    assert lib.ckey_graph_create(arr, 1, ctypes.byref(fused), ctypes.c_void_p(256), one - 1,
+                                 ctypes.byref(g)) == ck.CKEY_ERR_WORKSPACE
+
+
 def test_maintenance_argument_errors_and_queries(ck):
     lib = ck.lib()
     need = ctypes.c_size_t(0)
