@@ -232,9 +232,15 @@ ckey_status enqueue_rebuild(const ckey_index_desc *idx, uint32_t count, const ck
     CKEY_HIP_TRY(hipEventRecord(g_fork_ev[kForkStreams], st));
     const int ns = int(count < uint32_t(kForkStreams) ? count : kForkStreams);
     for (int i = 0; i < ns; ++i) CKEY_HIP_TRY(hipStreamWaitEvent(g_fork[i], g_fork_ev[kForkStreams], 0));
-    for (uint32_t x = 0; x < count; ++x)
-        CKEY_TRY(enqueue_one(idx[x], idx[x].opts ? idx[x].opts : opts, plan.ix[x], w8,
-                             g_fork[x % kForkStreams]));
+    // Radix indexes first: they enqueue without waiting, so they run while a
+    // bucketing index's host synchronization (its overflow count) holds the
+    // enqueue loop.
+    for (int pass = 0; pass < 2; ++pass)
+        for (uint32_t x = 0; x < count; ++x) {
+            const ckey_sort_opts *o = idx[x].opts ? idx[x].opts : opts;
+            if ((method_of(o) == CKEY_SORT_RADIX) != (pass == 0)) continue;
+            CKEY_TRY(enqueue_one(idx[x], o, plan.ix[x], w8, g_fork[x % kForkStreams]));
+        }
     for (int i = 0; i < ns; ++i) {
         CKEY_HIP_TRY(hipEventRecord(g_fork_ev[i], g_fork[i]));
         CKEY_HIP_TRY(hipStreamWaitEvent(st, g_fork_ev[i], 0));
