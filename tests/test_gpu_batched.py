@@ -67,6 +67,27 @@ def test_table_rebuild_per_index_options(ck, table):
     check(ck, tab, refs, ck.ckey_rebuild_index(specs))
 
 
+def test_table_rebuild_mixed_methods(ck, table):
+    """Radix and bucketing indexes in one call (the bucketing ones enqueue
+    after the radix ones and wait on their overflow counts): every index still
+    gets the oracle's permutation and D-bitmap."""
+    import torch
+    tab, refs = table
+    specs = specs_for(ck, tab, refs, first_build_every=1 << 30)  # refreshes but index 0
+    models = []
+    for x, (name, rows) in enumerate(tab.items()):
+        if x % 3 == 2:
+            continue  # stays radix
+        prev = ck.ckey_rebuild_index([dict(specs[x], want_ckeys=True)])[0]
+        model = ck.CdfModel(bucket_log2=8, seed=3)
+        ck.ckey_cdf_fit(model, prev["ckeys"][0].contiguous(), steps=50, batch=1 << 12)
+        models.append(model)
+        specs[x]["opts"] = dict(method=ck.CKEY_SORT_SPLITTER if x % 3 == 0 else ck.CKEY_SORT_LEARNED,
+                                model=model)
+    check(ck, tab, refs, ck.ckey_rebuild_index(specs))
+    torch.cuda.synchronize()
+
+
 def test_graph_replays(ck, table):
     import torch
     tab, refs = table
