@@ -95,6 +95,20 @@ def traffic_for(kernel, wl, src_file):
     return rec.get("bytes_per_launch")
 
 
+# The paper's own timings (Sec. 6, the INDBTAB sorting and index-building
+# table), quoted for context only: another machine, another dataset (16,392k
+# SAP HANA sales-document keys of 35 bytes, 16-byte compressed sort keys).
+PAPER_CONTEXT = {
+    "hardware": "Intel Xeon E7-8880 v4, 2.2 GHz; 1 core, and 16 cores of one socket",
+    "workload": "INDBTAB, 16,392k keys",
+    "one_core_s": {"extract": 0.543, "compressed_sort": 2.063, "full_key_sort": 4.251},
+    "one_core_compress_sort_keys_per_s": 16_392_000 / (0.543 + 2.063),
+    "sixteen_cores_s": {"extract": 0.034, "compressed_sort": 0.148, "full_key_sort": 0.310},
+    "sixteen_cores_compress_sort_keys_per_s": 16_392_000 / (0.034 + 0.148),
+    "use": "context only; not the target",
+}
+
+
 def cpu_baseline(rows_all, n_sample):
     """The CPU oracle, as it stands, on the first n_sample rows: compress with the
     sample's D-bitmap, then sort the compressed keys (single thread)."""
@@ -659,6 +673,7 @@ def main():
             "what": "ckey_compress with an all-ones bitmap + ckey_sort over all 8L bits",
             "skip_trivial_ms_per_step": None if full_skip is None else full_skip * 1e3,
             "speedup_of_compressed_vs_skip": None if full_skip is None else full_skip * 1e3 / ms},
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_maintenance and full is not None:
         del ck, ws
