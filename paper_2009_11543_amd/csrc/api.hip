@@ -235,17 +235,20 @@ ckey_status enqueue_rebuild(const ckey_index_desc *idx, uint32_t count, const ck
     // Radix indexes first: they enqueue without waiting, so they run while a
     // bucketing index's host synchronization (its overflow count) holds the
     // enqueue loop.
-    for (int pass = 0; pass < 2; ++pass)
-        for (uint32_t x = 0; x < count; ++x) {
+    ckey_status status = CKEY_OK;
+    for (int pass = 0; pass < 2 && status == CKEY_OK; ++pass)
+        for (uint32_t x = 0; x < count && status == CKEY_OK; ++x) {
             const ckey_sort_opts *o = idx[x].opts ? idx[x].opts : opts;
             if ((method_of(o) == CKEY_SORT_RADIX) != (pass == 0)) continue;
-            CKEY_TRY(enqueue_one(idx[x], o, plan.ix[x], w8, g_fork[x % kForkStreams]));
+            status = enqueue_one(idx[x], o, plan.ix[x], w8, g_fork[x % kForkStreams]);
         }
+    // Joined back even after an error, so the caller's stream still orders
+    // after whatever was enqueued on the forks.
     for (int i = 0; i < ns; ++i) {
         CKEY_HIP_TRY(hipEventRecord(g_fork_ev[i], g_fork[i]));
         CKEY_HIP_TRY(hipStreamWaitEvent(st, g_fork_ev[i], 0));
     }
-    return CKEY_OK;
+    return status;
 }
 
 }  // namespace
