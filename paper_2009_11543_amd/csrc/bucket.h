@@ -3,7 +3,9 @@
 // stand-alone assignment kernel and by compression fused with assignment.
 //   splitter: binary search of a 1-in-S sample of T held in LDS, then of T;
 //   learned:  a 4 -> 64 -> 1 ReLU MLP guesses b, then an exponential-then-
-//             binary search of T from the guess finds it exactly.
+//             binary search of T from the guess finds it exactly (fused with
+//             compression: a fixed-depth search of the buckets around the
+//             guess, or of all of T when x lies outside them).
 // Up to 2^14 buckets (S == 1) all of T is held in LDS for both methods.
 #pragma once
 
@@ -136,6 +138,27 @@ __device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ 
         if (T[mid] <= x) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// Exact bucket from a guess g without per-lane loops of varying length (so a
+// wave never waits on its slowest lane): the 2W buckets around g are searched
+// to a fixed depth when they hold x (checked with one read at each end), else
+// all B are (B a power of two, T sorted, T[0] = 0).  Returns the largest b
+// with T[b] <= x, as correct_bucket does.
+template <uint32_t W>
+__device__ __forceinline__ uint32_t correct_bucket_window(const uint64_t *__restrict__ T, uint32_t B, uint64_t x,
+                                                          uint32_t g) {
+    uint32_t lo = 0, span = B;
+    if (B > 2 * W) {
+        lo = g > W ? g - W : 0;
+        if (lo + 2 * W > B) lo = B - 2 * W;
+        if (T[lo] <= x && (lo + 2 * W == B || T[lo + 2 * W] > x)) span = 2 * W;
+        else lo = 0;
+    }
+    uint32_t b = lo;  // T[b] <= x throughout
+    for (uint32_t step = span >> 1; step >= 1; step >>= 1)
+        if (b + step < B && T[b + step] <= x) b += step;
+    return b;
 }
 
 template <int AMODE>

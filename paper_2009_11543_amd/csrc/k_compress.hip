@@ -337,8 +337,9 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
 #pragma unroll
                 for (int q = 0; q < KPI; ++q) {
                     const uint64_t r = base + uint64_t(q) * kBucketWG;
-                    uint32_t probes = 0;
-                    const uint32_t b = correct_bucket(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q], probes);
+                    // 2 x 512 buckets around the guess (the trained network's
+                    // rank error is a few hundred buckets at 2^14)
+                    const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q]);
                     if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
                 }
             } else {
