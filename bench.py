@@ -630,7 +630,9 @@ def main():
     # compress_bucket writes words + bucket id (the first bucket pass generates
     # the record IDs); the two bucket passes move rec + 2 bytes in and out,
     # less the record IDs pass 1 does not read, plus pass 1's bucket-id copy.
-    per_key = {"compress": key_bytes_read + rec, "compress_bucket": key_bytes_read + 8 * w + 2,
+    # (the bucketing methods' compression writes no record IDs)
+    per_key = {"compress": key_bytes_read + (rec if best == "radix" else 8 * w),
+               "compress_bucket": key_bytes_read + 8 * w + 2,
                "hist": 8 * w, "onesweep": 2 * rec,
                "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "tile_counts": 2,
                "bucket_pass": 2 * rec + 1,

@@ -203,9 +203,11 @@ size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_
 ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
                          int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
                          hipStream_t st);
-// Compression and bucketing sort in one pass over the keys: the bucket of
-// each key is found while it is compressed.  CKEY_ERR_UNSUPPORTED when the
-// keys do not allow the fused kernel (then compress and sort separately).
+// Compression and bucketing sort with the record IDs generated by the first
+// grouping pass.  Learned (mode 1): the bucket of each key is found while it
+// is compressed; CKEY_ERR_UNSUPPORTED when the keys do not allow that fused
+// kernel (then compress and sort separately).  Splitter (mode 0): a plain
+// compression, then the assignment over the first words.
 ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ck,
                                   uint32_t words, uint32_t nbits, uint32_t *rid, int mode,
                                   const void *model, uint32_t b_log2, uint32_t *flags, void *ws,

@@ -202,8 +202,28 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
     const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
     uint32_t probes = 0, err = 0;
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
-        (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
+    if (MODE == 0 && ba.S == 1 && !stats) {
+        // Splitter with every threshold in LDS: eight keys per thread, all
+        // their loads first, then their searches interleaved.
+        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 8 * kBucketWG) {
+            uint64_t x[8];
+            uint32_t b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                x[q] = r < i1 ? w0[r] : 0ull;
+            }
+            splitter_search_n<8>(ba, s_dyn, x, b);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
+            }
+        }
+    } else {
+        for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
+            (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
+    }
     __syncthreads();
     bucket_lds_flush<MODE>(ba, s_dyn);
     if (stats) {
@@ -1114,8 +1134,17 @@ ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *
     CKEY_TRY(fill_u32(q.hist, B, 0, st));
     CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
     // The row ids start as 0..n-1: the first grouping pass generates them.
-    CKEY_TRY(compress_bucket_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, mode,
-                                    bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), st));
+    const BucketArgs ba = bucket_args(model, B, q.bid, nullptr, nullptr, q.hist);
+    if (mode == 0) {
+        // Splitter: compression streams at copy speed in small workgroups;
+        // the search then reads the first words again (8 bytes a key) in
+        // workgroups that hold all thresholds in LDS.  Together faster than
+        // one kernel doing both at one 160 KB-LDS workgroup per CU.
+        CKEY_TRY(compress_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, st));
+        if (n >= 2) CKEY_TRY(assign_launch(mode, ck, n, ba, nullptr, st));
+    } else {
+        CKEY_TRY(compress_bucket_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, mode, ba, st));
+    }
     if (n < 2) return CKEY_OK;
     return bucket_finish(ck, words, nbits, rid, true, n, model, b_log2, q, l, flags, ws, st);
 }
