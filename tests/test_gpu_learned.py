@@ -427,3 +427,29 @@ def test_fused_compress_sort_wide_keys(ck):
                                      model=model)
     np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
     np.testing.assert_array_equal(ck.as_u64(ckd), O.compress(k, bm)[:, perm])
+
+
+@pytest.mark.parametrize("trained", [True, False])
+def test_fused_learned_window_search(ck, trained):
+    """The learned method's fused kernel (64-byte keys, 2^12 buckets: a
+    fixed-depth search of the 1024 buckets around each guess, or of all of T
+    for keys outside them).  A trained network puts most keys inside the
+    window; an untrained one (same thresholds) sends most through the full
+    search.  Either way the permutation and the compressed keys are the
+    oracle's."""
+    n = (1 << 20) + 333
+    rows = datagen.dna_window_keys(n, seed=23, seq_len=1 << 21)
+    k = O.Keys(rows)
+    perm = O.full_sort(k)
+    d, _ = O.dbits(k, perm)
+    cko = O.compress(k, d)
+    model = ck.CdfModel(bucket_log2=12, seed=2)
+    ck.ckey_cdf_fit(model, to_dev(np.ascontiguousarray(cko[0, perm])), steps=300 if trained else 0, batch=1 << 14)
+    if not trained:
+        fresh = ck.CdfModel(bucket_log2=12, seed=9)
+        fresh.thresholds().copy_(model.thresholds())
+        model = fresh
+    print(f"fused learned window search, trained={trained}, n={n}", flush=True)
+    ckd, rid = ck.ckey_compress_sort(ck.DeviceKeys.from_numpy(rows), d, method=ck.CKEY_SORT_LEARNED, model=model)
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    np.testing.assert_array_equal(ck.as_u64(ckd), cko[:, perm])
