@@ -220,7 +220,26 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
                 if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
             }
         }
-    } else {
+    } else if (MODE == 1 && ba.S == 1 && !stats) {
+        // Learned with every threshold in LDS: four keys' networks at once,
+        // then the fixed-depth search around each guess.
+        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
+            uint64_t x[4];
+            uint32_t g[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                x[q] = r < i1 ? w0[r] : 0ull;
+            }
+            predict_bucket_n<4>(ba.p, x, ba.B, g);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, x[q], g[q]);
+                if (r < i1) bucket_record<MODE>(ba, s_dyn, b, r);
+            }
+        }
+    } else {  // with statistics (probes, guess error) or a sampled threshold table
         for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
             (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
     }
