@@ -246,6 +246,30 @@ __device__ __forceinline__ void splitter_search_n(const BucketArgs &a, const uin
     for (int q = 0; q < N; ++q) b[q] -= a.B;
 }
 
+// The same for a 1-in-S sample of T in LDS (S > 1, sorted order): a
+// fixed-depth search of the sample, then of the S thresholds of T (global
+// memory) below the next sample, the keys' steps interleaved.
+template <int N>
+__device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, const uint32_t *s,
+                                                          const uint64_t *x, uint32_t *b) {
+    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s);
+    const uint32_t m = a.B / a.S;  // sample size; ts[0] = T[0] = 0
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] = 0;
+    for (uint32_t step = m >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (ts[b[q] + step] <= x[q]) b[q] += step;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] *= a.S;
+    for (uint32_t step = a.S >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            if (a.T[b[q] + step] <= x[q]) b[q] += step;  // b[q] + step < B
+    }
+}
+
 template <int AMODE>
 __device__ __forceinline__ void bucket_record(const BucketArgs &a, uint32_t *s, uint32_t b, uint64_t i) {
     if (a.bid) a.bid[i] = uint16_t(b);

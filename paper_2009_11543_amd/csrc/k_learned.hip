@@ -202,9 +202,9 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
     const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
     uint32_t probes = 0, err = 0;
-    if (MODE == 0 && ba.S == 1 && !stats) {
-        // Splitter with every threshold in LDS: eight keys per thread, all
-        // their loads first, then their searches interleaved.
+    if (MODE == 0 && !stats) {
+        // Splitter: eight keys per thread, all their loads first, then their
+        // searches interleaved (every threshold in LDS, or a sample of them).
         for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 8 * kBucketWG) {
             uint64_t x[8];
             uint32_t b[8];
@@ -213,7 +213,10 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
                 const uint64_t r = b0 + uint64_t(q) * kBucketWG;
                 x[q] = r < i1 ? w0[r] : 0ull;
             }
-            splitter_search_n<8>(ba, s_dyn, x, b);
+            if (ba.S == 1)
+                splitter_search_n<8>(ba, s_dyn, x, b);
+            else
+                splitter_search_sampled_n<8>(ba, s_dyn, x, b);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint64_t r = b0 + uint64_t(q) * kBucketWG;
