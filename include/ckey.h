@@ -148,8 +148,9 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
  * and rowids (device uint32[n]) receive the sorted compressed keys and the row
  * ids in full-key order.  Arguments as for ckey_compress and ckey_sort.  With
  * a bucketing method the record IDs are generated by the first grouping pass
- * instead of being written and read back; with the learned method and
- * fixed-width keys each key's bucket is found while the key is compressed.
+ * instead of being written and read back; with fixed-width keys each key's
+ * bucket is found while the key is compressed for the learned method, and for
+ * the splitter beyond 2^14 buckets.
  * Needs a workspace (the size ckey_sort needs). */
 ckey_status ckey_compress_sort(const ckey_keys *keys, const uint8_t *bitmap, uint64_t *ckeys,
                                uint32_t words, uint32_t *rowids, const ckey_sort_opts *opts,

@@ -307,9 +307,9 @@ __device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *
     }
 }
 
-// Compression fused with the learned bucket assignment (k_compress.hip,
-// amode 1).  Fixed-width keys whose compression fits one launch only (else,
-// and for any other amode, CKEY_ERR_UNSUPPORTED).
+// Compression fused with bucket assignment (k_compress.hip; amode 1 learned,
+// 0 splitter).  Fixed-width keys whose compression fits one launch only (else
+// CKEY_ERR_UNSUPPORTED).
 ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ckeys,
                                    uint32_t words, uint32_t *rowids, uint32_t *flags, int amode,
                                    const BucketArgs &ba, hipStream_t st);

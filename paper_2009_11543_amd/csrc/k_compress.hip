@@ -283,13 +283,15 @@ struct RegLoader {
     }
 };
 
-// Compression fused with the learned bucket assignment: each workgroup
-// compresses a range of up to kBucketKeysPerWG keys (grid-stride over its
-// threads), finds each key's bucket from its first compressed word while it
-// is in registers (the network's guess, then the exact bucket), and keeps a
-// packed 16-bit bucket histogram in LDS.  (The splitter's search is cheap
-// enough that a separate assignment kernel over the first words, after a
-// plain compression, is faster than this one-workgroup-per-CU kernel.)
+// Compression fused with bucket assignment: each workgroup compresses a
+// range of up to kBucketKeysPerWG keys (grid-stride over its threads), finds
+// each key's bucket from its first compressed word while it is in registers
+// (learned: the network's guess, then the exact bucket; splitter: a search of
+// the threshold sample in LDS, then of T in memory), and keeps a packed 16-bit
+// bucket histogram in LDS.  (With every threshold in LDS the splitter's search
+// is cheap enough that a separate assignment kernel over the first words,
+// after a plain compression, is faster than this one-workgroup-per-CU kernel;
+// with a sample, the search's reads of T overlap the compression's loads here.)
 template <int MODE, int AMODE, int KPI>
 __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, CompressPlan plan,
                                                                uint64_t *__restrict__ ck,
@@ -337,6 +339,14 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
                     const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q]);
                     if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
                 }
+            } else if (AMODE == 0 && ba.S > 1) {  // the keys' sampled searches interleaved
+                uint32_t b[KPI];
+                splitter_search_sampled_n<KPI>(ba, s_dyn, w0, b);
+#pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < KPI; ++q) {
@@ -364,9 +374,7 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
 ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
                                    uint32_t *rowids, uint32_t *flags, int amode, const BucketArgs &ba,
                                    hipStream_t st) {
-    // Fused only for the learned method and fixed-width keys whose
-    // compression fits one launch.
-    if (amode != 1) return CKEY_ERR_UNSUPPORTED;
+    // Fused only for fixed-width keys whose compression fits one launch.
     const int mode = load_mode(k);
     std::vector<SrcWord> src;
     uint32_t nbits = 0, nch = 0, lc = UINT32_MAX;
@@ -406,14 +414,22 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
     const size_t lds = bucket_lds_bytes(ba, amode);
     constexpr int kKPI = 4;  // keys per thread per iteration
     const bool multi = mode == kLoad16 && cidx <= 4;
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
     raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, kKPI>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, 1>));
     raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 1, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 0, 1>));
     raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad4, 1, 1>));
+    raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 0, 1>));
     raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoadBytes, 1, 1>));
     const int pr_ = prof_begin(st, "compress_bucket");
 #define CKEY_LAUNCH_CB(M, KPI)                                                                         \
-    hipLaunchKernelGGL((k_compress_bucket<M, 1, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k, plan, \
-                       ck, rowids, ba);
+    if (amode)                                                                                         \
+        hipLaunchKernelGGL((k_compress_bucket<M, 1, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
+                           plan, ck, rowids, ba);                                                      \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_compress_bucket<M, 0, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
+                           plan, ck, rowids, ba);
     switch (mode) {
         case kLoad16:
             if (multi) {

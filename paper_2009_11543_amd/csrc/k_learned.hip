@@ -1157,15 +1157,20 @@ ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *
     CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
     // The row ids start as 0..n-1: the first grouping pass generates them.
     const BucketArgs ba = bucket_args(model, B, q.bid, nullptr, nullptr, q.hist);
-    if (mode == 0) {
-        // Splitter: compression streams at copy speed in small workgroups;
-        // the search then reads the first words again (8 bytes a key) in
-        // workgroups that hold all thresholds in LDS.  Together faster than
-        // one kernel doing both at one 160 KB-LDS workgroup per CU.
+    // Splitter with every threshold in LDS: compression streams at copy speed
+    // in small workgroups; the search then reads the first words again (8
+    // bytes a key) in workgroups that hold all thresholds.  Together faster
+    // than one kernel doing both at one 160 KB-LDS workgroup per CU.  With
+    // only a sample in LDS (more than 2^14 buckets) the search reads T in
+    // memory, and doing it while the keys are compressed hides those reads.
+    ckey_status s = CKEY_ERR_UNSUPPORTED;
+    if (mode == 1 || ba.S > 1)
+        s = compress_bucket_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, mode, ba, st);
+    if (mode == 0 && s == CKEY_ERR_UNSUPPORTED) {
         CKEY_TRY(compress_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, st));
         if (n >= 2) CKEY_TRY(assign_launch(mode, ck, n, ba, nullptr, st));
     } else {
-        CKEY_TRY(compress_bucket_launch(k, bm, ck, words, n < 2 ? rid : nullptr, flags, mode, ba, st));
+        CKEY_TRY(s);
     }
     if (n < 2) return CKEY_OK;
     return bucket_finish(ck, words, nbits, rid, true, n, model, b_log2, q, l, flags, ws, st);
