@@ -126,3 +126,15 @@ def test_table_emulated_edges(emu, tmp_path):
         (O.Keys(rng.integers(0, 8, (1500, 12), dtype=np.uint8), L=10), None, 8),
     ]
     run_table(emu, tmp_path, cases, 2)
+
+
+def test_table_emulated_gpu_test_table(emu, tmp_path):
+    """The table of the skipped GPU test (8 indexes of 2^15 + 777 rows, every
+    other one a refresh, 8-bit digits), six workgroups at once."""
+    n = (1 << 15) + 777
+    tab = datagen.table_indexes(n, seed=5)
+    cases = []
+    for x, (name, rows) in enumerate(tab.items()):
+        k = O.Keys(rows)
+        cases.append((k, None if x % 2 == 0 else O.dbits(k, O.full_sort(k))[0], 8))
+    run_table(emu, tmp_path, cases, 6)
