@@ -328,10 +328,17 @@ ckey_status ckey_bulk_load(const ckey_tree_input *in, uint32_t pk_bits, float fi
  * Model memory is device memory owned by the caller, ckey_cdf_model_bytes()
  * long, 256-byte aligned: a 4 -> 64 -> 1 ReLU MLP (385 fp32 parameters, plus
  * Adam moments) and a table T of 2^bucket_log2 sorted 64-bit thresholds.
+ * Layout: the parameters as float[385] at byte 0 (ckey_cdf_grad's order),
+ * Adam's first and second moments as float[385] at bytes 2048 and 4096, T as
+ * uint64[2^bucket_log2] at byte 8192; a caller may write the parameters
+ * (zeroing the moments) in place of ckey_cdf_model_init.
  * bucket(x) = the b with T[b] <= x < T[b+1] for the key's first compressed
  * word x; it is non-decreasing in key order.  The network predicts b from x's
- * four 16-bit chunks (each / 65536); an exponential-then-binary search from
- * the prediction makes it exact, so results never depend on the network. */
+ * four 16-bit chunks (each / 65536); a search of T from the prediction makes
+ * it exact, so results never depend on the network: the sort searches the
+ * 2^10 buckets around the guess at a fixed depth (all of T when the key lies
+ * outside them), ckey_cdf_bucket with statistics searches exponentially
+ * outward from the guess, then by bisection. */
 size_t ckey_cdf_model_bytes(uint32_t bucket_log2);
 
 /* Initialise the parameters deterministically from `seed`, zero the moments. */

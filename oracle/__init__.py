@@ -53,6 +53,7 @@ def _load():
         D = ctypes.c_double
         lib.oracle_adam.argtypes = [P, P, P, P, U32, D, D, D, D, U32]
         lib.oracle_bucket.argtypes = [P, U64, P, U32, P]
+        lib.oracle_thresholds.argtypes = [P, U64, U32, P]
         _lib = lib
     return _lib
 
@@ -277,3 +278,13 @@ def bucket(prefix, T):
     out = np.zeros(len(x), np.uint32)
     _load().oracle_bucket(_ptr(x), len(x), _ptr(T), len(T), _ptr(out))
     return out
+
+
+def thresholds(sorted_prefix, B):
+    """uint64[B]: T[0] = 0, T[b] = sorted_prefix[b*m // B] (m = len(sorted_prefix))."""
+    x = np.ascontiguousarray(sorted_prefix, np.uint64)
+    if len(x) == 0:
+        raise ValueError("thresholds need a non-empty training set")
+    T = np.zeros(B, np.uint64)
+    _load().oracle_thresholds(_ptr(x), len(x), B, _ptr(T))
+    return T

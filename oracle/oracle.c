@@ -573,6 +573,21 @@ void oracle_adam(double *p, const double *g, double *m, double *v, uint32_t n, d
     }
 }
 
+/* Threshold table of the learned bucketing (the extension's definition of a
+ * bucket): B thresholds cut a sorted training set of m first compressed words
+ * into B rank ranges of (nearly) equal size.  T[0] = 0 so every 64-bit value
+ * has a bucket; for b >= 1, T[b] = sorted[floor(b*m/B)], the word of rank
+ * floor(b*m/B).  T is non-decreasing because sorted is. */
+void oracle_thresholds(const uint64_t *sorted, uint64_t m, uint32_t B, uint64_t *T)
+{
+    for (uint32_t b = 0; b < B; ++b) {
+        if (b == 0) { T[b] = 0; continue; }
+        /* b*m < 2^16 * 2^32 here, so the product cannot overflow */
+        uint64_t rank = ((uint64_t)b * m) / B;
+        T[b] = sorted[rank];
+    }
+}
+
 /* bucket[i] = the b with T[b] <= x[i] < T[b+1] (T[B] taken as +infinity),
  * for a non-decreasing threshold table T of B entries with T[0] = 0. */
 void oracle_bucket(const uint64_t *x, uint64_t n, const uint64_t *T, uint32_t B, uint32_t *bucket)

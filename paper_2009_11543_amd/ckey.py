@@ -485,7 +485,7 @@ def as_u64(t):
 # ----------------------------------------------------- learned bucketing --
 
 MODEL_PARAMS = 385
-_OFF_T = 8192
+_OFF_M, _OFF_V, _OFF_T = 2048, 4096, 8192  # byte offsets of the model memory's parts
 
 
 class CdfModel:
@@ -506,6 +506,14 @@ class CdfModel:
 
     def params(self):
         return self.mem[: 4 * MODEL_PARAMS].view(torch.float32)
+
+    def set_params(self, p):
+        """Write 385 host parameters (ckey_cdf_grad's order) and zero both Adam moments."""
+        t = torch.as_tensor(np.ascontiguousarray(p, np.float32))
+        if t.numel() != MODEL_PARAMS:
+            raise ValueError(f"expected {MODEL_PARAMS} parameters, got {t.numel()}")
+        self.params().copy_(t.to(self.mem.device))
+        self.mem[_OFF_M:_OFF_T].zero_()
 
     def thresholds(self):
         return self.mem[_OFF_T:].view(torch.int64)

@@ -61,32 +61,83 @@ def test_grad_matches_oracle(ck):
     assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-4)
 
 
+def host_params(seed):
+    """A starting point for training made on the host (seeded), in the shape the
+    library's own initialisation uses: unit k watches the top 16-bit chunk with
+    its kink at k/64, the output starts near the first unit's identity."""
+    rng = np.random.default_rng(seed)
+    H = O.MLP_H
+    p = np.zeros(O.MLP_P)
+    p[:4 * H] = 1e-3 * rng.standard_normal(4 * H)
+    p[0:4 * H:4] += 1.0
+    p[4 * H:5 * H] = -np.arange(H) / H
+    p[5 * H:6 * H] = 1e-3 * rng.standard_normal(H)
+    p[5 * H] += 1.0
+    return p.astype(np.float32).astype(np.float64)
+
+
+def oracle_training(srt, p0, steps, batch, seed, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """`steps` oracle Adam steps on the batches ckey_cdf_fit documents (sample j
+    of step s is row SplitMix64(seed + phi*((s << 32) + j + 1)) mod m, target
+    (row + 0.5)/m); returns the parameters after every step and each loss."""
+    m = len(srt)
+    p, mm, vv = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
+    after, losses = [], []
+    for s in range(1, steps + 1):
+        idx = np.array([splitmix_index(seed, s, j, m) for j in range(batch)])
+        X = O.mlp_features(srt[idx])
+        tgt = (idx.astype(np.float64) + 0.5) / m
+        loss, g = O.mlp_loss_grad(p, X, tgt)
+        O.adam(p, g, mm, vv, s, lr, b1, b2, eps)
+        after.append(p.copy())
+        losses.append(loss)
+    return after, losses
+
+
 def test_adam_step_matches_oracle(ck):
     """One training step: sampled batch (documented SplitMix64 rule), gradient,
-    Adam update -- all compared with the fp64 oracle."""
-    import torch
+    Adam update -- all compared with the fp64 oracle from the same host-made
+    starting parameters; the threshold table against the oracle's."""
     _, _, perm, _, cko = dna_prefixes(1 << 12, 3)
     srt = np.ascontiguousarray(cko[0, perm])
-    m = len(srt)
     model = ck.CdfModel(bucket_log2=8, seed=5)
-    p0 = model.params().double().cpu().numpy().copy()
+    p0 = host_params(5)
+    model.set_params(p0)
     batch, seed, lr = 2048, 11, 1e-2
     ck.ckey_cdf_fit(model, to_dev(srt), steps=1, batch=batch, lr=lr, seed=seed)
     p1 = model.params().double().cpu().numpy()
-    idx = np.array([splitmix_index(seed, 1, j, m) for j in range(batch)])
-    X = O.mlp_features(srt[idx])
-    tgt = (idx.astype(np.float64) + 0.5) / m
-    _, g = O.mlp_loss_grad(p0, X, tgt)
-    pr, mm, vv = p0.copy(), np.zeros_like(p0), np.zeros_like(p0)
-    O.adam(pr, g, mm, vv, 1, lr)
+    (pr,), _ = oracle_training(srt, p0, 1, batch, seed, lr)
+    # an fp32 gradient of 2048 terms moves a component by lr*sign(g) up to a
+    # relative error of ~1e-4, except where g is tiny and the sign is noise
+    idx = np.array([splitmix_index(seed, 1, j, len(srt)) for j in range(batch)])
+    _, g = O.mlp_loss_grad(p0, O.mlp_features(srt[idx]), (idx + 0.5) / len(srt))
     big = np.abs(g) > 1e-3 * np.abs(g).max()
     np.testing.assert_allclose((p1 - p0)[big], (pr - p0)[big], rtol=1e-3, atol=1e-6)
-    # thresholds: T[b] = sorted[b*m/B], T[0] = 0
     T = model.thresholds().cpu().numpy().view(np.uint64)
-    B = 1 << 8
-    ref = srt[(np.arange(B) * m) // B]
-    ref[0] = 0
-    np.testing.assert_array_equal(T, ref)
+    np.testing.assert_array_equal(T, O.thresholds(srt, 1 << 8))
+
+
+def test_training_ten_steps_matches_oracle(ck):
+    """Ten steps of ckey_cdf_fit against ten oracle steps on the same SplitMix64
+    batches from the same host-made parameters.  Bound: each fp32 step's update
+    lr*m_hat/sqrt(v_hat) carries the relative error of a 2048-term fp32 sum
+    (~1e-4 at most) and the error of earlier steps, so after s steps every
+    parameter agrees within 1e-3*lr*s (an fp32 emulation of the same ten steps
+    stays within 5e-5*lr); each step's loss within rtol 1e-4."""
+    _, _, perm, _, cko = dna_prefixes(1 << 12, 3)
+    srt = np.ascontiguousarray(cko[0, perm])
+    batch, seed, lr, steps = 2048, 11, 1e-2, 10
+    p0 = host_params(6)
+    after, losses = oracle_training(srt, p0, steps, batch, seed, lr)
+    for s in (1, 4, steps):
+        model = ck.CdfModel(bucket_log2=8, seed=0)
+        model.set_params(p0)
+        trace = ck.ckey_cdf_fit(model, to_dev(srt), steps=s, batch=batch, lr=lr, seed=seed)
+        got = model.params().double().cpu().numpy()
+        np.testing.assert_allclose(got, after[s - 1], rtol=0, atol=1e-3 * lr * s)
+        np.testing.assert_allclose(trace.double().cpu().numpy(), losses[:s], rtol=1e-4)
+    # the ten steps really move the parameters (by about lr each)
+    assert np.abs(after[-1] - p0).max() > 5 * lr
 
 
 @pytest.mark.parametrize("method", ["learned", "splitter"])

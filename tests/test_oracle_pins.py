@@ -392,3 +392,68 @@ def test_bucket_definition():
 def test_features():
     x = np.array([0x0001_8000_FFFF_0000], np.uint64)
     np.testing.assert_array_equal(O.mlp_features(x)[0], [1 / 65536, 0.5, 65535 / 65536, 0.0])
+
+
+@pytest.mark.parametrize("b1,b2", [(0.9, 0.999), (0.5, 0.7), (0.0, 0.99)])
+def test_adam_constant_gradient_every_step(b1, b2):
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step t (m_t = g(1-b1^t), v_t = g^2(1-b2^t)), so with eps = 0
+    each step moves every parameter by exactly lr * sign(g).  A correction
+    that used the wrong step count, or one beta for both moments, fails from
+    step 2 on."""
+    g = np.array([0.3, -4.0, 1e-3, -2.5e-6])
+    p = np.array([1.0, -2.0, 0.5, 0.0])
+    m, v = np.zeros(4), np.zeros(4)
+    lr = 0.01
+    for t in range(1, 61):
+        before = p.copy()
+        O.adam(p, g, m, v, t, lr, b1=b1, b2=b2, eps=0.0)
+        np.testing.assert_allclose(before - p, lr * np.sign(g), rtol=1e-12, atol=0)
+        np.testing.assert_allclose(m, g * (1 - b1 ** t), rtol=1e-12)
+        np.testing.assert_allclose(v, g * g * (1 - b2 ** t), rtol=1e-12)
+
+
+def test_adam_after_gradient_stops():
+    """t0 steps of a constant g, then k steps of g = 0: the moments decay as
+    m = g(1-b1^t0) b1^j, v = g^2(1-b2^t0) b2^j after j zero steps, so step
+    t0+j moves the parameter by lr * m_hat / sqrt(v_hat) with the corrections
+    of step t0+j -- summed here in closed form, not by the recurrence."""
+    b1, b2, lr, t0, k = 0.9, 0.999, 0.05, 7, 25
+    g = np.array([2.0, -0.75])
+    p = np.zeros(2)
+    m, v = np.zeros(2), np.zeros(2)
+    for t in range(1, t0 + k + 1):
+        O.adam(p, g if t <= t0 else np.zeros(2), m, v, t, lr, b1=b1, b2=b2, eps=0.0)
+    moved = t0 * lr * np.sign(g)
+    for j in range(1, k + 1):
+        t = t0 + j
+        mh = g * (1 - b1 ** t0) * b1 ** j / (1 - b1 ** t)
+        vh = g * g * (1 - b2 ** t0) * b2 ** j / (1 - b2 ** t)
+        moved = moved + lr * mh / np.sqrt(vh)
+    np.testing.assert_allclose(-p, moved, rtol=1e-12)
+
+
+def test_thresholds_hand_worked():
+    """T[0] = 0 and T[b] = sorted[floor(b*m/B)]: worked by hand for m = 10,
+    B = 4 (ranks 0, 2, 5, 7) and for more buckets than rows (m = 3, B = 8:
+    ranks 0, 0, 0, 1, 1, 1, 2, 2)."""
+    s = np.array([3, 5, 5, 8, 13, 21, 34, 55, 89, 144], np.uint64)
+    np.testing.assert_array_equal(O.thresholds(s, 4), [0, 5, 21, 55])
+    s3 = np.array([10, 20, 30], np.uint64)
+    np.testing.assert_array_equal(O.thresholds(s3, 8), [0, 10, 10, 20, 20, 20, 30, 30])
+
+
+@pytest.mark.parametrize("m,B", [(10007, 256), (4096, 4096), (65536, 1 << 14)])
+def test_thresholds_balance_training_set(m, B):
+    """With distinct training words and m >= B, bucket b of the thresholds
+    (the bucket definition, itself pinned by bisect) holds exactly
+    floor((b+1)m/B) - floor(bm/B) of the training rows: the table splits the
+    training set into equal rank ranges."""
+    rng = np.random.default_rng(m + B)
+    s = np.unique(rng.integers(1, 1 << 63, int(m * 1.01) + 64, dtype=np.uint64))[:m]
+    assert len(s) == m
+    T = O.thresholds(s, B)
+    assert T[0] == 0 and np.all(np.diff(T.astype(np.float64)) >= 0)
+    counts = np.bincount(O.bucket(s, T).astype(np.int64), minlength=B)
+    b = np.arange(B + 1, dtype=np.int64)
+    np.testing.assert_array_equal(counts, np.diff((b * m) // B))
