@@ -105,3 +105,44 @@ def test_compress_and_sort_full_size(setup, method):
     got = rid.cpu().numpy().view(np.uint32)
     np.testing.assert_array_equal(got, perm)
     assert int(flags.item()) & ck.CKEY_FLAG_SPIN_LIMIT == 0
+
+
+@pytest.fixture(scope="module")
+def headline_model(setup):
+    """The benchmark's model: thresholds and network from a rebuild of the same
+    generator at seed 2 (2^24 rows), 2^14 buckets."""
+    import torch
+    ck, rows, keys, d, perm = setup
+    train = datagen.dna_window_keys(1 << 24, seed=2)
+    kt = ck.DeviceKeys(torch.from_numpy(train).cuda())
+    ckt, ridt = ck.ckey_compress(kt, d)
+    ck.ckey_sort(ckt, ck.ckey_plan_query(d)["nbits"], ridt)
+    model = ck.CdfModel(bucket_log2=14, seed=3)
+    ck.ckey_cdf_fit(model, ckt[0].contiguous(), steps=1000, batch=1 << 16, seed=2)
+    del kt, ckt, ridt
+    torch.cuda.empty_cache()
+    return model
+
+
+@pytest.mark.parametrize("method", ["splitter", "learned"])
+def test_compress_sort_headline_call(setup, headline_model, method):
+    """The timed call of the benchmark itself: ckey_compress_sort over the 2^26
+    keys with a bucketing method at 2^14 buckets (compression without record
+    IDs, the bucket assignment, the record-ID-generating first grouping pass,
+    the in-LDS bucket sorts).  Its record IDs must be the property-checked
+    first build's permutation and its sorted words the oracle's compression
+    of the rows in that order, at sampled positions."""
+    import torch
+    ck, rows, keys, d, perm = setup
+    m = ck.CKEY_SORT_SPLITTER if method == "splitter" else ck.CKEY_SORT_LEARNED
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    print(f"compress_sort 2^26 DNA {method} 2^14 buckets", flush=True)
+    cks, rid = ck.ckey_compress_sort(keys, d, method=m, model=headline_model, flags=flags)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(rid.cpu().numpy().view(np.uint32), perm)
+    rng = np.random.default_rng(9)
+    pos = np.sort(rng.choice(N, 4096, replace=False))
+    ref = O.compress(O.Keys(np.ascontiguousarray(rows[perm[pos]])), d)
+    np.testing.assert_array_equal(ck.as_u64(cks[:, torch.from_numpy(pos).cuda()]), ref)
+    assert int(flags.item()) & ck.CKEY_FLAG_SPIN_LIMIT == 0
+
