@@ -143,6 +143,24 @@ ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t 
                       uint64_t n, const ckey_sort_opts *opts, void *workspace,
                       size_t *workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ckey_sort
+ * with the radix method, its scratch space taken from one static device array
+ * of CKEY_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of a caller workspace.  Arguments, results
+ * and flags as for ckey_sort.  The call allocates no memory (no hipMalloc, no
+ * host heap) and never synchronizes the stream; the scratch array's address
+ * is looked up once per device, on the first call with that device current.
+ * Returns CKEY_ERR_UNSUPPORTED for a bucketing method, skip_trivial, more
+ * than 512 radix passes, or a sort whose workspace (ckey_sort's query with
+ * the same arguments) exceeds CKEY_NOALLOC_SCRATCH_BYTES -- e.g. about
+ * 5.5 million rows of one-word keys, 2.3 million of three words.  All calls on
+ * one GPU share its array: calls that overlap on one GPU (different streams
+ * without ordering) race and give wrong results. */
+#define CKEY_NOALLOC_SCRATCH_BYTES (64u << 20)
+ckey_status ckey_sort_noalloc(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
+                              uint64_t n, const ckey_sort_opts *opts, void *stream);
+
 /* Compress and sort in one call (Sec. 5 steps 2-3: extract the compressed
  * keys, sort the (compressed key, row id) pairs): ckeys (device, words x n)
  * and rowids (device uint32[n]) receive the sorted compressed keys and the row

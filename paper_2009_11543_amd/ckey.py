@@ -79,6 +79,7 @@ def _load():
     lib.ckey_distinction_bits.argtypes = [ctypes.POINTER(ckey_keys), P, P, P, P, SZP, P]
     lib.ckey_compress.argtypes = [ctypes.POINTER(ckey_keys), P, P, U32, P, P, P]
     lib.ckey_sort.argtypes = [P, U32, U32, P, U64, ctypes.POINTER(ckey_sort_opts), P, SZP, P]
+    lib.ckey_sort_noalloc.argtypes = [P, U32, U32, P, U64, ctypes.POINTER(ckey_sort_opts), P]
     lib.ckey_rebuild_index.argtypes = [ctypes.POINTER(ckey_index_desc), U32,
                                        ctypes.POINTER(ckey_sort_opts), P, SZP, P]
     lib.ckey_compress_sort.argtypes = [ctypes.POINTER(ckey_keys), P, P, U32, P,
@@ -107,7 +108,7 @@ def _load():
                                       ctypes.POINTER(ctypes.c_uint64)]
     lib.ckey_profile_reset.argtypes = []
     lib.ckey_bench_copy.argtypes = [P, P, ctypes.c_size_t, P]
-    for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort",
+    for fn in ("ckey_plan_query", "ckey_distinction_bits", "ckey_compress", "ckey_sort", "ckey_sort_noalloc",
                "ckey_rebuild_index", "ckey_compress_sort", "ckey_graph_create", "ckey_graph_launch",
                "ckey_graph_destroy", "ckey_tune_index", "ckey_variant_bitmap", "ckey_insert_keys", "ckey_tree_plan", "ckey_bulk_load", "ckey_cdf_model_init", "ckey_cdf_fit",
                "ckey_cdf_grad", "ckey_cdf_bucket", "ckey_profile_enable", "ckey_profile_read",
@@ -358,6 +359,19 @@ def ckey_sort(ck, nbits, rowids, workspace=None, stream=None, **opts):
     need = ctypes.c_size_t(ws.numel())
     _check("ckey_sort", _lib.ckey_sort(_ptr(ck), words, nbits, _ptr(rowids), n, ctypes.byref(o),
                                        _ptr(ws), ctypes.byref(need), _stream(stream)))
+    return ck, rowids
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ckey_sort_noalloc(ck, nbits, rowids, stream=None, **opts):
+    """ckey_sort (radix method) with the library's static scratch array instead
+    of a workspace: allocates nothing."""
+    words, n = ck.shape
+    o = _opts(**opts)
+    _check("ckey_sort_noalloc", _lib.ckey_sort_noalloc(_ptr(ck), words, nbits, _ptr(rowids), n,
+                                                       ctypes.byref(o), _stream(stream)))
     return ck, rowids
 
 

@@ -159,6 +159,11 @@ ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
 // so that ties end up in row-id order whatever the input order.
 size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits,
                        uint32_t rid_bits = 0);
+// Passes of a sort of the top nbits of `words` words with digit_bits-bit
+// digits.  A sort of at most kRadixInlinePasses passes (no skip_trivial)
+// makes no heap allocation on the host.
+constexpr uint32_t kRadixInlinePasses = 512;
+uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t digit_bits);
 // skip_trivial: read the pass histograms back (one stream synchronization)
 // and skip every pass whose digit is the same for all n rows.
 ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nbits,

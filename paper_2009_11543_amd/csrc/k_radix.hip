@@ -554,8 +554,29 @@ __global__ void k_copy_back(Bufs bf, uint64_t n, uint32_t words) {
     }
 }
 
-void make_passes(uint32_t words, uint32_t nbits, uint32_t d, uint32_t rid_bits,
-                 std::vector<Pass> &ps) {
+// The passes of one sort: held inline (no heap allocation) up to
+// kRadixInlinePasses, on the heap beyond.
+class PassList {
+  public:
+    void clear() {
+        n_ = 0;
+        heap_.clear();
+    }
+    void push_back(const Pass &p) {
+        if (n_ < kRadixInlinePasses) inl_[n_] = p;
+        else heap_.push_back(p);
+        ++n_;
+    }
+    size_t size() const { return n_; }
+    const Pass &operator[](size_t i) const { return i < kRadixInlinePasses ? inl_[i] : heap_[i - kRadixInlinePasses]; }
+
+  private:
+    Pass inl_[kRadixInlinePasses];
+    std::vector<Pass> heap_;
+    size_t n_ = 0;
+};
+
+void make_passes(uint32_t words, uint32_t nbits, uint32_t d, uint32_t rid_bits, PassList &ps) {
     ps.clear();
     for (uint32_t s = 0; s < rid_bits;) {  // row-id digits are the least significant
         const uint32_t b = std::min<uint32_t>(d, rid_bits - s);
@@ -582,7 +603,7 @@ struct Layout {
 };
 
 Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
-    std::vector<Pass> ps;
+    PassList ps;
     make_passes(words, nbits, d, rid_bits, ps);
     Layout l{};
     l.npass = uint32_t(ps.size());
@@ -752,11 +773,20 @@ size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, u
     return layout(words, nbits, n, d, rid_bits).total;
 }
 
+uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t d) {
+    uint32_t p = 0;
+    for (uint32_t k = 0; k < words; ++k) {
+        const int64_t have = int64_t(nbits) - 64 * int64_t(k);
+        if (have > 0) p += (uint32_t(have > 64 ? 64 : have) + d - 1) / d;
+    }
+    return p;
+}
+
 ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits, uint32_t *rid,
                        uint64_t n, uint32_t d, uint32_t rid_bits, uint32_t *flags, void *ws,
                        hipStream_t st, bool skip_trivial) {
     if (n < 2 || (nbits == 0 && rid_bits == 0)) return CKEY_OK;
-    std::vector<Pass> ps;
+    PassList ps;
     make_passes(words, nbits, d, rid_bits, ps);
     const Layout l = layout(words, nbits, n, d, rid_bits);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
@@ -795,19 +825,15 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         CKEY_TRY(launch_status());
         p0 = p;
     }
-    std::vector<size_t> run;  // passes to run
+    std::vector<uint8_t> trivial;  // skip_trivial only: passes that leave the order as it is
     if (skip_trivial) {
         // A pass whose digit is the same for every row leaves the order as it is.
         std::vector<uint32_t> h(size_t(l.npass) * kRadixMax);
         CKEY_HIP_TRY(hipMemcpyAsync(h.data(), hist, h.size() * 4, hipMemcpyDeviceToHost, st));
         CKEY_HIP_TRY(hipStreamSynchronize(st));
-        for (size_t p = 0; p < ps.size(); ++p) {
-            bool trivial = false;
-            for (int b = 0; b < kRadixMax; ++b) trivial |= h[p * kRadixMax + b] == n;
-            if (!trivial) run.push_back(p);
-        }
-    } else {
-        for (size_t p = 0; p < ps.size(); ++p) run.push_back(p);
+        trivial.assign(ps.size(), 0);
+        for (size_t p = 0; p < ps.size(); ++p)
+            for (int b = 0; b < kRadixMax; ++b) trivial[p] |= h[p * kRadixMax + b] == n;
     }
     hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist);
     CKEY_TRY(launch_status());
@@ -815,7 +841,8 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
     // Ping-pong between the caller's arrays (leading dimension ld) and the
     // workspace copy (leading dimension n).
     Bufs cur{ck, rid, alt, alt_rid, ld, n, nullptr, nullptr};
-    for (size_t p : run) {
+    for (size_t p = 0; p < ps.size(); ++p) {
+        if (!trivial.empty() && trivial[p]) continue;
         CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
         {
             const int pr_ = prof_begin(st, "onesweep");

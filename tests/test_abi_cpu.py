@@ -198,3 +198,25 @@ def test_maintenance_argument_errors_and_queries(ck):
     small = ctypes.c_size_t(1)
     assert lib.ckey_variant_bitmap(ctypes.byref(ia), None, ctypes.c_void_p(512), None, None, ws,
                                    ctypes.byref(small), None) == ck.CKEY_ERR_WORKSPACE
+
+
+def test_sort_noalloc_checks_before_any_gpu_call(ck):
+    """ckey_sort_noalloc validates everything on the host before it touches the
+    GPU: a sort whose workspace exceeds the static scratch array, a bucketing
+    method, skip_trivial and more than 512 passes are refused as unsupported;
+    bad words, digit widths and null pointers as invalid."""
+    lib = ck.lib()
+    U = ck.CKEY_ERR_UNSUPPORTED
+    call = lambda o, words, nbits, n: lib.ckey_sort_noalloc(None, words, nbits, None, n, ctypes.byref(o), None)
+    assert ck.ckey_sort_workspace(1, 60, 6_000_000) > ck.NOALLOC_SCRATCH_BYTES
+    assert call(ck._opts(), 1, 60, 6_000_000) == U
+    assert call(ck._opts(), 3, 192, 2_500_000) == U
+    assert call(ck._opts(method=ck.CKEY_SORT_SPLITTER, bucket_log2=10), 1, 60, 100) == U
+    assert call(ck._opts(method=ck.CKEY_SORT_LEARNED, bucket_log2=10), 1, 60, 100) == U
+    assert call(ck._opts(skip_trivial=True), 1, 60, 100) == U
+    assert call(ck._opts(digit_bits=1), 9, 576, 100) == U          # 576 one-bit passes
+    assert call(ck._opts(), 1, 60, (1 << 30) + 1) == U                 # beyond CKEY_MAX_ROWS
+    assert call(ck._opts(), 0, 0, 100) == ck.CKEY_ERR_INVALID
+    assert call(ck._opts(), 1, 65, 100) == ck.CKEY_ERR_INVALID
+    assert call(ck._opts(digit_bits=9), 1, 60, 100) == ck.CKEY_ERR_INVALID
+    assert call(ck._opts(), 1, 60, 100) == ck.CKEY_ERR_INVALID      # null key and row-id pointers
