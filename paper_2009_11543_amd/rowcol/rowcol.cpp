@@ -4,17 +4,23 @@
 // sort keys -- run on the host cores to set beside the GPU path.  It is not
 // part of the GPU library and nothing in the GPU library calls it.
 //
-// Row-column sort, as Appendix A describes it: with p threads, element size e
-// and C bytes of last-level cache per thread, c = floor(C/e) and
-// t = max(floor(sqrt(n/c)/p), 1).  The n elements form tp init blocks, each
-// cut into sub-blocks of c elements.  (1) Each thread takes t init blocks:
-// sorts each sub-block with the basic sort (quicksort around the pseudo-median
-// of nine, insertion sort below a small size) and merges a block's sub-blocks
-// with a tournament tree into a sorted block (second array).  (2) Thread i
-// computes the i*n/p-split of the tp sorted blocks (how many elements of each
-// block are among the i*n/p smallest), which together form the perfect
-// p-partition.  (3) Thread i merges the i-th parts of all sorted blocks with a
-// tournament tree into the i-th final block (first array).
+// What the row-column sort computes (Appendix A): the elements are cut into
+// t*p equal segments for p threads, t chosen so that a segment holds about
+// t*p runs of cache size (c elements, c*e bytes = the cache per thread).
+// Every run is sorted in cache by a quicksort, each segment's runs are merged
+// by a tournament into a sorted segment, the sorted segments are split at the
+// ranks n*i/p (the "perfect partition": piece i of every segment holds
+// exactly the elements of global rank [n*i/p, n*(i+1)/p)), and thread i
+// merges the i-th pieces of all segments into its slice of the output.
+//
+// How it is built here: an iterative quicksort (explicit stack, pivot = a
+// median of three medians of three on large ranges, insertion sort on short
+// ones); a loser tree for every multi-way merge; and the split ranks found by
+// a multi-sequence selection that keeps, per segment, a window [lo, hi) known
+// to contain the cut, takes the middle element of the widest window as a
+// pivot, counts its global rank with one binary search per segment, and
+// shrinks every window to one side of the pivot's position until all windows
+// are empty.
 //
 // Beside it, the GCC parallel-mode sort (__gnu_parallel::sort, OpenMP) of the
 // same (compressed key, record ID) records, and of (full key, record ID) by
@@ -46,130 +52,152 @@ inline bool less(const Elem<W> &a, const Elem<W> &b) {
     return a.rid < b.rid;
 }
 
-// ---------------------------------------------------------------- basic sort --
+// ----------------------------------------------------------------- run sort --
 
 template <int W>
 void insertion_sort(Elem<W> *a, size_t n) {
     for (size_t i = 1; i < n; ++i) {
+        if (!less(a[i], a[i - 1])) continue;
         Elem<W> v = a[i];
         size_t j = i;
-        while (j > 0 && less(v, a[j - 1])) {
+        do {
             a[j] = a[j - 1];
-            --j;
-        }
+        } while (--j > 0 && less(v, a[j - 1]));
         a[j] = v;
     }
 }
 
+// Middle one of a[x], a[y], a[z] (distinct elements: record IDs differ).
 template <int W>
-size_t med3(const Elem<W> *a, size_t i, size_t j, size_t k) {
-    return less(a[i], a[j]) ? (less(a[j], a[k]) ? j : (less(a[i], a[k]) ? k : i))
-                            : (less(a[k], a[j]) ? j : (less(a[k], a[i]) ? k : i));
+const Elem<W> &mid3(const Elem<W> *a, size_t x, size_t y, size_t z) {
+    const bool xy = less(a[x], a[y]), yz = less(a[y], a[z]), xz = less(a[x], a[z]);
+    if (xy == yz) return a[y];   // x < y < z or z < y < x
+    return xy == xz ? a[z] : a[x];
 }
 
-// Quicksort; the pivot is the median of the medians of three samples of three
-// (Bentley and McIlroy's pseudo-median of nine) on large ranges.
+// Quicksort of one cache-sized run without recursion: the larger side of
+// every partition goes on a small explicit stack, the smaller is sorted next,
+// so the stack never holds more than log2(n) ranges.
 template <int W>
-void basic_sort(Elem<W> *a, size_t n) {
-    while (n > 24) {
-        size_t m;
-        if (n > 40) {
-            const size_t s = n / 8;
-            const size_t x = med3(a, 0, s, 2 * s);
-            const size_t y = med3(a, n / 2 - s, n / 2, n / 2 + s);
-            const size_t z = med3(a, n - 1 - 2 * s, n - 1 - s, n - 1);
-            m = med3(a, x, y, z);
-        } else {
-            m = med3(a, 0, n / 2, n - 1);
+void run_sort(Elem<W> *a, size_t n) {
+    struct Range { size_t b, n; };
+    Range stack[64];
+    int top = 0;
+    stack[top++] = Range{0, n};
+    while (top) {
+        Range r = stack[--top];
+        while (r.n > 16) {
+            Elem<W> *x = a + r.b;
+            const size_t m = r.n;
+            Elem<W> piv;
+            if (m >= 64) {
+                const size_t q = m / 8, h = m / 2;
+                const Elem<W> lo = mid3(x, 0, q, 2 * q), md = mid3(x, h - q, h, h + q),
+                              hi = mid3(x, m - 1 - 2 * q, m - 1 - q, m - 1);
+                const Elem<W> three[3] = {lo, md, hi};
+                piv = mid3(three, 0, 1, 2);
+            } else {
+                piv = mid3(x, 0, m / 2, m - 1);
+            }
+            // Two cursors meet: left of i nothing exceeds the pivot, right of
+            // j nothing is below it; the pivot itself stops both scans.
+            size_t i = 0, j = m - 1;
+            for (;;) {
+                while (less(x[i], piv)) ++i;
+                while (less(piv, x[j])) --j;
+                if (i >= j) break;
+                std::swap(x[i++], x[j--]);
+            }
+            const size_t left = j + 1;
+            Range small{r.b, left}, large{r.b + left, m - left};
+            if (small.n > large.n) std::swap(small, large);
+            stack[top++] = large;
+            r = small;
         }
-        const Elem<W> piv = a[m];
-        // Hoare partition around the pivot value
-        size_t i = 0, j = n - 1;
-        for (;;) {
-            while (less(a[i], piv)) ++i;
-            while (less(piv, a[j])) --j;
-            if (i >= j) break;
-            std::swap(a[i], a[j]);
-            ++i;
-            --j;
-        }
-        const size_t left = j + 1;  // [0, left) <= pivot <= [left, n)
-        if (left < n - left) {
-            basic_sort(a, left);
-            a += left;
-            n -= left;
-        } else {
-            basic_sort(a + left, n - left);
-            n = left;
-        }
+        insertion_sort(a + r.b, r.n);
     }
-    insertion_sort(a, n);
 }
 
-// ------------------------------------------------------------ multiway merge --
+// ---------------------------------------------------------------- loser tree --
 
-struct Run {
+struct Seq {
     size_t b, e;  // [b, e) of the source array
 };
 
-// Tournament (winner) tree over k runs: node v holds the run that wins its
-// subtree; popping the overall winner replays the path from its leaf.
+// k-way merge by a loser tree: each inner node keeps the sequence that lost
+// the match played there, node 0 the overall winner; after the winner's head
+// is output only the matches on its leaf-to-root path are replayed.
 template <int W>
-void multiway_merge(const Elem<W> *src, const std::vector<Run> &runs, Elem<W> *out) {
-    const size_t k = runs.size();
+void loser_merge(const Elem<W> *src, const std::vector<Seq> &in, Elem<W> *out) {
+    const size_t k = in.size();
     if (k == 0) return;
-    size_t cap = 1;
-    while (cap < k) cap <<= 1;
-    std::vector<Run> r(runs);
-    std::vector<int64_t> tree(2 * cap, -1);  // -1: empty
-    auto better = [&](int64_t x, int64_t y) -> int64_t {
-        if (x < 0 || r[x].b >= r[x].e) return y;
-        if (y < 0 || r[y].b >= r[y].e) return x;
-        return less(src[r[y].b], src[r[x].b]) ? y : x;  // ties cannot occur (unique rids)
+    if (k == 1) {
+        std::copy(src + in[0].b, src + in[0].e, out);
+        return;
+    }
+    std::vector<Seq> q(in);
+    // an exhausted sequence loses every match
+    auto beats = [&](size_t u, size_t v) {
+        if (q[u].b == q[u].e) return false;
+        if (q[v].b == q[v].e) return true;
+        return less(src[q[u].b], src[q[v].b]);
     };
-    for (size_t i = 0; i < cap; ++i) tree[cap + i] = i < k ? int64_t(i) : -1;
-    for (size_t v = cap - 1; v >= 1; --v) tree[v] = better(tree[2 * v], tree[2 * v + 1]);
+    std::vector<size_t> node(k);   // node[1..k-1]: losers; node[0]: winner
+    // Build bottom-up: leaves are k + s for sequence s; play every inner match.
+    std::vector<size_t> win(2 * k);
+    for (size_t s = 0; s < k; ++s) win[k + s] = s;
+    for (size_t v = k - 1; v >= 1; --v) {
+        const size_t a = win[2 * v], b = win[2 * v + 1];
+        const bool ab = beats(a, b);
+        win[v] = ab ? a : b;
+        node[v] = ab ? b : a;
+    }
+    node[0] = win[1];
     size_t o = 0;
     for (;;) {
-        const int64_t w = tree[1];
-        if (w < 0 || r[w].b >= r[w].e) break;
-        out[o++] = src[r[w].b++];
-        for (size_t v = (cap + size_t(w)) >> 1; v >= 1; v >>= 1) tree[v] = better(tree[2 * v], tree[2 * v + 1]);
-    }
-}
-
-// ------------------------------------------------------------------ x-split --
-
-// Number of elements of sorted block [b, e) that are less than v.
-template <int W>
-size_t count_less(const Elem<W> *a, const Run &blk, const Elem<W> &v) {
-    size_t lo = blk.b, hi = blk.e;
-    while (lo < hi) {
-        const size_t mid = lo + (hi - lo) / 2;
-        if (less(a[mid], v)) lo = mid + 1; else hi = mid;
-    }
-    return lo - blk.b;
-}
-
-// The x-split of sorted blocks: cut[i] = how many elements of block i are
-// among the x smallest of all blocks.  Elements are distinct (the record ID is
-// part of the sort key), so element v is among them iff fewer than x elements
-// are less than v; within a block that holds for a prefix, found by binary
-// search.
-template <int W>
-void x_split(const Elem<W> *a, const std::vector<Run> &blocks, size_t x, std::vector<size_t> &cut) {
-    cut.assign(blocks.size(), 0);
-    for (size_t i = 0; i < blocks.size(); ++i) {
-        size_t lo = 0, hi = blocks[i].e - blocks[i].b;  // answer in [lo, hi]
-        while (lo < hi) {
-            const size_t mid = lo + (hi - lo + 1) / 2;  // is element mid-1 among the x smallest?
-            const Elem<W> &v = a[blocks[i].b + mid - 1];
-            size_t rank = 0;
-            for (size_t m = 0; m < blocks.size() && rank < x; ++m) rank += count_less(a, blocks[m], v);
-            if (rank < x) lo = mid; else hi = mid - 1;
+        size_t w = node[0];
+        if (q[w].b == q[w].e) break;  // the winner is empty: every sequence is
+        out[o++] = src[q[w].b++];
+        for (size_t v = (k + w) >> 1; v >= 1; v >>= 1) {
+            if (beats(node[v], w)) std::swap(node[v], w);
         }
-        cut[i] = lo;
+        node[0] = w;
     }
+}
+
+// ---------------------------------------------------------- perfect partition --
+
+// Elements of sorted sequence s below v.
+template <int W>
+size_t rank_in(const Elem<W> *a, const Seq &s, const Elem<W> &v) {
+    return size_t(std::lower_bound(a + s.b, a + s.e, v, less<W>) - (a + s.b));
+}
+
+// Multi-sequence selection: cut[i] = how many elements of sorted sequence i
+// have global rank below x (elements are distinct).  Window [lo[i], hi[i])
+// of sequence i holds the positions not yet known to be below or above the
+// cut; a pivot from the widest window settles at least half of it.
+template <int W>
+void select_cut(const Elem<W> *a, const std::vector<Seq> &seqs, size_t x, std::vector<size_t> &cut) {
+    const size_t k = seqs.size();
+    std::vector<size_t> lo(k, 0), hi(k), pos(k);
+    for (size_t i = 0; i < k; ++i) hi[i] = seqs[i].e - seqs[i].b;
+    for (;;) {
+        size_t wi = k, width = 0;
+        for (size_t i = 0; i < k; ++i)
+            if (hi[i] - lo[i] > width) { width = hi[i] - lo[i]; wi = i; }
+        if (wi == k) break;
+        const Elem<W> &v = a[seqs[wi].b + lo[wi] + width / 2];
+        size_t r = 0;  // global rank of v
+        for (size_t i = 0; i < k; ++i) { pos[i] = rank_in(a, seqs[i], v); r += pos[i]; }
+        if (r < x) {         // v and everything below it is under the cut
+            for (size_t i = 0; i < k; ++i) lo[i] = std::max(lo[i], pos[i] + (i == wi ? 1 : 0));
+        } else {             // v and everything above it is over the cut
+            for (size_t i = 0; i < k; ++i) hi[i] = std::min(hi[i], pos[i]);
+        }
+        for (size_t i = 0; i < k; ++i) hi[i] = std::max(hi[i], lo[i]);
+    }
+    cut = lo;
 }
 
 template <typename F>
@@ -180,43 +208,50 @@ void parallel(int p, F f) {
     for (auto &t : th) t.join();
 }
 
+// Row-column sort (Appendix A) of key[0, n) using temp[0, n); the result is
+// back in key.  t_phase (or NULL): seconds of the segment sorts, the
+// partition and the final merges.
 template <int W>
 void row_column_sort(Elem<W> *key, Elem<W> *temp, size_t n, int p, uint64_t cache_bytes, double *t_phase) {
     using clk = std::chrono::steady_clock;
     if (n < 2) return;
-    const size_t e = sizeof(Elem<W>);
-    const size_t c = std::max<size_t>(1, size_t(cache_bytes / e));
-    const size_t t = std::max<size_t>(1, size_t(std::floor(std::sqrt(double(n) / double(c)) / p)));
-    const size_t nb = t * size_t(p);  // init blocks
-    std::vector<Run> blocks(nb);
-    for (size_t i = 0; i < nb; ++i) blocks[i] = Run{n * i / nb, n * (i + 1) / nb};
+    const size_t P = size_t(p);
+    const size_t c = std::max<size_t>(1, size_t(cache_bytes / sizeof(Elem<W>)));  // elements per run
+    // segments per thread: a segment of n/(t p) elements holds n/(t p c) runs,
+    // which balances the segment merge (runs per segment) against the final
+    // merge (t p segments) when n/(t p c) = t p
+    const size_t t = std::max<size_t>(1, size_t(std::sqrt(double(n) / double(c)) / double(P)));
+    const size_t nseg = t * P;
+    auto seg = [&](size_t s) { return Seq{n * s / nseg, n * (s + 1) / nseg}; };
     auto t0 = clk::now();
     parallel(p, [&](int th) {
-        for (size_t j = 0; j < t; ++j) {
-            const Run B = blocks[size_t(th) * t + j];
-            std::vector<Run> subs;
-            for (size_t s = B.b; s < B.e; s += c) {
-                const size_t se = std::min(B.e, s + c);
-                basic_sort(key + s, se - s);
-                subs.push_back(Run{s, se});
+        for (size_t s = size_t(th); s < nseg; s += P) {  // thread th: segments th, th + p, ...
+            const Seq S = seg(s);
+            std::vector<Seq> runs;
+            for (size_t b = S.b; b < S.e; b += c) {
+                const size_t e = std::min(S.e, b + c);
+                run_sort(key + b, e - b);
+                runs.push_back(Seq{b, e});
             }
-            multiway_merge(key, subs, temp + B.b);
+            loser_merge(key, runs, temp + S.b);
         }
     });
     auto t1 = clk::now();
-    std::vector<std::vector<size_t>> cuts(size_t(p) + 1);
-    cuts[0].assign(nb, 0);
-    cuts[size_t(p)].resize(nb);
-    for (size_t i = 0; i < nb; ++i) cuts[size_t(p)][i] = blocks[i].e - blocks[i].b;
+    std::vector<Seq> segs(nseg);
+    for (size_t s = 0; s < nseg; ++s) segs[s] = seg(s);
+    std::vector<std::vector<size_t>> cut(P + 1);
+    cut[0].assign(nseg, 0);
+    cut[P].resize(nseg);
+    for (size_t s = 0; s < nseg; ++s) cut[P][s] = segs[s].e - segs[s].b;
     parallel(p, [&](int th) {
-        if (th >= 1) x_split(temp, blocks, n * size_t(th) / size_t(p), cuts[size_t(th)]);
+        if (th > 0) select_cut(temp, segs, n * size_t(th) / P, cut[size_t(th)]);
     });
     auto t2 = clk::now();
     parallel(p, [&](int th) {
-        std::vector<Run> parts(nb);
-        for (size_t i = 0; i < nb; ++i)
-            parts[i] = Run{blocks[i].b + cuts[size_t(th)][i], blocks[i].b + cuts[size_t(th) + 1][i]};
-        multiway_merge(temp, parts, key + n * size_t(th) / size_t(p));
+        std::vector<Seq> piece(nseg);
+        for (size_t s = 0; s < nseg; ++s)
+            piece[s] = Seq{segs[s].b + cut[size_t(th)][s], segs[s].b + cut[size_t(th) + 1][s]};
+        loser_merge(temp, piece, key + n * size_t(th) / P);
     });
     auto t3 = clk::now();
     if (t_phase) {
