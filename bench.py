@@ -123,7 +123,23 @@ def cpu_baseline(rows_all, n_sample):
     assert len(perm) == n_sample
     return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample} rows of the workload; oracle compress (bit by bit) + "
-                      f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s"}, d, perm
+                      f"qsort of compressed keys, D-bitmap of the sample given; {dt:.1f} s",
+            **host_cpu()}, d, perm
+
+
+def host_cpu():
+    """The host CPU the baselines ran on: model name, logical CPUs the process
+    may use, and logical CPUs of the machine."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpus_total": os.cpu_count()}
 
 
 def cpu_rowcol(rows_all, n_sample, d, perm_ref):
@@ -138,7 +154,7 @@ def cpu_rowcol(rows_all, n_sample, d, perm_ref):
     return {"value": n_sample / dt, "unit": "keys/s", "cores": threads,
             "kind": "row-column sort (Appendix A) + PEXT compression (Sec. 5.1)",
             "sample": f"first {n_sample} rows; compress {t['compress_s']:.3f} s + sort {t['sort_s']:.3f} s "
-                      f"(C = {t['cache_bytes']} B per thread)"}
+                      f"(C = {t['cache_bytes']} B per thread)", **host_cpu()}
 
 
 def cpu_gnu(rows_all, n_sample, d, perm_ref):
@@ -156,7 +172,8 @@ def cpu_gnu(rows_all, n_sample, d, perm_ref):
     return {"full_keys": {"value": n_sample / sf, "unit": "keys/s", "seconds": sf},
             "compressed": {"value": n_sample / dt, "unit": "keys/s", "compress_s": t["compress_s"],
                            "sort_s": t["sort_s"]},
-            "cores": threads, "kind": "__gnu_parallel::sort (OpenMP)", "sample": f"first {n_sample} rows"}
+            "cores": threads, "kind": "__gnu_parallel::sort (OpenMP)", "sample": f"first {n_sample} rows",
+            **host_cpu()}
 
 
 def bench_table(args, torch, ckey, prof, dev):
@@ -582,16 +599,19 @@ def main():
                                 **method_opts[m])
 
     def timed(m, steps):
-        # The step time with the per-kernel event timing off; then the same
-        # steps again with it on, for the per-kernel times.
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # The step time with the per-kernel event timing off (an event between
+        # consecutive steps: the median step, and the mean over the region);
+        # then the same steps again with it on, for the per-kernel times.
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
-        e0.record()
-        for _ in range(steps):
+        ev[0].record()
+        for i in range(steps):
             step(m)
-        e1.record()
+            ev[i + 1].record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        ms = float(np.median(per))
+        timed.mean_ms = ev[0].elapsed_time(ev[steps]) / steps
         prof.on()
         for _ in range(steps):
             step(m)
@@ -619,7 +639,8 @@ def main():
             step(best)
         results[best] = timed(best, args.steps)
     ms, kern = results[best]
-    log(f"chosen {best}: {ms:.3f} ms/step; kernels {json.dumps(kern)}")
+    mean_ms = timed.mean_ms
+    log(f"chosen {best}: {ms:.3f} ms/step (median; mean {mean_ms:.3f}); kernels {json.dumps(kern)}")
     assert int(flags.item()) & ckey.CKEY_FLAG_SPIN_LIMIT == 0
 
     # Algorithmic bytes per key of each kernel: what it must read and write once.
@@ -631,13 +652,25 @@ def main():
     # the record IDs); the two bucket passes move rec + 2 bytes in and out,
     # less the record IDs pass 1 does not read, plus pass 1's bucket-id copy.
     # (the bucketing methods' compression writes no record IDs)
+    # Kernel bytes as implemented (what each launch moves once) ...
     per_key = {"compress": key_bytes_read + (rec if best == "radix" else 8 * w),
                "compress_bucket": key_bytes_read + 8 * w + 2,
                "hist": 8 * w, "onesweep": 2 * rec,
                "assign_learned": 8 + 2, "assign_splitter": 8 + 2, "tile_counts": 2,
-               "bucket_pass": 2 * rec + 1,
+               "bucket_pass": 2 * rec,
                "bucket_sort": 2 * rec}
-    step_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
+    moved_bytes = sum(per_key[k] * n * v["launches_per_step"] for k, v in kern.items())
+    # ... and the method's bytes per key, which the GB/s figure is taken from:
+    # key bytes read + compressed record written + (radix) one histogram read
+    # of the words and a read and a write of every record per pass, or
+    # (bucketing) a read of the first word for the bucket, the one scatter of
+    # every record into its bucket, and the bucket sort's read and write.
+    if best == "radix":
+        npass = sum(-(-min(64, nbits - 64 * k) // 8) for k in range(w) if nbits > 64 * k)
+        method_key = key_bytes_read + rec + 8 * w + 2 * npass * rec
+    else:
+        method_key = key_bytes_read + rec + 8 + 2 * rec + 2 * rec
+    step_bytes = method_key * n
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     dom_bytes = per_key[dom] * n
     achieved = dom_bytes / (kern[dom]["ms_per_launch"] / 1e3) / 1e9
@@ -655,8 +688,11 @@ def main():
                    "nbits": nbits, "words": w, "method": best,
                    "bucket_log2": args.bucket_log2 if best != "radix" else None,
                    "digit_bits": 8 if best == "radix" else None},
+        "ms_per_step_mean": mean_ms,
         "hbm_gbps_algorithmic": step_bytes / (ms / 1e3) / 1e9,
         "bytes_per_key_algorithmic": step_bytes / n,
+        "hbm_gbps_moved": moved_bytes / (ms / 1e3) / 1e9,
+        "bytes_per_key_moved": moved_bytes / n,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBPS,
                      "traffic": traffic, "bytes_per_launch_algorithmic": dom_bytes,
