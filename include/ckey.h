@@ -137,8 +137,10 @@ typedef struct {
  * capacity (a second synchronization), and those still left (larger, or with
  * a run of more than 32 equal first words) are finished by the radix sort and
  * raise CKEY_FLAG_BUCKET_OVERFLOW; so does a widespread overflow (more than
- * 64 buckets or an eighth of the rows), which radix-sorts everything.  Needs
- * a workspace. */
+ * 64 buckets or an eighth of the rows), which radix-sorts everything.  While
+ * `stream` is being captured into a graph the same decisions are taken on the
+ * device instead (see ckey_graph_create), with no synchronization.  Needs a
+ * workspace. */
 ckey_status ckey_sort(uint64_t *ckeys, uint32_t words, uint32_t nbits, uint32_t *rowids,
                       uint64_t n, const ckey_sort_opts *opts, void *workspace,
                       size_t *workspace_bytes, void *stream);
@@ -215,11 +217,15 @@ ckey_status ckey_rebuild_index(const ckey_index_desc *idx, uint32_t count,
 
 /* A table rebuild captured once into a HIP graph and replayed with one launch.
  * ckey_graph_create records what ckey_rebuild_index(idx, count, opts, ...)
- * enqueues (the descriptors' pointers, bitmaps and sizes are fixed at
+ * enqueues (the descriptors' pointers, bitmaps, sizes and models are fixed at
  * creation; the workspace must stay valid while the graph exists) and
- * instantiates it; only the radix method can be captured (the bucketing
- * methods read an overflow count back to the host).  With opts->fused_table
- * the graph holds the fill kernel and the one persistent launch.
+ * instantiates it.  Every sort method can be captured: a captured bucketing
+ * sort never asks the host about overflowing buckets -- one kernel walks the
+ * overflow list on the device (more than 64 overflowing buckets skip it), and
+ * a radix sort of the whole index, whose kernels are always in the graph and
+ * return at once unless a device word opens them, finishes any bucket still
+ * unsorted (raising CKEY_FLAG_BUCKET_OVERFLOW).  With opts->fused_table the
+ * graph holds the fill kernel and the one persistent launch.
  * ckey_graph_launch replays it on `stream`. */
 typedef struct ckey_graph ckey_graph;
 ckey_status ckey_graph_create(const ckey_index_desc *idx, uint32_t count, const ckey_sort_opts *opts,

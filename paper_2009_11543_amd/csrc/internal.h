@@ -106,8 +106,9 @@ void prof_end(hipStream_t st, int idx);
 // Distinction bits (k_dbits.hip).
 ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc_words,
                          uint32_t *flags, hipStream_t st);
-// Clear n u32 words (a fill kernel, safe inside graph capture).
-ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st);
+// Clear n u32 words (a fill kernel, safe inside graph capture).  gate: a
+// device word read by the kernel, which writes nothing while it is 0.
+ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const uint32_t *gate = nullptr);
 // Copy a little-endian u32 bitmap accumulator into a byte bitmap of L bytes.
 ckey_status bitmap_finalize(const uint32_t *acc_words, uint8_t *bitmap, uint32_t L, hipStream_t st);
 
@@ -166,9 +167,13 @@ constexpr uint32_t kRadixInlinePasses = 512;
 uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t digit_bits);
 // skip_trivial: read the pass histograms back (one stream synchronization)
 // and skip every pass whose digit is the same for all n rows.
+// gate (device word, or nullptr): every kernel of the sort returns at once
+// while it is 0 -- a sort enqueued whether or not it turns out to be needed
+// (a captured graph cannot ask the host).
 ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nbits,
                        uint32_t *rowids, uint64_t n, uint32_t digit_bits, uint32_t rid_bits,
-                       uint32_t *flags, void *ws, hipStream_t st, bool skip_trivial = false);
+                       uint32_t *flags, void *ws, hipStream_t st, bool skip_trivial = false,
+                       const uint32_t *gate = nullptr);
 
 // Stable sort of rows [0, n) by a 16-bit aux key of aux_bits bits (two
 // one-sweep passes; the aux array is read, not reordered), moving the words

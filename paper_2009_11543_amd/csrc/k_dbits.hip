@@ -136,7 +136,8 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
         if (s_bm[t]) atomicOr(&acc[t], s_bm[t]);
 }
 
-__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v, const uint32_t *gate) {
+    if (gate && *gate == 0u) return;
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) p[i] = v;
 }
@@ -153,11 +154,11 @@ ckey_status fill_flag_or(uint32_t *flags, uint32_t v, hipStream_t st) {
     return launch_status();
 }
 
-ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st) {
+ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t st, const uint32_t *gate) {
     if (n == 0) return CKEY_OK;
     uint64_t blocks = (n + kWG - 1) / kWG;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_u32, dim3(uint32_t(blocks)), dim3(kWG), 0, st, p, n, v);
+    hipLaunchKernelGGL(k_fill_u32, dim3(uint32_t(blocks)), dim3(kWG), 0, st, p, n, v, gate);
     return launch_status();
 }
 

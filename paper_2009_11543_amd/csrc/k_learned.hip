@@ -366,14 +366,13 @@ __device__ __forceinline__ void run_carries(uint32_t cnt, uint32_t starts, uint3
 //    are staged in LDS (coalesced load) and written back in sorted order
 //    (coalesced store).
 //
-// list (optional): the buckets to sort are list[1 + 3 i] for workgroup i (an
-// overflow list of the smaller kernels), else bucket = workgroup.  Buckets it
-// cannot sort go to ovf as (bucket, start, count) triples after ovf[0].
+// Buckets it cannot sort go to ovf as (bucket, start, count) triples after
+// ovf[0] (their count).  Every thread of the workgroup calls it.
 template <int WC, int kCap, int kSortWG>
-__global__ __launch_bounds__(kSortWG, (kCap > 5120 ? 4 : 8)) void k_bucket_sort(
-    uint64_t *__restrict__ ck, uint32_t *__restrict__ rid, uint64_t n, uint32_t words_rt,
+__device__ __forceinline__ void sort_bucket(
+    uint32_t b, uint64_t *__restrict__ ck, uint32_t *__restrict__ rid, uint64_t n, uint32_t words_rt,
     const uint32_t *__restrict__ starts, const uint64_t *__restrict__ T, uint32_t B,
-    uint32_t *__restrict__ ovf, const uint32_t *__restrict__ list) {
+    uint32_t *__restrict__ ovf) {
     constexpr int NW = kSortWG / 64;
     constexpr int PER = (kCap + kSortWG - 1) / kSortWG;
     constexpr uint32_t kTieCap = 256;
@@ -399,7 +398,6 @@ __global__ __launch_bounds__(kSortWG, (kCap > 5120 ? 4 : 8)) void k_bucket_sort(
     __shared__ int32_t s_rb[2 * NW];     // run_carries exchange
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint32_t b = list ? list[1 + 3 * blockIdx.x] : blockIdx.x;
     const uint32_t start = starts[b];
     const uint32_t cnt = starts[b + 1] - start;
     auto overflow = [&]() {  // leave the bucket for the radix sort
@@ -990,6 +988,50 @@ __global__ __launch_bounds__(kSortWG, (kCap > 5120 ? 4 : 8)) void k_bucket_sort(
     }
 }
 
+// One workgroup per bucket; list (optional): the buckets to sort are
+// list[1 + 3 i] for workgroup i (an overflow list of the smaller kernels),
+// else bucket = workgroup.
+template <int WC, int kCap, int kSortWG>
+__global__ __launch_bounds__(kSortWG, (kCap > 5120 ? 4 : 8)) void k_bucket_sort(
+    uint64_t *__restrict__ ck, uint32_t *__restrict__ rid, uint64_t n, uint32_t words_rt,
+    const uint32_t *__restrict__ starts, const uint64_t *__restrict__ T, uint32_t B,
+    uint32_t *__restrict__ ovf, const uint32_t *__restrict__ list) {
+    const uint32_t b = list ? list[1 + 3 * blockIdx.x] : blockIdx.x;
+    sort_bucket<WC, kCap, kSortWG>(b, ck, rid, n, words_rt, starts, T, B, ovf);
+}
+
+// Overflowing buckets when the host cannot be asked how many there are (a
+// captured graph): every workgroup walks the overflow list of the first bucket
+// sort (list[0] entries), sorting its share with the second-chance capacity;
+// what still overflows goes to ovf2.  More than kMaxSecondChance entries
+// (data the thresholds do not split) skip this and open the gate of the
+// whole-array radix sort at once.
+constexpr uint32_t kMaxSecondChance = 64;
+template <int WC>
+__global__ __launch_bounds__(1024, 4) void k_bucket_sort_again(
+    uint64_t *__restrict__ ck, uint32_t *__restrict__ rid, uint64_t n, uint32_t words_rt,
+    const uint32_t *__restrict__ starts, const uint64_t *__restrict__ T, uint32_t B,
+    const uint32_t *__restrict__ list, uint32_t *__restrict__ ovf2, uint32_t *__restrict__ gate) {
+    const uint32_t c = list[0];
+    if (c > kMaxSecondChance) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *gate = 1u;
+        return;
+    }
+    for (uint32_t i = blockIdx.x; i < c; i += gridDim.x) {
+        __syncthreads();  // the previous bucket's LDS reads are done
+        sort_bucket<WC, kCapHuge, 1024>(list[1 + 3 * i], ck, rid, n, words_rt, starts, T, B, ovf2);
+    }
+}
+
+// Opens the fallback's gate when a bucket is still unsorted (and says so in
+// the flags word); one thread.
+__global__ void k_overflow_gate(const uint32_t *__restrict__ ovf2, uint32_t *__restrict__ gate,
+                                uint32_t *__restrict__ flags) {
+    const bool open = *gate != 0u || ovf2[0] != 0u;
+    *gate = open ? 1u : 0u;
+    if (open && flags) atomicOr(flags, CKEY_FLAG_BUCKET_OVERFLOW);
+}
+
 struct LLayout {
     size_t bid, hist, starts, ovf, ovf2, stats, sortws, total;
 };
@@ -1033,10 +1075,17 @@ ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const Bucket
 
 bool learned_b_ok(uint32_t b_log2) { return b_log2 >= 8 && b_log2 <= 16; }
 
-size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2) {
+// The bucket layout and the fallback radix sort share the workspace from
+// offset 0 (the radix sort starts once the lists are no longer needed); the
+// gate of a captured fallback sits past both.
+size_t gate_offset(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2) {
     const size_t a = llayout(words, n, 1u << b_log2).total;
     const size_t r = radix_workspace(words, nbits, n, 8, 32);
-    return a > r ? a : r;
+    return align256(a > r ? a : r);
+}
+
+size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2) {
+    return gate_offset(words, nbits, n, b_log2) + 256;
 }
 
 namespace {
@@ -1085,6 +1134,34 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    CKEY_HIP_TRY(hipStreamIsCapturing(st, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        // Captured: no host round trip.  The second chance walks the list on
+        // the device; a bucket it still cannot sort (or a widespread
+        // overflow) opens the gate of one radix sort of everything by (key,
+        // row id), exact from any arrangement, whose kernels are enqueued
+        // always and return at once while the gate is closed.
+        uint32_t *gate = reinterpret_cast<uint32_t *>(w8 + gate_offset(words, nbits, n, b_log2));
+        CKEY_TRY(fill_u32(gate, 1, 0, st));
+        CKEY_TRY(fill_u32(q.ovf2, 1, 0, st));
+        int dev = 0, cus = 0;
+        CKEY_HIP_TRY(hipGetDevice(&dev));
+        CKEY_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const uint32_t grid = uint32_t(cus > 0 ? cus : 1);
+        auto ka = words == 1 ? k_bucket_sort_again<1> : words == 2 ? k_bucket_sort_again<2>
+                : words == 3 ? k_bucket_sort_again<3> : k_bucket_sort_again<0>;
+        {
+            const int pr = prof_begin(st, "bucket_sort_large");
+            hipLaunchKernelGGL(ka, dim3(grid), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf,
+                               q.ovf2, gate);
+            prof_end(st, pr);
+        }
+        CKEY_TRY(launch_status());
+        hipLaunchKernelGGL(k_overflow_gate, dim3(1), dim3(1), 0, st, q.ovf2, gate, flags);
+        CKEY_TRY(launch_status());
+        return radix_sort(ck, n, words, nbits, rid, n, 8, 32, flags, ws, st, false, gate);
+    }
     // Overflowing buckets (count, then (bucket, start, rows) triples).
     auto read_list = [&](const uint32_t *dev, std::vector<uint32_t> &v) -> ckey_status {
         uint32_t c = 0;

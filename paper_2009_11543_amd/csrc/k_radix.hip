@@ -61,6 +61,7 @@ struct Bufs {
     uint64_t src_ld, dst_ld;
     const uint16_t *src_aux;  // aux key: read by aux-digit passes,
     uint16_t *dst_aux;        // and moved along when dst_aux != nullptr
+    const uint32_t *gate;     // nullptr, or a device word: 0 = the sort does nothing
 };
 
 struct HistArgs {
@@ -68,12 +69,18 @@ struct HistArgs {
     uint32_t shift[8];
     uint32_t bits[8];
     uint32_t out[8];  // pass index of each digit
+    const uint32_t *gate;
 };
+
+// A gated sort (the fallback of a captured bucketing sort) runs only when the
+// device word says so: every kernel of it returns at once on a closed gate.
+__device__ __forceinline__ bool gate_closed(const uint32_t *gate) { return gate && *gate == 0u; }
 
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_hist(const T *__restrict__ word, uint64_t n, HistArgs ha,
                                               uint32_t *__restrict__ hist) {
     __shared__ uint32_t s_h[8][kRadixMax];
+    if (gate_closed(ha.gate)) return;
     for (int t = threadIdx.x; t < 8 * kRadixMax; t += kWG) (&s_h[0][0])[t] = 0;
     __syncthreads();
     const uint64_t step = uint64_t(gridDim.x) * kWG;
@@ -92,8 +99,9 @@ __global__ __launch_bounds__(kWG) void k_hist(const T *__restrict__ word, uint64
 }
 
 // One workgroup per pass: hist[p][*] -> exclusive prefix in place.
-__global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(kWG) void k_scan(uint32_t *__restrict__ hist, const uint32_t *gate) {
     __shared__ uint32_t s_tmp[4];
+    if (gate_closed(gate)) return;
     uint32_t *h = hist + blockIdx.x * kRadixMax;
     const uint32_t v = h[threadIdx.x];
     uint32_t total;
@@ -114,6 +122,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     __shared__ uint32_t s_tmp[4];
     __shared__ uint64_t s_buf[kTile];
 
+    if (gate_closed(bf.gate)) return;
     const uint32_t words = WC > 0 ? uint32_t(WC) : words_rt;
     const uint64_t *__restrict__ src = bf.src;
     const uint32_t *__restrict__ src_rid = bf.src_rid;
@@ -302,6 +311,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
     __shared__ uint64_t s_buf[TILE];
     __shared__ uint8_t s_dig[TILE];               // digit of each slot, in slot order
 
+    if (gate_closed(bf.gate)) return;
     const bool rid_pass = ps.word == kRidWord;
     const bool aux_pass = ps.word == kAuxWord;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -546,6 +556,7 @@ void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, con
 }
 
 __global__ void k_copy_back(Bufs bf, uint64_t n, uint32_t words) {
+    if (gate_closed(bf.gate)) return;
     const uint64_t step = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
         for (uint32_t k = 0; k < words; ++k)
@@ -730,7 +741,7 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
         hipLaunchKernelGGL(k_hist<uint16_t>, dim3(uint32_t(hblocks)), dim3(kWG), 0, st, aux, n, ha, hist);
         prof_end(st, pr_);
         CKEY_TRY(launch_status());
-        hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist);
+        hipLaunchKernelGGL(k_scan, dim3(ha.npass), dim3(kWG), 0, st, hist, static_cast<const uint32_t *>(nullptr));
         CKEY_TRY(launch_status());
     }
     // With two passes: caller -> workspace (moving aux) -> caller.
@@ -784,7 +795,7 @@ uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t d) {
 
 ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits, uint32_t *rid,
                        uint64_t n, uint32_t d, uint32_t rid_bits, uint32_t *flags, void *ws,
-                       hipStream_t st, bool skip_trivial) {
+                       hipStream_t st, bool skip_trivial, const uint32_t *gate) {
     if (n < 2 || (nbits == 0 && rid_bits == 0)) return CKEY_OK;
     PassList ps;
     make_passes(words, nbits, d, rid_bits, ps);
@@ -796,13 +807,14 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
     uint32_t *lookback = reinterpret_cast<uint32_t *>(w8 + l.lookback);
     uint32_t *counters = reinterpret_cast<uint32_t *>(w8 + l.counters);
 
-    CKEY_TRY(fill_u32(hist, size_t(l.npass) * kRadixMax, 0, st));
-    CKEY_TRY(fill_u32(counters, l.npass, 0, st));
+    CKEY_TRY(fill_u32(hist, size_t(l.npass) * kRadixMax, 0, st, gate));
+    CKEY_TRY(fill_u32(counters, l.npass, 0, st, gate));
     // Upfront histograms, grouped by source array, at most 8 digits per launch.
     uint64_t hblocks = (n + kWG * 16 - 1) / (kWG * 16);
     if (hblocks > 2048) hblocks = 2048;
     for (size_t p0 = 0; p0 < ps.size();) {
         HistArgs ha{};
+        ha.gate = gate;
         const uint32_t wk = ps[p0].word;
         size_t p = p0;
         while (p < ps.size() && ps[p].word == wk && ha.npass < 8) {
@@ -835,15 +847,15 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         for (size_t p = 0; p < ps.size(); ++p)
             for (int b = 0; b < kRadixMax; ++b) trivial[p] |= h[p * kRadixMax + b] == n;
     }
-    hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist);
+    hipLaunchKernelGGL(k_scan, dim3(l.npass), dim3(kWG), 0, st, hist, gate);
     CKEY_TRY(launch_status());
 
     // Ping-pong between the caller's arrays (leading dimension ld) and the
     // workspace copy (leading dimension n).
-    Bufs cur{ck, rid, alt, alt_rid, ld, n, nullptr, nullptr};
+    Bufs cur{ck, rid, alt, alt_rid, ld, n, nullptr, nullptr, gate};
     for (size_t p = 0; p < ps.size(); ++p) {
         if (!trivial.empty() && trivial[p]) continue;
-        CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st));
+        CKEY_TRY(fill_u32(lookback, size_t(l.tiles) * kRadixMax, 0, st, gate));
         {
             const int pr_ = prof_begin(st, "onesweep");
             launch_pass(words, l.tiles, cur, n, ps[p], hist + p * kRadixMax, lookback, counters + p,
@@ -852,7 +864,7 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         }
         CKEY_TRY(launch_status());
         cur = Bufs{cur.dst, cur.dst_rid, const_cast<uint64_t *>(cur.src),
-                   const_cast<uint32_t *>(cur.src_rid), cur.dst_ld, cur.src_ld, nullptr, nullptr};
+                   const_cast<uint32_t *>(cur.src_rid), cur.dst_ld, cur.src_ld, nullptr, nullptr, gate};
     }
     if (cur.src != ck) {
         uint64_t blocks = (n + kWG - 1) / kWG;
