@@ -122,6 +122,14 @@ typedef struct {
     uint32_t fused_table; /* ckey_rebuild_index / ckey_graph_create only (the call's
                            * opts): 1 = every index rebuilt by one persistent kernel
                            * launch (radix method; see ckey_rebuild_index)          */
+    uint32_t tile;        /* rows a workgroup takes at once (an autotuning choice);
+                           * 0 = chosen from the shape.  Radix, keys of 1..8 words:
+                           * 1 = the full pass tile (1024 threads x 12, 10, 8, 6, 6,
+                           * 5, 4, 4 rows for 1..8 words), 2 = half of it (512
+                           * threads); wider keys have one tile.  Bucketing: the
+                           * in-LDS capacity of a bucket, 1 = 2560 rows (512
+                           * threads), 2 = 5120, 3 = 10240 (1024 threads); 0 picks
+                           * by the mean bucket size (<= 1600, <= 4400, more)      */
 } ckey_sort_opts;
 
 /* Sort (compressed key, row id) pairs (Sec. 3.2 compressed key sort; Sec. 5,

@@ -39,7 +39,7 @@ class ckey_sort_opts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_uint32), ("digit_bits", ctypes.c_uint32),
                 ("bucket_log2", ctypes.c_uint32), ("skip_trivial", ctypes.c_uint32),
                 ("model", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("fused_table", ctypes.c_uint32)]
+                ("fused_table", ctypes.c_uint32), ("tile", ctypes.c_uint32)]
 
 
 class ckey_index_desc(ctypes.Structure):
@@ -307,12 +307,12 @@ def ckey_compress(keys, bitmap, words=None, out=None, rowids=None, flags=None, s
 
 
 def _opts(method=CKEY_SORT_RADIX, digit_bits=0, bucket_log2=None, model=None, flags=None, skip_trivial=False,
-          fused_table=False):
+          fused_table=False, tile=0):
     if bucket_log2 is None:
         bucket_log2 = model.bucket_log2 if model is not None else 0
     return ckey_sort_opts(method, digit_bits, bucket_log2, 1 if skip_trivial else 0,
                           None if model is None else model.handle,
-                          None if flags is None else flags.data_ptr(), 1 if fused_table else 0)
+                          None if flags is None else flags.data_ptr(), 1 if fused_table else 0, tile)
 
 
 def ckey_compress_sort(keys, bitmap, out=None, rowids=None, words=None, workspace=None,

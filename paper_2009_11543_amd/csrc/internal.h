@@ -158,8 +158,10 @@ ckey_status refine_launch(const uint64_t *ckeys, uint32_t words, uint64_t n,
 // (word k of row i at ckeys[k*ld + i]) by their top nbits, moving rowids
 // along.  rid_bits > 0 first sorts by the low rid_bits bits of the row ids,
 // so that ties end up in row-id order whatever the input order.
+// half_tile: passes over 1..8 words take half the rows per workgroup (512
+// threads); an option the autotuner may choose.
 size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t digit_bits,
-                       uint32_t rid_bits = 0);
+                       uint32_t rid_bits = 0, bool half_tile = false);
 // Passes of a sort of the top nbits of `words` words with digit_bits-bit
 // digits.  A sort of at most kRadixInlinePasses passes (no skip_trivial)
 // makes no heap allocation on the host.
@@ -173,7 +175,7 @@ uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t digit_bits);
 ckey_status radix_sort(uint64_t *ckeys, uint64_t ld, uint32_t words, uint32_t nbits,
                        uint32_t *rowids, uint64_t n, uint32_t digit_bits, uint32_t rid_bits,
                        uint32_t *flags, void *ws, hipStream_t st, bool skip_trivial = false,
-                       const uint32_t *gate = nullptr);
+                       const uint32_t *gate = nullptr, bool half_tile = false);
 
 // Stable sort of rows [0, n) by a 16-bit aux key of aux_bits bits (two
 // one-sweep passes; the aux array is read, not reordered), moving the words
@@ -210,9 +212,11 @@ ckey_status table_fused_plan(const TableIndex *ti, uint32_t count, void *ws, siz
 // mode 0 = splitter search.
 bool learned_b_ok(uint32_t b_log2);
 size_t learned_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t b_log2);
+// cap: the in-LDS capacity of a bucket, 1 = 2560 rows, 2 = 5120, 3 = 10240,
+// 0 = chosen from the mean bucket size.
 ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
                          int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
-                         hipStream_t st);
+                         hipStream_t st, uint32_t cap = 0);
 // Compression and bucketing sort with the record IDs generated by the first
 // grouping pass.  Learned (mode 1): the bucket of each key is found while it
 // is compressed; CKEY_ERR_UNSUPPORTED when the keys do not allow that fused
@@ -221,7 +225,7 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
 ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bitmap_host, uint64_t *ck,
                                   uint32_t words, uint32_t nbits, uint32_t *rid, int mode,
                                   const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
-                                  hipStream_t st);
+                                  hipStream_t st, uint32_t cap = 0);
 size_t model_bytes(uint32_t b_log2);
 ckey_status model_init(void *model, uint64_t seed, hipStream_t st);
 ckey_status model_thresholds(void *model, uint32_t b_log2, const uint64_t *sorted, uint64_t m,

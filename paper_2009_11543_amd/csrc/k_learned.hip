@@ -1108,7 +1108,7 @@ LPtrs lptrs(void *ws, uint32_t words, uint64_t n, uint32_t B, LLayout &l) {
 // nothing yet and the row ids are 0..n-1 (generated by the first pass).
 ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid,
                           bool rid_identity, uint64_t n, const void *model, uint32_t b_log2, const LPtrs &q, const LLayout &l,
-                          uint32_t *flags, void *ws, hipStream_t st) {
+                          uint32_t *flags, void *ws, hipStream_t st, uint32_t cap) {
     const uint32_t B = 1u << b_log2;
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, st, q.hist, B, q.starts);
@@ -1118,15 +1118,16 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
     const uint64_t *T = thresholds_of(model);
     {
         const int pr = prof_begin(st, "bucket_sort");
-        if (n / B <= 1600) {  // small buckets: 2560-row capacity, 512 threads, 4 per CU
+        if (cap == 0) cap = n / B <= 1600 ? 1 : n / B <= 4400 ? 2 : 3;  // by the mean bucket size
+        if (cap == 1) {  // small buckets: 2560-row capacity, 512 threads, 4 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapSmall, 512> : words == 2 ? k_bucket_sort<2, kCapSmall, 512>
                     : words == 3 ? k_bucket_sort<3, kCapSmall, 512> : k_bucket_sort<0, kCapSmall, 512>;
             hipLaunchKernelGGL(kb, dim3(B), dim3(512), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
-        } else if (n / B <= 4400) {  // 5120-row capacity, 1024 threads, 2 per CU
+        } else if (cap == 2) {  // 5120-row capacity, 1024 threads, 2 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapLarge, 1024> : words == 2 ? k_bucket_sort<2, kCapLarge, 1024>
                     : words == 3 ? k_bucket_sort<3, kCapLarge, 1024> : k_bucket_sort<0, kCapLarge, 1024>;
             hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
-        } else {  // 10240-row capacity, 1 per CU (mean buckets beyond 4400 rows)
+        } else {  // 10240-row capacity, 1 per CU
             auto kb = words == 1 ? k_bucket_sort<1, kCapHuge, 1024> : words == 2 ? k_bucket_sort<2, kCapHuge, 1024>
                     : words == 3 ? k_bucket_sort<3, kCapHuge, 1024> : k_bucket_sort<0, kCapHuge, 1024>;
             hipLaunchKernelGGL(kb, dim3(B), dim3(1024), 0, st, ck, rid, n, words, q.starts, T, B, q.ovf, nullptr);
@@ -1134,9 +1135,9 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
         prof_end(st, pr);
     }
     CKEY_TRY(launch_status());
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    CKEY_HIP_TRY(hipStreamIsCapturing(st, &cap));
-    if (cap != hipStreamCaptureStatusNone) {
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    CKEY_HIP_TRY(hipStreamIsCapturing(st, &capture));
+    if (capture != hipStreamCaptureStatusNone) {
         // Captured: no host round trip.  The second chance walks the list on
         // the device; a bucket it still cannot sort (or a widespread
         // overflow) opens the gate of one radix sort of everything by (key,
@@ -1212,7 +1213,7 @@ ckey_status bucket_finish(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t
 
 ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t *rid, uint64_t n,
                          int mode, const void *model, uint32_t b_log2, uint32_t *flags, void *ws,
-                         hipStream_t st) {
+                         hipStream_t st, uint32_t cap) {
     if (n < 2) return CKEY_OK;
     const uint32_t B = 1u << b_log2;
     LLayout l;
@@ -1220,12 +1221,12 @@ ckey_status learned_sort(uint64_t *ck, uint32_t words, uint32_t nbits, uint32_t 
     CKEY_TRY(fill_u32(q.hist, B, 0, st));
     CKEY_TRY(fill_u32(q.ovf, 1, 0, st));
     CKEY_TRY(assign_launch(mode, ck, n, bucket_args(model, B, q.bid, nullptr, nullptr, q.hist), nullptr, st));
-    return bucket_finish(ck, words, nbits, rid, false, n, model, b_log2, q, l, flags, ws, st);
+    return bucket_finish(ck, words, nbits, rid, false, n, model, b_log2, q, l, flags, ws, st, cap);
 }
 
 ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *ck, uint32_t words,
                                   uint32_t nbits, uint32_t *rid, int mode, const void *model,
-                                  uint32_t b_log2, uint32_t *flags, void *ws, hipStream_t st) {
+                                  uint32_t b_log2, uint32_t *flags, void *ws, hipStream_t st, uint32_t cap) {
     const uint32_t B = 1u << b_log2;
     const uint64_t n = k.n;
     LLayout l;
@@ -1250,7 +1251,7 @@ ckey_status compress_learned_sort(const KeySrc &k, const uint8_t *bm, uint64_t *
         CKEY_TRY(s);
     }
     if (n < 2) return CKEY_OK;
-    return bucket_finish(ck, words, nbits, rid, true, n, model, b_log2, q, l, flags, ws, st);
+    return bucket_finish(ck, words, nbits, rid, true, n, model, b_log2, q, l, flags, ws, st, cap);
 }
 
 // ------------------------------------------------------------- model API --

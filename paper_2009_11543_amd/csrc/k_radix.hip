@@ -530,17 +530,33 @@ inline int pre_kpt(uint32_t words) {
 constexpr int kPreNT = 1024;  // threads of the load-first kernel
 // Passes over 1..8 words take the load-first kernel, wider keys the 256-thread one.
 inline bool use_pre(uint32_t words) { return words >= 1 && words <= 8; }
-inline uint64_t pass_tile(uint32_t words) {
-    return use_pre(words) ? uint64_t(kPreNT) * pre_kpt(words) : uint64_t(kTile);
+// half: the half tile (512 threads, the same rows per thread) -- half the
+// LDS, so two workgroups share a CU; an autotuning choice.
+inline uint64_t pass_tile(uint32_t words, bool half = false) {
+    return use_pre(words) ? uint64_t(half ? kPreNT / 2 : kPreNT) * pre_kpt(words) : uint64_t(kTile);
 }
 
 void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
                  const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
-                 hipStream_t st, const uint32_t *offs = nullptr) {
+                 hipStream_t st, const uint32_t *offs = nullptr, bool half = false) {
     const uint32_t nt = uint32_t(tiles);
-    const dim3 g = dim3(uint32_t(tiles)), b = dim3(use_pre(words) ? kPreNT : kWG);
+    const dim3 g = dim3(uint32_t(tiles)), b = dim3(use_pre(words) ? (half ? kPreNT / 2 : kPreNT) : kWG);
     if (!use_pre(words)) {
         hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
+        return;
+    }
+    if (half) {
+        constexpr int H = kPreNT / 2;
+        switch (words) {
+            case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 6, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 5: hipLaunchKernelGGL((k_onesweep_pre<5, 6, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 6: hipLaunchKernelGGL((k_onesweep_pre<6, 5, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            case 7: hipLaunchKernelGGL((k_onesweep_pre<7, 4, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+            default: hipLaunchKernelGGL((k_onesweep_pre<8, 4, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        }
         return;
     }
     switch (words) {
@@ -613,12 +629,12 @@ struct Layout {
     uint32_t npass;
 };
 
-Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
+Layout layout(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits, bool half) {
     PassList ps;
     make_passes(words, nbits, d, rid_bits, ps);
     Layout l{};
     l.npass = uint32_t(ps.size());
-    l.tiles = (n + pass_tile(words) - 1) / pass_tile(words);
+    l.tiles = (n + pass_tile(words, half) - 1) / pass_tile(words, half);
     size_t off = 0;
     l.alt_keys = off; off += align256(size_t(words) * n * 8);
     l.alt_rid = off;  off += align256(size_t(n) * 4);
@@ -780,8 +796,9 @@ ckey_status aux_sort(uint64_t *ck, uint32_t *rid, bool rid_identity, const uint1
     return CKEY_OK;
 }
 
-size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits) {
-    return layout(words, nbits, n, d, rid_bits).total;
+size_t radix_workspace(uint32_t words, uint32_t nbits, uint64_t n, uint32_t d, uint32_t rid_bits,
+                       bool half_tile) {
+    return layout(words, nbits, n, d, rid_bits, half_tile).total;
 }
 
 uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t d) {
@@ -795,11 +812,11 @@ uint32_t radix_pass_count(uint32_t words, uint32_t nbits, uint32_t d) {
 
 ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits, uint32_t *rid,
                        uint64_t n, uint32_t d, uint32_t rid_bits, uint32_t *flags, void *ws,
-                       hipStream_t st, bool skip_trivial, const uint32_t *gate) {
+                       hipStream_t st, bool skip_trivial, const uint32_t *gate, bool half_tile) {
     if (n < 2 || (nbits == 0 && rid_bits == 0)) return CKEY_OK;
     PassList ps;
     make_passes(words, nbits, d, rid_bits, ps);
-    const Layout l = layout(words, nbits, n, d, rid_bits);
+    const Layout l = layout(words, nbits, n, d, rid_bits, half_tile);
     uint8_t *w8 = static_cast<uint8_t *>(ws);
     uint64_t *alt = reinterpret_cast<uint64_t *>(w8 + l.alt_keys);
     uint32_t *alt_rid = reinterpret_cast<uint32_t *>(w8 + l.alt_rid);
@@ -859,7 +876,7 @@ ckey_status radix_sort(uint64_t *ck, uint64_t ld, uint32_t words, uint32_t nbits
         {
             const int pr_ = prof_begin(st, "onesweep");
             launch_pass(words, l.tiles, cur, n, ps[p], hist + p * kRadixMax, lookback, counters + p,
-                        flags, st);
+                        flags, st, nullptr, half_tile);
             prof_end(st, pr_);
         }
         CKEY_TRY(launch_status());

@@ -220,3 +220,21 @@ def test_sort_noalloc_checks_before_any_gpu_call(ck):
     assert call(ck._opts(), 1, 65, 100) == ck.CKEY_ERR_INVALID
     assert call(ck._opts(digit_bits=9), 1, 60, 100) == ck.CKEY_ERR_INVALID
     assert call(ck._opts(), 1, 60, 100) == ck.CKEY_ERR_INVALID      # null key and row-id pointers
+
+
+def test_tile_option_checked(ck):
+    """ckey_sort_opts.tile: radix 0..2, bucketing 0..3; anything else invalid
+    (checked by the workspace query, before any GPU call)."""
+    need = ctypes.c_size_t(0)
+    def query(**kw):
+        o = ck._opts(**kw)
+        return ck.lib().ckey_sort(None, 1, 60, None, 1000, ctypes.byref(o), None, ctypes.byref(need), None)
+    assert query(tile=2) == ck.CKEY_OK
+    assert query(tile=3) == ck.CKEY_ERR_INVALID
+    assert query(method=ck.CKEY_SORT_SPLITTER, bucket_log2=10, tile=3) == ck.CKEY_OK
+    assert query(method=ck.CKEY_SORT_SPLITTER, bucket_log2=10, tile=4) == ck.CKEY_ERR_INVALID
+    # the half pass tile doubles the radix sort's tile count, not its buffers
+    full = ck.ckey_sort_workspace(1, 60, 1 << 20, tile=1)
+    half = ck.ckey_sort_workspace(1, 60, 1 << 20, tile=2)
+    assert full <= half < full + (1 << 20)
+

@@ -222,3 +222,53 @@ def test_autotune(ck, table, tmp_path):
     assert choice2 == choice
     out = ck.ckey_rebuild_index([{"keys": keys, "bitmap": d, "opts": choice}])[0]
     np.testing.assert_array_equal(out["perm"].cpu().numpy().view(np.uint32), perm)
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_radix_pass_tiles_exact(ck, table, tile):
+    """Both radix pass tiles (1024 and 512 threads) give the oracle's order for
+    keys of 1, 2 and 6 words and several digit widths."""
+    tab, refs = table
+    for name in ("int32_a", "day_id", "title"):
+        perm, d = refs[name]
+        for db in (5, 8):
+            out = ck.ckey_rebuild_index([{"keys": ck.DeviceKeys.from_numpy(tab[name]), "bitmap": None,
+                                          "opts": dict(method=ck.CKEY_SORT_RADIX, digit_bits=db, tile=tile)}])[0]
+            np.testing.assert_array_equal(out["perm"].cpu().numpy().view(np.uint32), perm, err_msg=name)
+            np.testing.assert_array_equal(out["bitmap"].cpu().numpy(), d, err_msg=name)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_bucket_capacity_tiles_exact(ck, table, tile):
+    """Every in-LDS bucket capacity (2560, 5120, 10240 rows) gives the oracle's
+    order, with both bucketing methods and two bucket counts."""
+    from paper_2009_11543_amd import tune
+    tab, refs = table
+    for name in ("int64", "day_id"):
+        perm, d = refs[name]
+        spec = {"keys": ck.DeviceKeys.from_numpy(tab[name]), "bitmap": d}
+        prev = ck.ckey_rebuild_index([dict(spec, want_ckeys=True)])[0]
+        models = tune.fit_models(prev["ckeys"][0].contiguous(), (8, 10), steps=50, batch=1 << 12)
+        for b, model in models.items():
+            for meth in (ck.CKEY_SORT_SPLITTER, ck.CKEY_SORT_LEARNED):
+                out = ck.ckey_rebuild_index([dict(spec, opts=dict(method=meth, model=model, tile=tile))])[0]
+                np.testing.assert_array_equal(out["perm"].cpu().numpy().view(np.uint32), perm,
+                                              err_msg=f"{name} b={b} method={meth}")
+
+
+def test_autotune_bucket_counts_and_tiles(ck, table):
+    """The autotuner over digit widths, pass tiles, bucket counts and bucket
+    capacities: its choice rebuilds the index exactly."""
+    from paper_2009_11543_amd import tune
+    tab, refs = table
+    perm, d = refs["int64"]
+    keys = ck.DeviceKeys.from_numpy(tab["int64"])
+    prev = ck.ckey_rebuild_index([{"keys": keys, "bitmap": d, "want_ckeys": True}])[0]
+    models = tune.fit_models(prev["ckeys"][0].contiguous(), (8, 10), steps=50, batch=1 << 12)
+    choice, rec = tune.autotune(keys, d, models=models)
+    kinds = {(c["method"], c.get("tile"), c.get("bucket_log2")) for c in rec["candidates"]}
+    assert (ck.CKEY_SORT_RADIX, 2, None) in kinds and (ck.CKEY_SORT_SPLITTER, 1, 10) in kinds
+    assert len(rec["times_ms"]) == len(rec["candidates"]) and min(rec["times_ms"]) > 0
+    out = ck.ckey_rebuild_index([{"keys": keys, "bitmap": d, "opts": choice}])[0]
+    np.testing.assert_array_equal(out["perm"].cpu().numpy().view(np.uint32), perm)
+
