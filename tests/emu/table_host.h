@@ -1,9 +1,10 @@
 // Host emulation of the persistent table-rebuild kernel (k_table.hip), used by
 // a CPU test: the kernel source is compiled for the host with these
-// definitions in place of the HIP runtime.  A workgroup is 256 std::threads
-// with a std::barrier for __syncthreads and a 64-thread barrier per wave for
-// ballots; several workgroups run at once on shared host memory with real
-// atomics, so the work queue, the per-phase waits and the look-back run
+// definitions in place of the HIP runtime.  A workgroup is 256 threads with a
+// std::barrier for __syncthreads and a 64-thread barrier per wave for ballots
+// and DPP moves (the kernel's own scans, csrc/scan.h, run on a model of the
+// DPP forms they use); many workgroups run at once on shared host memory with
+// real atomics, so the work queue, the per-phase waits and the look-back run
 // concurrently.  Every LDS array of a workgroup is its own heap block, so an
 // address sanitizer build sees any out-of-bounds access to LDS or to the
 // global buffers.
@@ -16,8 +17,11 @@
 #include <barrier>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <thread>
 #include <vector>
+
+#include <pthread.h>
 
 #include "ckey.h"
 
@@ -37,7 +41,7 @@ struct EmuWG {
     std::barrier<> *bar;
     std::barrier<> *wbar[4];
     int ballot[4][64];
-    uint32_t scan[256];
+    int dpp[4][64];
 };
 extern thread_local EmuTid threadIdx;
 extern thread_local EmuWG *g_wg;
@@ -55,6 +59,34 @@ inline uint64_t __ballot(int pred) {
         if (g_wg->ballot[w][i]) m |= 1ull << i;
     g_wg->wbar[w]->arrive_and_wait();
     return m;
+}
+// DPP move of a wave (the forms the scans use): every lane publishes src,
+// then reads the lane its control word names.  row_shr:n (0x110 + n) reads
+// lane - n of the same 16-lane row; row_bcast:15 (0x142) reads lane 15 of the
+// previous row; row_bcast:31 (0x143) reads lane 31 (rows 2 and 3).  Rows
+// outside row_mask (and banks outside bank_mask) keep `old`; a source outside
+// the row reads 0 with bound_ctrl, else keeps `old`.
+inline int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    const int w = int(threadIdx.x) / 64, l = int(threadIdx.x) % 64, row = l / 16, in = l % 16;
+    g_wg->dpp[w][l] = src;
+    g_wg->wbar[w]->arrive_and_wait();
+    int res = old;
+    if (((row_mask >> row) & 1) && ((bank_mask >> (in / 4)) & 1)) {
+        int from = -1;
+        if ((ctrl & ~0xF) == 0x110) {
+            const int sh = ctrl & 0xF;
+            from = in >= sh ? l - sh : -1;
+        } else if (ctrl == 0x142) {
+            from = row > 0 ? 16 * row - 1 : -1;
+        } else if (ctrl == 0x143) {
+            from = row >= 2 ? 31 : -1;
+        } else {
+            abort();  // a form the emulation does not model
+        }
+        res = from >= 0 ? g_wg->dpp[w][from] : (bound_ctrl ? 0 : old);
+    }
+    g_wg->wbar[w]->arrive_and_wait();
+    return res;
 }
 inline int __popc(uint32_t v) { return __builtin_popcount(v); }
 inline int __popcll(uint64_t v) { return __builtin_popcountll(v); }
@@ -113,19 +145,6 @@ inline uint32_t key_word_aligned(const uint8_t *p, uint32_t j, uint32_t len) {
     return v;
 }
 inline uint32_t bitmap_word_bit(uint32_t p) { return 1u << (8 * ((p >> 3) & 3) + (7 - (p & 7))); }
-inline uint32_t block_excl_scan(uint32_t v, uint32_t *, uint32_t &total) {
-    uint32_t *vals = g_wg->scan;
-    vals[threadIdx.x] = v;
-    __syncthreads();
-    uint32_t ex = 0, tot = 0;
-    for (unsigned i = 0; i < 256; ++i) {
-        if (i < threadIdx.x) ex += vals[i];
-        tot += vals[i];
-    }
-    __syncthreads();
-    total = tot;
-    return ex;
-}
 inline ckey_status fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t) {
     for (uint64_t i = 0; i < n; ++i) p[i] = v;
     return CKEY_OK;
@@ -145,6 +164,9 @@ struct TableIndex {
 ckey_status table_fused_plan(const TableIndex *ti, uint32_t count, void *ws, size_t *need, hipStream_t st);
 }  // namespace ckey
 
+// The kernel's own wave and workgroup scans (DPP moves modelled above).
+#include "scan.h"
+
 inline int hipGetDevice(int *d) {
     *d = 0;
     return 0;
@@ -157,7 +179,15 @@ template <class F> inline int hipOccupancyMaxActiveBlocksPerMultiprocessor(int *
     *v = 1;
     return 0;
 }
-// g_nwg concurrent workgroups of 256 threads, whatever the requested grid.
+// g_nwg concurrent workgroups of 256 threads, whatever the requested grid;
+// each thread a pthread with a small stack, so that many workgroups fit.
+struct EmuThreadArg {
+    std::function<void()> body;
+};
+inline void *emu_thread_main(void *p) {
+    static_cast<EmuThreadArg *>(p)->body();
+    return nullptr;
+}
 #define hipLaunchKernelGGL(K, G, B, S, ST, ...)                                                   \
     do {                                                                                           \
         std::vector<EmuWG *> wgs_;                                                                 \
@@ -171,15 +201,24 @@ template <class F> inline int hipOccupancyMaxActiveBlocksPerMultiprocessor(int *
             e_->lds[3] = malloc(16);                                                               \
             wgs_.push_back(e_);                                                                    \
         }                                                                                          \
-        std::vector<std::thread> th_;                                                              \
+        std::vector<EmuThreadArg> args_(size_t(g_nwg) * 256);                                     \
+        std::vector<pthread_t> th_(args_.size());                                                  \
+        pthread_attr_t at_;                                                                        \
+        pthread_attr_init(&at_);                                                                   \
+        pthread_attr_setstacksize(&at_, 1u << 20);                                                 \
         for (int w_ = 0; w_ < g_nwg; ++w_)                                                         \
-            for (unsigned t_ = 0; t_ < 256; ++t_)                                                  \
-                th_.emplace_back([&, t_, w_]() {                                                   \
+            for (unsigned t_ = 0; t_ < 256; ++t_) {                                                \
+                EmuThreadArg &a_ = args_[size_t(w_) * 256 + t_];                                   \
+                a_.body = [&, t_, w_]() {                                                          \
                     threadIdx.x = t_;                                                              \
                     g_wg = wgs_[w_];                                                               \
                     K(__VA_ARGS__);                                                                \
-                });                                                                                \
-        for (auto &h_ : th_) h_.join();                                                            \
+                };                                                                                 \
+                if (pthread_create(&th_[size_t(w_) * 256 + t_], &at_, emu_thread_main, &a_) != 0) \
+                    abort();                                                                       \
+            }                                                                                      \
+        for (pthread_t &h_ : th_) pthread_join(h_, nullptr);                                       \
+        pthread_attr_destroy(&at_);                                                                \
         for (EmuWG *e_ : wgs_) {                                                                   \
             for (int q_ = 0; q_ < 4; ++q_) { free(e_->lds[q_]); delete e_->wbar[q_]; }             \
             delete e_->bar;                                                                        \

@@ -51,8 +51,9 @@ def emu(tmp_path_factory):
     open(d / "k_table.cpp", "w").write(src)
     exe = d / "emu"
     r = subprocess.run([gxx, "-std=c++20", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-                        "-I", EMU, "-I", os.path.join(ROOT, "include"), "-o", str(exe),
-                        os.path.join(EMU, "table_main.cpp"), str(d / "k_table.cpp"), "-lpthread"],
+                        "-I", EMU, "-I", os.path.join(ROOT, "paper_2009_11543_amd", "csrc"),
+                        "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                        os.path.join(EMU, "table_main.cpp"), str(d / "k_table.cpp"), "-pthread"],
                        capture_output=True, text=True)
     if r.returncode != 0 and "barrier" in r.stderr and "No such file" in r.stderr:
         pytest.skip("no C++20 <barrier>")
@@ -96,7 +97,8 @@ def run_table(emu, tmp_path, cases, nwg):
 
 @pytest.mark.parametrize("nwg", [1, 2])
 def test_table_emulated(emu, tmp_path, nwg):
-    n = (1 << 12) + 777  # ragged: two pass tiles
+    # ragged: two pass tiles (one workgroup alone drains every item: a smaller table)
+    n = (1 << 12) + 777 if nwg > 1 else 4096 + 77
     tab = datagen.table_indexes(n, seed=5)
     cases = []
     for x, (name, rows) in enumerate(tab.items()):
@@ -138,3 +140,17 @@ def test_table_emulated_gpu_test_table(emu, tmp_path):
         k = O.Keys(rows)
         cases.append((k, None if x % 2 == 0 else O.dbits(k, O.full_sort(k))[0], 8))
     run_table(emu, tmp_path, cases, 6)
+
+
+def test_table_emulated_many_workgroups(emu, tmp_path):
+    """The GPU test's table with 48 workgroups at once (12288 threads): more
+    workgroups than items in several phases, so most wait on earlier items
+    while the look-back chains run in parallel."""
+    n = (1 << 13) + 777
+    tab = datagen.table_indexes(n, seed=5)
+    cases = []
+    for x, (name, rows) in enumerate(tab.items()):
+        k = O.Keys(rows)
+        cases.append((k, None if x % 2 == 0 else O.dbits(k, O.full_sort(k))[0], 8 if x < 6 else 4))
+    run_table(emu, tmp_path, cases, 48)
+
