@@ -247,8 +247,13 @@ __device__ __forceinline__ void splitter_search_n(const BucketArgs &a, const uin
 }
 
 // The same for a 1-in-S sample of T in LDS (S > 1, sorted order): a
-// fixed-depth search of the sample, then of the S thresholds of T (global
-// memory) below the next sample, the keys' steps interleaved.
+// fixed-depth search of the sample finds the run of S thresholds of T that
+// holds the answer; a linear interpolation between the two samples around
+// the key guesses the bucket, two reads of T (global memory, issued together)
+// test the guess and its right neighbour, and a binary search finishes
+// whatever is left of the run.  Exact whatever the data; for smooth data the
+// guess is right or one off, so most keys read T in one round instead of
+// log2(S) dependent ones.
 template <int N>
 __device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, const uint32_t *s,
                                                           const uint64_t *x, uint32_t *b) {
@@ -261,13 +266,49 @@ __device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, c
         for (int q = 0; q < N; ++q)
             if (ts[b[q] + step] <= x[q]) b[q] += step;
     }
+    // The answer lies in [lo, hi): T[lo] = ts[i] <= x, and T[hi] > x (hi =
+    // (i + 1) S is the next sample, or hi = B).
+    uint32_t lo[N], hi[N], g[N];
+    uint64_t tg[N], tn[N];
 #pragma unroll
-    for (int q = 0; q < N; ++q) b[q] *= a.S;
-    for (uint32_t step = a.S >> 1; step >= 1; step >>= 1) {
-#pragma unroll
-        for (int q = 0; q < N; ++q)
-            if (a.T[b[q] + step] <= x[q]) b[q] += step;  // b[q] + step < B
+    for (int q = 0; q < N; ++q) {
+        const uint32_t i = b[q];
+        const uint64_t t0 = ts[i], t1 = i + 1 < m ? ts[i + 1] : ~0ull;
+        lo[q] = i * a.S;
+        hi[q] = lo[q] + a.S;
+        const uint64_t span = t1 - t0;  // > 0 unless the run ends at the top of the range
+        const uint32_t k = span ? uint32_t(float(x[q] - t0) / float(span) * float(a.S)) : 0u;
+        g[q] = lo[q] + min(k, a.S - 1u);
+        tg[q] = a.T[g[q]];
+        tn[q] = g[q] + 1 < hi[q] ? a.T[g[q] + 1] : ~0ull;
     }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        if (tg[q] <= x[q]) {
+            lo[q] = g[q];
+            if (g[q] + 1 < hi[q]) {
+                if (tn[q] <= x[q]) lo[q] = g[q] + 1;
+                else hi[q] = g[q] + 1;
+            }
+        } else {
+            hi[q] = g[q];  // g > lo here, as T[lo] <= x
+        }
+    }
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            if (hi[q] - lo[q] > 1) {
+                const uint32_t mid = (lo[q] + hi[q]) >> 1;
+                if (a.T[mid] <= x[q]) lo[q] = mid;
+                else hi[q] = mid;
+                more = true;
+            }
+        }
+        if (!more) break;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] = lo[q];
 }
 
 template <int AMODE>
