@@ -140,6 +140,92 @@ __device__ __forceinline__ uint32_t correct_bucket(const uint64_t *__restrict__ 
     return lo;
 }
 
+// Exact buckets of N keys from guesses g, T in global memory (the learned
+// method beyond 2^14 buckets): the guess and its right neighbour are read
+// together; a miss gallops outward from the guess with doubling steps until
+// the answer is bracketed, then halves the bracket.  Each round issues every
+// key's read before any is used, so the reads overlap.  b[q] = the largest b
+// with T[b] <= x[q] (T sorted, T[0] = 0), as correct_bucket returns.
+template <int N>
+__device__ __forceinline__ void correct_bucket_n(const uint64_t *__restrict__ T, uint32_t B, const uint64_t *x,
+                                                 const uint32_t *g, uint32_t *b) {
+    uint32_t lo[N], hi[N], step[N];  // T[lo] <= x; hi == B or T[hi] > x once bracketed
+    int dir[N];                      // +1 galloping up, -1 down, 0 bracketed
+    uint64_t t0[N], t1[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        t0[q] = T[g[q]];
+        t1[q] = g[q] + 1 < B ? T[g[q] + 1] : ~0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        step[q] = 1;
+        if (t0[q] <= x[q]) {
+            lo[q] = g[q];
+            if (g[q] + 1 >= B || t1[q] > x[q]) {
+                hi[q] = g[q] + 1;
+                dir[q] = 0;
+            } else {
+                lo[q] = g[q] + 1;
+                hi[q] = B;
+                dir[q] = 1;
+            }
+        } else {
+            lo[q] = 0;
+            hi[q] = g[q];
+            dir[q] = -1;
+        }
+    }
+    for (;;) {  // gallop
+        bool more = false;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            if (dir[q] > 0) {
+                const uint32_t j = lo[q] + step[q];
+                if (j >= B) {
+                    dir[q] = 0;
+                } else if (T[j] > x[q]) {
+                    hi[q] = j;
+                    dir[q] = 0;
+                } else {
+                    lo[q] = j;
+                    step[q] <<= 1;
+                }
+            } else if (dir[q] < 0) {
+                if (hi[q] <= step[q]) {
+                    dir[q] = 0;  // lo stays 0: T[0] = 0 <= x
+                } else {
+                    const uint32_t j = hi[q] - step[q];
+                    if (T[j] <= x[q]) {
+                        lo[q] = j;
+                        dir[q] = 0;
+                    } else {
+                        hi[q] = j;
+                        step[q] <<= 1;
+                    }
+                }
+            }
+            more |= dir[q] != 0;
+        }
+        if (!more) break;
+    }
+    for (;;) {  // halve the brackets
+        bool more = false;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            if (hi[q] - lo[q] > 1) {
+                const uint32_t mid = lo[q] + (hi[q] - lo[q]) / 2;
+                if (T[mid] <= x[q]) lo[q] = mid;
+                else hi[q] = mid;
+                more = true;
+            }
+        }
+        if (!more) break;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] = lo[q];
+}
+
 // Exact bucket from a guess g without per-lane loops of varying length (so a
 // wave never waits on its slowest lane): the 2W buckets around g are searched
 // to a fixed depth when they hold x (checked with one read at each end), else

@@ -339,6 +339,15 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
                     const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q]);
                     if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
                 }
+            } else if (AMODE == 1) {  // the keys' networks together, then T in memory searched from the guesses
+                uint32_t g[KPI], b[KPI];
+                predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
+                correct_bucket_n<KPI>(ba.T, ba.B, w0, g, b);
+#pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
+                }
             } else if (AMODE == 0 && ba.S > 1) {  // the keys' sampled searches interleaved
                 uint32_t b[KPI];
                 splitter_search_sampled_n<KPI>(ba, s_dyn, w0, b);

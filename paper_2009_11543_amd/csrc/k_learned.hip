@@ -242,7 +242,26 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
                 if (r < i1) bucket_record<MODE>(ba, s_dyn, b, r);
             }
         }
-    } else {  // with statistics (probes, guess error) or a sampled threshold table
+    } else if (MODE == 1 && !stats) {
+        // Learned beyond 2^14 buckets (T in memory): four keys' networks at
+        // once, then their galloping searches of T from the guesses together.
+        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
+            uint64_t x[4];
+            uint32_t g[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                x[q] = r < i1 ? w0[r] : 0ull;
+            }
+            predict_bucket_n<4>(ba.p, x, ba.B, g);
+            correct_bucket_n<4>(ba.T, ba.B, x, g, b);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
+            }
+        }
+    } else {  // with statistics (probes, guess error)
         for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
             (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
     }

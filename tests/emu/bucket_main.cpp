@@ -44,7 +44,7 @@ int main(int argc, char **argv) {
     std::vector<uint32_t> s1(bucket_lds_bytes(a, 1) / 4, 0xDEADBEEFu);
     bucket_lds_init<0>(a, s0.data());
     bucket_lds_init<1>(a, s1.data());
-    std::vector<uint32_t> one(nx), many(nx), lcorr(nx), lwin(nx), pr1(nx), pr4(nx);
+    std::vector<uint32_t> one(nx), many(nx), lcorr(nx), lwin(nx), lmany(nx), pr1(nx), pr4(nx);
     for (size_t i = 0; i < nx; ++i) {
         uint32_t probes = 0, guess = 0;
         one[i] = bucket_of<0>(a, s0.data(), x[i], probes, guess);
@@ -64,6 +64,16 @@ int main(int argc, char **argv) {
             splitter_search_sampled_n<8>(a, s0.data(), xs, b);
         for (int q = 0; q < 8 && i + q < nx; ++q) many[i + q] = b[q];
     }
+    for (size_t i = 0; i < nx; i += 4) {  // the learned correction of four keys at once, T in memory
+        uint64_t xs[4];
+        uint32_t gs[4], b[4];
+        for (int q = 0; q < 4; ++q) {
+            xs[q] = i + q < nx ? x[i + q] : 0;
+            gs[q] = i + q < nx ? g[i + q] : 0;
+        }
+        correct_bucket_n<4>(T.data(), B, xs, gs, b);
+        for (int q = 0; q < 4 && i + q < nx; ++q) lmany[i + q] = b[q];
+    }
     for (size_t i = 0; i < nx; i += 4) {
         uint64_t xs[4];
         uint32_t gq[4];
@@ -76,6 +86,7 @@ int main(int argc, char **argv) {
     wr(d + "/many.bin", many);
     wr(d + "/lcorr.bin", lcorr);
     wr(d + "/lwin.bin", lwin);
+    wr(d + "/lmany.bin", lmany);
     wr(d + "/pr1.bin", pr1);
     wr(d + "/pr4.bin", pr4);
     wr(d + "/hist.bin", hist);

@@ -9,8 +9,9 @@ table T (T[0] = 0): the largest b with T[b] <= x.
   * splitter, a 1-in-S sample in LDS then T in memory: one key at a time and
     eight interleaved (S = 16, 32 as chosen beyond 2^14 buckets, and a forced
     S at a small B);
-  * learned: the outward exponential search and the fixed-depth window search
-    from arbitrary guesses (near, far, at either end);
+  * learned: the outward exponential search, the fixed-depth window search
+    and the four-key interleaved galloping search of T in memory, from
+    arbitrary guesses (near, far, at either end);
   * the network's guess for one key and for four at once agree exactly;
   * the packed 16-bit LDS histogram flushed to the global one equals the
     bucket counts.
@@ -84,8 +85,8 @@ def run(emu, tmp_path, B, S, kind, seed):
     r = subprocess.run([str(emu), str(tmp_path)], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, r.stderr[-4000:]
     out = {k: np.fromfile(tmp_path / f"{k}.bin", np.uint32)
-           for k in ("one", "many", "lcorr", "lwin", "pr1", "pr4", "hist")}
-    for k in ("one", "many", "lcorr", "lwin"):
+           for k in ("one", "many", "lcorr", "lwin", "lmany", "pr1", "pr4", "hist")}
+    for k in ("one", "many", "lcorr", "lwin", "lmany"):
         np.testing.assert_array_equal(out[k], exp, err_msg=f"{k} B={B} S={S} {kind}")
     np.testing.assert_array_equal(out["pr1"], out["pr4"])
     assert int(out["pr1"].max()) < B

@@ -114,7 +114,7 @@ def test_uniform32_2p28(ck):
     import torch
     rows = datagen.uniform_keys(1 << 28, seed=1)
     keys = ck.DeviceKeys(torch.from_numpy(rows).cuda())
-    run_config(ck, keys, rows, datagen.uniform_keys(1 << 22, seed=2), 16, ["splitter"])
+    run_config(ck, keys, rows, datagen.uniform_keys(1 << 22, seed=2), 16, ["splitter", "learned"])
 
 
 def test_cluster32_2p28(ck):
