@@ -424,11 +424,12 @@ __device__ __forceinline__ void bucket_assign_one(const BucketArgs &a, uint32_t 
 }
 
 template <int AMODE>
-__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *s) {
+__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *s, bool clear = false) {
     if (!a.hist) return;
-    const uint32_t *h = bucket_counters<AMODE>(a, s);
+    uint32_t *h = bucket_counters<AMODE>(a, s);
     for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
         const uint32_t v = h[t];
+        if (clear) h[t] = 0u;
         if (v & 0xFFFFu) atomicAdd(&a.hist[2 * t], v & 0xFFFFu);
         if (v >> 16) atomicAdd(&a.hist[2 * t + 1], v >> 16);
     }

@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 #include <set>
+#include <tuple>
 #include <utility>
 
 #include "../../include/ckey.h"
@@ -96,6 +98,26 @@ inline void raise_lds_limit(const void *fn) {
         const size_t stat = hipFuncGetAttributes(&at, fn) == hipSuccess ? at.sharedSizeBytes : 0;
         (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(160 * 1024 - stat));
     }
+}
+
+// Workgroups of `fn` that are resident on the current device at once: CUs x
+// workgroups per CU at `threads` threads and `lds` bytes of dynamic LDS (at
+// least 1).  Remembered per (device, kernel, threads, lds).
+inline uint32_t resident_grid(const void *fn, int threads, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, int, size_t>, uint32_t> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    const auto key = std::make_tuple(dev, fn, threads, lds);
+    const auto it = done.find(key);
+    if (it != done.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) per_cu = 1;
+    const uint32_t grid = uint32_t(cus > 0 ? cus : 1) * uint32_t(per_cu > 0 ? per_cu : 1);
+    done.emplace(key, grid);
+    return grid;
 }
 
 // Event timing around a launch when profiling is enabled (profiler.hip).

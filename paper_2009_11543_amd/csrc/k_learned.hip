@@ -41,8 +41,6 @@ constexpr int kCapLarge = 5120;  // max bucket size sorted in LDS (large-bucket 
 constexpr int kCapSmall = 2560;  // (small-bucket kernel, for <= 1600 rows per bucket on average)
 constexpr int kCapHuge = 10240;  // second chance for buckets over those (one workgroup per CU)
 constexpr int kRunCap = 32;      // max run of equal first words sorted in place
-constexpr int kAssignWG = 1024;
-constexpr uint32_t kKeysPerAssignWG = 65535;  // keeps the packed 16-bit LDS counters exact
 
 inline float *params_of(void *model) { return reinterpret_cast<float *>(static_cast<uint8_t *>(model) + kOffParams); }
 inline const float *params_of(const void *model) {
@@ -192,6 +190,10 @@ __global__ __launch_bounds__(512) void k_mlp_reduce(const float *__restrict__ pa
 // ------------------------------------------------------- bucket assignment --
 
 // Stand-alone assignment of first words w0[0..n) (MODE 0: splitter, 1: learned).
+// Persistent: a workgroup loads the thresholds into LDS once and takes the
+// chunks of kBucketKeysPerWG keys blockIdx.x, + gridDim.x, ...; after each
+// chunk its packed 16-bit bucket counters (exact up to 65535) are added to the
+// global histogram and cleared.
 template <int MODE>
 __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__restrict__ w0,
                                                              uint64_t n, BucketArgs ba,
@@ -199,74 +201,77 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     extern __shared__ uint32_t s_dyn[];
     bucket_lds_init<MODE>(ba, s_dyn);
     __syncthreads();
-    const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
-    const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
     uint32_t probes = 0, err = 0;
-    if (MODE == 0 && !stats) {
-        // Splitter: eight keys per thread, all their loads first, then their
-        // searches interleaved (every threshold in LDS, or a sample of them).
-        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 8 * kBucketWG) {
-            uint64_t x[8];
-            uint32_t b[8];
+    for (uint64_t c = blockIdx.x; c * kBucketKeysPerWG < n; c += gridDim.x) {
+        const uint64_t i0 = c * kBucketKeysPerWG;
+        const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
+        if (MODE == 0 && !stats) {
+            // Splitter: eight keys per thread, all their loads first, then their
+            // searches interleaved (every threshold in LDS, or a sample of them).
+            for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 8 * kBucketWG) {
+                uint64_t x[8];
+                uint32_t b[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                x[q] = r < i1 ? w0[r] : 0ull;
-            }
-            if (ba.S == 1)
-                splitter_search_n<8>(ba, s_dyn, x, b);
-            else
-                splitter_search_sampled_n<8>(ba, s_dyn, x, b);
+                for (int q = 0; q < 8; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    x[q] = r < i1 ? w0[r] : 0ull;
+                }
+                if (ba.S == 1)
+                    splitter_search_n<8>(ba, s_dyn, x, b);
+                else
+                    splitter_search_sampled_n<8>(ba, s_dyn, x, b);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
+                for (int q = 0; q < 8; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
+                }
             }
+        } else if (MODE == 1 && ba.S == 1 && !stats) {
+            // Learned with every threshold in LDS: four keys' networks at once,
+            // then the fixed-depth search around each guess.
+            for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
+                uint64_t x[4];
+                uint32_t g[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    x[q] = r < i1 ? w0[r] : 0ull;
+                }
+                predict_bucket_n<4>(ba.p, x, ba.B, g);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, x[q], g[q]);
+                    if (r < i1) bucket_record<MODE>(ba, s_dyn, b, r);
+                }
+            }
+        } else if (MODE == 1 && !stats) {
+            // Learned beyond 2^14 buckets (T in memory): four keys' networks at
+            // once, then their galloping searches of T from the guesses together.
+            for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
+                uint64_t x[4];
+                uint32_t g[4], b[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    x[q] = r < i1 ? w0[r] : 0ull;
+                }
+                predict_bucket_n<4>(ba.p, x, ba.B, g);
+                correct_bucket_n<4>(ba.T, ba.B, x, g, b);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t r = b0 + uint64_t(q) * kBucketWG;
+                    if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
+                }
+            }
+        } else {  // with statistics (probes, guess error)
+            for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
+                (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
         }
-    } else if (MODE == 1 && ba.S == 1 && !stats) {
-        // Learned with every threshold in LDS: four keys' networks at once,
-        // then the fixed-depth search around each guess.
-        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
-            uint64_t x[4];
-            uint32_t g[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                x[q] = r < i1 ? w0[r] : 0ull;
-            }
-            predict_bucket_n<4>(ba.p, x, ba.B, g);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, x[q], g[q]);
-                if (r < i1) bucket_record<MODE>(ba, s_dyn, b, r);
-            }
-        }
-    } else if (MODE == 1 && !stats) {
-        // Learned beyond 2^14 buckets (T in memory): four keys' networks at
-        // once, then their galloping searches of T from the guesses together.
-        for (uint64_t b0 = i0 + threadIdx.x; b0 < i1; b0 += 4 * kBucketWG) {
-            uint64_t x[4];
-            uint32_t g[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                x[q] = r < i1 ? w0[r] : 0ull;
-            }
-            predict_bucket_n<4>(ba.p, x, ba.B, g);
-            correct_bucket_n<4>(ba.T, ba.B, x, g, b);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t r = b0 + uint64_t(q) * kBucketWG;
-                if (r < i1) bucket_record<MODE>(ba, s_dyn, b[q], r);
-            }
-        }
-    } else {  // with statistics (probes, guess error)
-        for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG)
-            (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
+        __syncthreads();
+        bucket_lds_flush<MODE>(ba, s_dyn, true);
+        __syncthreads();  // counters cleared before the next chunk's records
     }
-    __syncthreads();
-    bucket_lds_flush<MODE>(ba, s_dyn);
     if (stats) {
         unsigned long long a = probes, e = err;
 #pragma unroll
@@ -1078,9 +1083,12 @@ ckey_status assign_launch(int mode, const uint64_t *w0, uint64_t n, const Bucket
                           unsigned long long *stats, hipStream_t st) {
     if (n == 0) return CKEY_OK;
     const size_t lds = bucket_lds_bytes(ba, mode);
-    const uint64_t blocks = (n + kBucketKeysPerWG - 1) / kBucketKeysPerWG;
-    raise_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<0>));
-    raise_lds_limit(reinterpret_cast<const void *>(k_bucket_assign<1>));
+    const void *fn = mode ? reinterpret_cast<const void *>(k_bucket_assign<1>)
+                          : reinterpret_cast<const void *>(k_bucket_assign<0>);
+    raise_lds_limit(fn);
+    // One pass of workgroups resident at once (each loads the thresholds once).
+    const uint64_t blocks = std::min<uint64_t>((n + kBucketKeysPerWG - 1) / kBucketKeysPerWG,
+                                               resident_grid(fn, kBucketWG, lds));
     const int pr = prof_begin(st, mode ? "assign_learned" : "assign_splitter");
     if (mode)
         hipLaunchKernelGGL(k_bucket_assign<1>, dim3(uint32_t(blocks)), dim3(kBucketWG), lds, st, w0, n, ba, stats);
