@@ -24,7 +24,7 @@ struct BucketArgs {
     uint16_t *bid;         // bucket ids (u16) or null
     uint32_t *bid32;       // bucket ids (u32) or null
     uint32_t *pred;        // network guesses or null (learned)
-    uint32_t *hist;        // global bucket histogram (added to) or null
+    uint32_t *hist;        // global bucket histogram (added to; 8-byte aligned) or null
 };
 
 // Splitter sample stride.  S == 1 means every threshold is held in LDS
@@ -430,8 +430,11 @@ __device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *
     for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
         const uint32_t v = h[t];
         if (clear) h[t] = 0u;
-        if (v & 0xFFFFu) atomicAdd(&a.hist[2 * t], v & 0xFFFFu);
-        if (v >> 16) atomicAdd(&a.hist[2 * t + 1], v >> 16);
+        // Buckets 2t and 2t+1 in one 64-bit add (hist is 8-byte aligned): the
+        // low count cannot carry into the high one, as every count is < 2^32.
+        if (v)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + 2 * t),
+                      (static_cast<unsigned long long>(v >> 16) << 32) | (v & 0xFFFFu));
     }
 }
 

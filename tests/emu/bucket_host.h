@@ -25,6 +25,11 @@ inline uint32_t atomicAdd(uint32_t *p, uint32_t v) {
     *p = o + v;
     return o;
 }
+inline unsigned long long atomicAdd(unsigned long long *p, unsigned long long v) {
+    const unsigned long long o = *p;
+    *p = o + v;
+    return o;
+}
 template <class T> inline T min(T a, T b) { return a < b ? a : b; }
 
 namespace ckey {
