@@ -76,19 +76,32 @@ struct HistArgs {
 // device word says so: every kernel of it returns at once on a closed gate.
 __device__ __forceinline__ bool gate_closed(const uint32_t *gate) { return gate && *gate == 0u; }
 
+// Histograms of up to 8 digit passes of one key word: eight words per thread
+// per round, all loaded before any is counted (eight loads in flight per
+// thread instead of one), counted with LDS atomics, then added to `hist`.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_hist(const T *__restrict__ word, uint64_t n, HistArgs ha,
                                               uint32_t *__restrict__ hist) {
+    constexpr int U = 8;
     __shared__ uint32_t s_h[8][kRadixMax];
     if (gate_closed(ha.gate)) return;
     for (int t = threadIdx.x; t < 8 * kRadixMax; t += kWG) (&s_h[0][0])[t] = 0;
     __syncthreads();
-    const uint64_t step = uint64_t(gridDim.x) * kWG;
-    for (uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x; i < n; i += step) {
-        const uint64_t x = word[i];
-        for (uint32_t p = 0; p < ha.npass; ++p) {
-            const uint32_t d = uint32_t(x >> ha.shift[p]) & ((1u << ha.bits[p]) - 1u);
-            atomicAdd(&s_h[p][d], 1u);
+    const uint64_t step = uint64_t(gridDim.x) * kWG * U;
+    for (uint64_t i0 = uint64_t(blockIdx.x) * kWG * U + threadIdx.x; i0 < n; i0 += step) {
+        uint64_t x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + uint64_t(u) * kWG;
+            x[u] = i < n ? uint64_t(word[i]) : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i0 + uint64_t(u) * kWG >= n) break;
+            for (uint32_t p = 0; p < ha.npass; ++p) {
+                const uint32_t d = uint32_t(x[u] >> ha.shift[p]) & ((1u << ha.bits[p]) - 1u);
+                atomicAdd(&s_h[p][d], 1u);
+            }
         }
     }
     __syncthreads();
