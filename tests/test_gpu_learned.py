@@ -426,6 +426,36 @@ def test_bucket_counts_many_buckets(ck, bucket_log2):
     np.testing.assert_array_equal(ck.as_u64(ckd), w[:, order])
 
 
+def test_bucket_counts_beyond_16_bits_per_workgroup(ck):
+    """2^25 one-word keys, 60 % of them one value: every assigning workgroup
+    walks two chunks of 65535 keys and counts more than 65535 keys into the
+    hot bucket in all, so its packed 16-bit counters are exact only when
+    flushed after each chunk.  The bucket starts decide every destination:
+    the permutation and keys equal a stable sort, and the hot bucket takes
+    the radix fallback (CKEY_FLAG_BUCKET_OVERFLOW)."""
+    import torch
+    n = 1 << 25
+    rng = np.random.default_rng(25)
+    w = rng.integers(0, 1 << 62, n, dtype=np.int64)
+    hot = rng.random(n) < 0.6
+    w[hot] = 0x2D9B_5A1F_0C3E_7711
+    B = 1 << 14
+    sample = np.sort(w[rng.choice(n, 1 << 20, replace=False)])
+    T = sample[(np.arange(B, dtype=np.int64) * sample.size) // B]
+    T[0] = 0
+    model = ck.CdfModel(bucket_log2=14, seed=1)
+    model.thresholds().copy_(torch.from_numpy(T).cuda())
+    ckd = torch.from_numpy(w).cuda().reshape(1, n).contiguous()
+    rid = torch.arange(n, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ck.ckey_sort(ckd, 64, rid, method=ck.CKEY_SORT_SPLITTER, model=model, flags=flags)
+    order = np.argsort(w, kind="stable")
+    np.testing.assert_array_equal(rid.cpu().numpy(), order.astype(np.int32))
+    np.testing.assert_array_equal(ckd[0].cpu().numpy(), w[order])
+    f = int(flags.item())
+    assert f & ck.CKEY_FLAG_BUCKET_OVERFLOW and not f & ck.CKEY_FLAG_SPIN_LIMIT
+
+
 @pytest.mark.parametrize("words", [1, 3])
 @pytest.mark.parametrize("too_big", [False, True])
 def test_bucket_second_chance(ck, words, too_big):
