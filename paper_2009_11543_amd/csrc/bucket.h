@@ -27,6 +27,17 @@ struct BucketArgs {
     uint32_t *hist;        // global bucket histogram (added to; 8-byte aligned) or null
 };
 
+// T[g] and T[g + 1] (g + 1 < B) in one 16-byte load: the pair lies in one
+// 128-byte cache line unless T[g] is a line's last word (1 in 16), so a
+// random pair costs one memory request instead of two.  The load needs only
+// the 8-byte alignment of T.
+struct alignas(8) TPair {
+    uint64_t lo, hi;
+};
+__device__ __forceinline__ TPair load_tpair(const uint64_t *__restrict__ T, uint32_t g) {
+    return *reinterpret_cast<const TPair *>(T + g);
+}
+
 // Splitter sample stride.  S == 1 means every threshold is held in LDS
 // (B <= 2^14: 128 KB) and the search runs in LDS alone.
 inline uint32_t splitter_stride(uint32_t B) {
@@ -154,8 +165,14 @@ __device__ __forceinline__ void correct_bucket_n(const uint64_t *__restrict__ T,
     uint64_t t0[N], t1[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-        t0[q] = T[g[q]];
-        t1[q] = g[q] + 1 < B ? T[g[q] + 1] : ~0ull;
+        if (g[q] + 1 < B) {
+            const TPair t = load_tpair(T, g[q]);
+            t0[q] = t.lo;
+            t1[q] = t.hi;
+        } else {
+            t0[q] = T[g[q]];
+            t1[q] = ~0ull;
+        }
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -365,8 +382,14 @@ __device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, c
         const uint64_t span = t1 - t0;  // > 0 unless the run ends at the top of the range
         const uint32_t k = span ? uint32_t(float(x[q] - t0) / float(span) * float(a.S)) : 0u;
         g[q] = lo[q] + min(k, a.S - 1u);
-        tg[q] = a.T[g[q]];
-        tn[q] = g[q] + 1 < hi[q] ? a.T[g[q] + 1] : ~0ull;
+        if (g[q] + 1 < a.B) {  // the neighbour only counts inside the run
+            const TPair t = load_tpair(a.T, g[q]);
+            tg[q] = t.lo;
+            tn[q] = g[q] + 1 < hi[q] ? t.hi : ~0ull;
+        } else {
+            tg[q] = a.T[g[q]];
+            tn[q] = ~0ull;
+        }
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) {
