@@ -294,10 +294,29 @@ __device__ __forceinline__ void bucket_lds_init(const BucketArgs &a, uint32_t *s
     } else if (a.S == 1) {  // learned: T in sorted order (searched outward from a guess)
         uint64_t *th = reinterpret_cast<uint64_t *>(s);
         for (uint32_t t = threadIdx.x; t < a.B; t += blockDim.x) th[t] = a.T[t];
-    } else if (AMODE == 0) {  // the splitter's 1-in-S sample
-        uint64_t *ts = reinterpret_cast<uint64_t *>(s);
-        for (uint32_t t = threadIdx.x; t < a.B / a.S; t += blockDim.x) ts[t] = a.T[uint64_t(t) * a.S];
+    } else if (AMODE == 0) {
+        // The splitter's 1-in-S sample ts[j] = T[j S], j < m = B/S, in the
+        // same breadth-first order as the full table: node i holds
+        // ts[(2p + 1) << (log2(m) - 1 - k)].
+        uint64_t *e = reinterpret_cast<uint64_t *>(s);
+        const uint32_t m = a.B / a.S, d = 31u - uint32_t(__clz(m));
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            if (i == 0) {
+                e[0] = 0;
+                continue;
+            }
+            const uint32_t k = 31u - uint32_t(__clz(i)), p = i - (1u << k);
+            e[i] = a.T[uint64_t(a.S) * ((2 * p + 1) << (d - 1 - k))];
+        }
     }
+}
+
+// Sorted element j (1 <= j < m) of a breadth-first image e of m sorted
+// values: j = (2p + 1) << (log2(m) - 1 - k) sits at node 2^k + p, so k and p
+// follow from the trailing zeros of j.
+__device__ __forceinline__ uint64_t bfs_sorted(const uint64_t *e, uint32_t m, uint32_t j) {
+    const uint32_t d = 31u - uint32_t(__clz(m)), tz = uint32_t(__ffs(j)) - 1u;
+    return e[(1u << (d - 1u - tz)) + (j >> (tz + 1u))];
 }
 
 template <int AMODE>
@@ -315,12 +334,11 @@ __device__ __forceinline__ uint32_t bucket_of(const BucketArgs &a, const uint32_
         guess = i - a.B;  // the number of T[1..B) at most x
         return guess;
     }
-    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s);
-    uint32_t lo = 0, hi = a.B / a.S;  // ts[lo] <= x < ts[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (ts[mid] <= x) lo = mid; else hi = mid;
-    }
+    const uint64_t *e = reinterpret_cast<const uint64_t *>(s);  // the sample, breadth-first
+    const uint32_t m = a.B / a.S;
+    uint32_t i = 1;
+    while (i < m) i = 2 * i + (e[i] <= x ? 1u : 0u);
+    const uint32_t lo = i - m;  // ts[lo] <= x < ts[lo + 1]
     uint32_t l2 = lo * a.S, h2 = min(a.B, (lo + 1) * a.S);
     while (h2 - l2 > 1) {
         const uint32_t mid = (l2 + h2) >> 1;
@@ -349,26 +367,27 @@ __device__ __forceinline__ void splitter_search_n(const BucketArgs &a, const uin
     for (int q = 0; q < N; ++q) b[q] -= a.B;
 }
 
-// The same for a 1-in-S sample of T in LDS (S > 1, sorted order): a
-// fixed-depth search of the sample finds the run of S thresholds of T that
+// The same for a 1-in-S sample of T in LDS (S > 1, breadth-first order): a
+// fixed-depth descent of the sample finds the run of S thresholds of T that
 // holds the answer; a linear interpolation between the two samples around
-// the key guesses the bucket, two reads of T (global memory, issued together)
-// test the guess and its right neighbour, and a binary search finishes
+// the key guesses the bucket, one 16-byte read of T (global memory) tests
+// the guess and its right neighbour, and a binary search finishes
 // whatever is left of the run.  Exact whatever the data; for smooth data the
 // guess is right or one off, so most keys read T in one round instead of
 // log2(S) dependent ones.
 template <int N>
 __device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, const uint32_t *s,
                                                           const uint64_t *x, uint32_t *b) {
-    const uint64_t *ts = reinterpret_cast<const uint64_t *>(s);
+    const uint64_t *e = reinterpret_cast<const uint64_t *>(s);  // the sample, breadth-first
     const uint32_t m = a.B / a.S;  // sample size; ts[0] = T[0] = 0
 #pragma unroll
-    for (int q = 0; q < N; ++q) b[q] = 0;
+    for (int q = 0; q < N; ++q) b[q] = 1;
     for (uint32_t step = m >> 1; step >= 1; step >>= 1) {
 #pragma unroll
-        for (int q = 0; q < N; ++q)
-            if (ts[b[q] + step] <= x[q]) b[q] += step;
+        for (int q = 0; q < N; ++q) b[q] = 2 * b[q] + (e[b[q]] <= x[q] ? 1u : 0u);
     }
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[q] -= m;  // ts[b] <= x < ts[b + 1]
     // The answer lies in [lo, hi): T[lo] = ts[i] <= x, and T[hi] > x (hi =
     // (i + 1) S is the next sample, or hi = B).
     uint32_t lo[N], hi[N], g[N];
@@ -376,7 +395,7 @@ __device__ __forceinline__ void splitter_search_sampled_n(const BucketArgs &a, c
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const uint32_t i = b[q];
-        const uint64_t t0 = ts[i], t1 = i + 1 < m ? ts[i + 1] : ~0ull;
+        const uint64_t t0 = i ? bfs_sorted(e, m, i) : 0ull, t1 = i + 1 < m ? bfs_sorted(e, m, i + 1) : ~0ull;
         lo[q] = i * a.S;
         hi[q] = lo[q] + a.S;
         const uint64_t span = t1 - t0;  // > 0 unless the run ends at the top of the range

@@ -20,6 +20,7 @@ struct EmuDim {
 };
 static const EmuDim threadIdx{0}, blockDim{1};
 inline int __clz(int v) { return v == 0 ? 32 : __builtin_clz(uint32_t(v)); }
+inline int __ffs(uint32_t v) { return __builtin_ffs(int(v)); }  // 1 + index of the lowest set bit, 0 for 0
 inline uint32_t atomicAdd(uint32_t *p, uint32_t v) {
     const uint32_t o = *p;
     *p = o + v;
