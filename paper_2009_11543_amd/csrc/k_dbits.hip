@@ -3,10 +3,13 @@
 // One thread per adjacent pair (i-1, i): the keys are compared as big-endian
 // 32-bit words (read 16 bytes at a time when rows are 16-byte aligned); the
 // first differing word gives the pair's D-bit as
-// 32*j + clz(x xor y).  The position is OR-ed into a workgroup bitmap in LDS
-// (one u32 per 4 bitmap bytes), and each workgroup OR-s its non-zero words into
-// the global accumulator once.  A pair whose earlier key has a 1 at its D-bit
-// is descending and raises CKEY_FLAG_DESCENDING.
+// 32*j + clz(x xor y).  Keys of at most 64 bytes: each thread ORs its pairs'
+// positions into a bitmap held in registers (16 u32), the wave OR-reduces it
+// by lane shuffles, and one lane per wave ORs it into the workgroup's bitmap in
+// LDS; longer keys OR each position into the LDS bitmap directly.  Each
+// workgroup ORs its non-zero words into the global accumulator once.  A pair
+// whose earlier key has a 1 at its D-bit is descending and raises
+// CKEY_FLAG_DESCENDING.
 #include "internal.h"
 
 namespace ckey {
@@ -35,7 +38,10 @@ __device__ __forceinline__ uint32_t key_word_unaligned(const uint8_t *bytes, uin
     return v;
 }
 
-template <int MODE>
+constexpr uint32_t kDbitsRegWords = 16;  // register bitmap: keys of at most 64 bytes
+
+// RB: words of the per-thread register bitmap (kDbitsRegWords, L <= 64), or 0.
+template <int MODE, int RB>
 __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restrict__ order,
                                                uint32_t *__restrict__ acc,
                                                uint32_t *__restrict__ flags) {
@@ -43,6 +49,18 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
     const uint32_t nw = (k.L + 3) / 4;
     for (uint32_t t = threadIdx.x; t < nw; t += kWG) s_bm[t] = 0;
     __syncthreads();
+    uint32_t rb[RB > 0 ? RB : 1];
+#pragma unroll
+    for (int q = 0; q < (RB > 0 ? RB : 1); ++q) rb[q] = 0u;
+    auto mark = [&](uint32_t p) {  // D-bit p of a pair
+        const uint32_t bit = bitmap_word_bit(p);
+        if constexpr (RB > 0) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q) rb[q] |= (p >> 5) == uint32_t(q) ? bit : 0u;
+        } else {
+            atomicOr(&s_bm[p >> 5], bit);
+        }
+    };
 
     bool desc = false;
     bool too_long = false;
@@ -103,7 +121,7 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
                         const uint32_t lz = __clz(x ^ y);
                         const uint32_t p = 32 * j + lz;
                         desc |= ((x >> (31 - lz)) & 1u) != 0;
-                        atomicOr(&s_bm[p >> 5], bitmap_word_bit(p));
+                        mark(p);
                         done = true;
                     }
                 }
@@ -124,13 +142,27 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
                 uint32_t lz = __clz(x ^ y);
                 uint32_t p = 32 * j + lz;
                 desc |= ((x >> (31 - lz)) & 1u) != 0;
-                atomicOr(&s_bm[p >> 5], bitmap_word_bit(p));
+                mark(p);
                 break;
             }
         }
     }
     if (flags && (desc || too_long))
         atomicOr(flags, (desc ? CKEY_FLAG_DESCENDING : 0u) | (too_long ? CKEY_FLAG_KEY_TOO_LONG : 0u));
+    if constexpr (RB > 0) {  // OR across the wave, then one lane per wave into LDS
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            uint32_t v = rb[q];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v |= uint32_t(__shfl_xor(int(v), off, 64));
+            rb[q] = v;
+        }
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+                if (rb[q]) atomicOr(&s_bm[q], rb[q]);  // rb[q] != 0 only for q < nw
+        }
+    }
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < nw; t += kWG)
         if (s_bm[t]) atomicOr(&acc[t], s_bm[t]);
@@ -175,32 +207,22 @@ ckey_status dbits_launch(const KeySrc &k, const uint32_t *order, uint32_t *acc, 
     uint64_t blocks = (k.n - 1 + kWG - 1) / kWG;
     if (blocks > 2048) blocks = 2048;
     const size_t lds = nw * sizeof(uint32_t);
+    const bool reg = nw <= kDbitsRegWords;
+#define CKEY_LAUNCH_DB(M)                                                                              \
+    if (reg)                                                                                           \
+        hipLaunchKernelGGL((k_dbits<M, kDbitsRegWords>), dim3(uint32_t(blocks)), dim3(kWG), lds, st, k, \
+                           order, acc, flags);                                                         \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_dbits<M, 0>), dim3(uint32_t(blocks)), dim3(kWG), lds, st, k, order, acc,  \
+                           flags);
+    const int pr_ = prof_begin(st, "dbits");
     switch (load_mode(k)) {
-        case kLoadBytes:
-            {
-                const int pr_ = prof_begin(st, "dbits");
-                hipLaunchKernelGGL(k_dbits<kLoadBytes>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
-                                   order, acc, flags);
-                prof_end(st, pr_);
-            }
-            break;
-        case kLoad16:
-            {
-                const int pr_ = prof_begin(st, "dbits");
-                hipLaunchKernelGGL(k_dbits<kLoad16>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
-                                   order, acc, flags);
-                prof_end(st, pr_);
-            }
-            break;
-        default:
-            {
-                const int pr_ = prof_begin(st, "dbits");
-                hipLaunchKernelGGL(k_dbits<kLoad4>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k,
-                                   order, acc, flags);
-                prof_end(st, pr_);
-            }
-            break;
+        case kLoadBytes: CKEY_LAUNCH_DB(kLoadBytes) break;
+        case kLoad16: CKEY_LAUNCH_DB(kLoad16) break;
+        default: CKEY_LAUNCH_DB(kLoad4) break;
     }
+#undef CKEY_LAUNCH_DB
+    prof_end(st, pr_);
     return launch_status();
 }
 
