@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <atomic>
 #include <barrier>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
@@ -93,7 +94,10 @@ inline int __popcll(uint64_t v) { return __builtin_popcountll(v); }
 inline int __clzll(uint64_t v) { return __builtin_clzll(v); }
 #define __builtin_amdgcn_readfirstlane(x) (x)
 #define __builtin_amdgcn_fence(a, b) std::atomic_thread_fence(std::memory_order_seq_cst)
-#define __builtin_amdgcn_s_sleep(x) std::this_thread::yield()
+// A waiting thread gives its CPU away for a while: with thousands of emulated
+// threads on a few host cores, a bare yield would let a wait reach the
+// kernel's spin limit before the awaited workgroup has been scheduled.
+#define __builtin_amdgcn_s_sleep(x) std::this_thread::sleep_for(std::chrono::microseconds(20))
 #define __HIP_MEMORY_SCOPE_AGENT 0
 template <class T> inline T __hip_atomic_load(T *p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
 template <class T> inline void __hip_atomic_store(T *p, T v, int, int) { __atomic_store_n(p, v, __ATOMIC_SEQ_CST); }
