@@ -882,9 +882,12 @@ __device__ __forceinline__ void sort_bucket(
 #pragma unroll
                     for (int k = 0; k < WC - 1; ++k) a[k] = cw[k * C + c];
                     const uint32_t ar = cr[c], rs = s_run[f];
+                    // a run's members hold consecutive positions, and so
+                    // consecutive compact indices: member q is cs + (q - rs)
+                    const uint32_t cs = c - (f - rs);
                     uint32_t r = 0;
                     for (uint32_t q = rs; q < cnt && s_run[q] == rs; ++q) {
-                        const uint32_t cq = map[ord[q]];
+                        const uint32_t cq = cs + (q - rs);
                         int cmp = 0;  // -1: member q orders first
 #pragma unroll
                         for (int k = 0; k < WC - 1; ++k) {
