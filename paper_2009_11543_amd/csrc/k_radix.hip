@@ -154,6 +154,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
     const uint32_t dmask = (1u << ps.bits) - 1u;
     const uint64_t *dsrc = src + uint64_t(word_pass ? ps.word : 0) * bf.src_ld + base;
     const uint64_t lane_lt = (1ull << lane) - 1ull;
+    const uint32_t gstart = bstart[tid];  // read early: its latency overlaps the tile's loads
 
     uint64_t xv[kKPT];
     uint32_t dig[kKPT];
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
             __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_gbase[tid] = bstart[tid] + excl - tstart;
+        s_gbase[tid] = gstart + excl - tstart;
     }
     __syncthreads();
 
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(kWG) void k_onesweep(
 //
 // offs (optional): each tile's global start per digit, offs[d * ntiles + tile],
 // from k_tile_counts + k_tile_scan; the tile then needs no look-back.
-template <int WC, int KPT, int NT>
+// AUX: the pass digit is a digit of the 16-bit aux key (a bucket-id pass).
+template <int WC, int KPT, int NT, bool AUX>
 __global__ __launch_bounds__(NT) void k_onesweep_pre(
     Bufs bf, uint64_t n, Pass ps, const uint32_t *__restrict__ bstart, uint32_t *lookback,
     uint32_t *tile_counter, uint32_t *flags, const uint32_t *__restrict__ offs, uint32_t ntiles) {
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
 
     if (gate_closed(bf.gate)) return;
     const bool rid_pass = ps.word == kRidWord;
-    const bool aux_pass = ps.word == kAuxWord;
+    const bool aux_pass = AUX;  // ps.word == kAuxWord
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int t = tid; t < NW * kRadixMax; t += NT) (&s_wc[0][0])[t] = 0;
@@ -336,25 +338,65 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
     const uint32_t cnt = uint32_t(min<uint64_t>(TILE, n - base));
     const uint32_t dmask = (1u << ps.bits) - 1u;
     const uint64_t lane_lt = (1ull << lane) - 1ull;
+    // The bucket's global start (this tile's from offs, else the pass's) is
+    // read before the tile, so that its latency overlaps the tile's loads.
+    uint32_t gstart = 0;
+    if (tid <= int(dmask)) gstart = offs ? offs[uint64_t(tid) * ntiles + tile] : bstart[tid];
 
     uint64_t wv[WC][KPT];
     uint32_t rv[KPT], av[KPT], dig[KPT], lpos[KPT];
+    if constexpr (AUX) {
+        // Every load of the tile is issued before any work, unconditionally:
+        // slots past the end of the last tile read its last row (their
+        // values are never used).  A select between a loaded value and a
+        // constant would make each round of loads wait for the previous ones.
+        // The bucket ids go first and the digits come from them alone: loads
+        // retire in order, so the ranking waits for those loads only while
+        // the other arrays' loads stay in flight.
+        const uint32_t last = cnt - 1;
 #pragma unroll
-    for (int m = 0; m < KPT; ++m) {  // every load of the tile first
-        const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
-        const bool valid = li < cnt;
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t li = min(wave * (KPT * 64) + m * 64 + lane, last);
+            av[m] = uint32_t(bf.src_aux[base + li]);
+        }
 #pragma unroll
-        for (int k = 0; k < WC; ++k) wv[k][m] = valid ? bf.src[uint64_t(k) * bf.src_ld + base + li] : 0ull;
-        rv[m] = valid ? (bf.src_rid ? bf.src_rid[base + li] : uint32_t(base + li)) : 0u;
-        av[m] = (valid && aux_pass) ? uint32_t(bf.src_aux[base + li]) : 0u;
-    }
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t li = min(wave * (KPT * 64) + m * 64 + lane, last);
 #pragma unroll
-    for (int m = 0; m < KPT; ++m) {
-        uint64_t x = rid_pass ? uint64_t(rv[m]) : uint64_t(av[m]);
+            for (int k = 0; k < WC; ++k) wv[k][m] = bf.src[uint64_t(k) * bf.src_ld + base + li];
+        }
 #pragma unroll
-        for (int k = 0; k < WC; ++k)
-            if (uint32_t(k) == ps.word) x = wv[k][m];
-        dig[m] = uint32_t(x >> ps.shift) & dmask;
+        for (int m = 0; m < KPT; ++m) rv[m] = uint32_t(base) + wave * (KPT * 64) + m * 64 + lane;
+        if (bf.src_rid) {  // else the pass generates the row ids
+#pragma unroll
+            for (int m = 0; m < KPT; ++m) {
+                const uint32_t li = min(wave * (KPT * 64) + m * 64 + lane, last);
+                rv[m] = bf.src_rid[base + li];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) dig[m] = (av[m] >> ps.shift) & dmask;
+    } else {
+        // The digit comes from a key word or the row id.  (Loading this way,
+        // one round of KPT loads after the other, measured faster here than
+        // every load issued first: the ranking needs the digit word's loads.)
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
+            const bool valid = li < cnt;
+#pragma unroll
+            for (int k = 0; k < WC; ++k) wv[k][m] = valid ? bf.src[uint64_t(k) * bf.src_ld + base + li] : 0ull;
+            rv[m] = valid ? (bf.src_rid ? bf.src_rid[base + li] : uint32_t(base + li)) : 0u;
+            av[m] = 0u;
+        }
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) {
+            uint64_t x = rid_pass ? uint64_t(rv[m]) : 0ull;
+#pragma unroll
+            for (int k = 0; k < WC; ++k)
+                if (uint32_t(k) == ps.word) x = wv[k][m];
+            dig[m] = uint32_t(x >> ps.shift) & dmask;
+        }
     }
 
     // Stable rank within the wave: peers = lanes holding the same digit.
@@ -392,7 +434,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
         const uint32_t tstart = block_excl_scan_n<NT>(tot, s_tmp, all);
         if (tid < kRadixMax && offs) {
             s_tstart[tid] = tstart;
-            s_gbase[tid] = (tid < (1 << ps.bits) ? offs[uint64_t(tid) * ntiles + tile] : 0u) - tstart;
+            s_gbase[tid] = gstart - tstart;
         } else if (tid < kRadixMax) {
             s_tstart[tid] = tstart;
             uint32_t *lb = lookback + uint64_t(tile) * kRadixMax + tid;
@@ -420,7 +462,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
                 __hip_atomic_store(lb, kFlagInc | (excl + tot), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
-            s_gbase[tid] = bstart[tid] + excl - tstart;
+            s_gbase[tid] = gstart + excl - tstart;
         }
     }
     __syncthreads();
@@ -549,39 +591,40 @@ inline uint64_t pass_tile(uint32_t words, bool half = false) {
     return use_pre(words) ? uint64_t(half ? kPreNT / 2 : kPreNT) * pre_kpt(words) : uint64_t(kTile);
 }
 
+template <int NT, bool AUX>
+void launch_pre(uint32_t words, dim3 g, hipStream_t st, const Bufs &bf, uint64_t n, const Pass &ps,
+                const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
+                const uint32_t *offs, uint32_t nt) {
+    const dim3 b(NT);
+    switch (words) {
+        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 6, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 5: hipLaunchKernelGGL((k_onesweep_pre<5, 6, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 6: hipLaunchKernelGGL((k_onesweep_pre<6, 5, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        case 7: hipLaunchKernelGGL((k_onesweep_pre<7, 4, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+        default: hipLaunchKernelGGL((k_onesweep_pre<8, 4, NT, AUX>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
+    }
+}
+
 void launch_pass(uint32_t words, uint64_t tiles, const Bufs &bf, uint64_t n, const Pass &ps,
                  const uint32_t *bstart, uint32_t *lookback, uint32_t *counter, uint32_t *flags,
                  hipStream_t st, const uint32_t *offs = nullptr, bool half = false) {
     const uint32_t nt = uint32_t(tiles);
-    const dim3 g = dim3(uint32_t(tiles)), b = dim3(use_pre(words) ? (half ? kPreNT / 2 : kPreNT) : kWG);
+    const dim3 g = dim3(uint32_t(tiles));
     if (!use_pre(words)) {
-        hipLaunchKernelGGL(k_onesweep<0>, g, b, 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
+        hipLaunchKernelGGL(k_onesweep<0>, g, dim3(kWG), 0, st, bf, n, words, ps, bstart, lookback, counter, flags);
         return;
     }
-    if (half) {
-        constexpr int H = kPreNT / 2;
-        switch (words) {
-            case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 6, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 5: hipLaunchKernelGGL((k_onesweep_pre<5, 6, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 6: hipLaunchKernelGGL((k_onesweep_pre<6, 5, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            case 7: hipLaunchKernelGGL((k_onesweep_pre<7, 4, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-            default: hipLaunchKernelGGL((k_onesweep_pre<8, 4, H>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        }
-        return;
-    }
-    switch (words) {
-        case 1: hipLaunchKernelGGL((k_onesweep_pre<1, 12, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 2: hipLaunchKernelGGL((k_onesweep_pre<2, 10, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 3: hipLaunchKernelGGL((k_onesweep_pre<3, 8, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 4: hipLaunchKernelGGL((k_onesweep_pre<4, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 5: hipLaunchKernelGGL((k_onesweep_pre<5, 6, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 6: hipLaunchKernelGGL((k_onesweep_pre<6, 5, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        case 7: hipLaunchKernelGGL((k_onesweep_pre<7, 4, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-        default: hipLaunchKernelGGL((k_onesweep_pre<8, 4, kPreNT>), g, b, 0, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt); break;
-    }
+    if (ps.word == kAuxWord && !half)
+        launch_pre<kPreNT, true>(words, g, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt);
+    else if (ps.word == kAuxWord)
+        launch_pre<kPreNT / 2, true>(words, g, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt);
+    else if (half)
+        launch_pre<kPreNT / 2, false>(words, g, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt);
+    else
+        launch_pre<kPreNT, false>(words, g, st, bf, n, ps, bstart, lookback, counter, flags, offs, nt);
 }
 
 __global__ void k_copy_back(Bufs bf, uint64_t n, uint32_t words) {
