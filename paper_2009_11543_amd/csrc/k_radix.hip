@@ -329,6 +329,7 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
     if (gate_closed(bf.gate)) return;
     const bool rid_pass = ps.word == kRidWord;
     const bool aux_pass = AUX;  // ps.word == kAuxWord
+    const uint32_t rot = (AUX || rid_pass) ? 0u : ps.word;  // word held in register row 0
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (int t = tid; t < NW * kRadixMax; t += NT) (&s_wc[0][0])[t] = 0;
@@ -377,25 +378,37 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
 #pragma unroll
         for (int m = 0; m < KPT; ++m) dig[m] = (av[m] >> ps.shift) & dmask;
     } else {
-        // The digit comes from a key word or the row id.  (Loading this way,
-        // one round of KPT loads after the other, measured faster here than
-        // every load issued first: the ranking needs the digit word's loads.)
+        // The digit comes from a key word (or the row id).  Register row k
+        // holds word (k + rot) mod WC, so the digit's word is row 0: its loads
+        // go first and the digits come from it alone, the ranking waiting
+        // for those loads only.  Every load is unconditional, as above.
+        const uint32_t last = cnt - 1;
 #pragma unroll
-        for (int m = 0; m < KPT; ++m) {
-            const uint32_t li = wave * (KPT * 64) + m * 64 + lane;
-            const bool valid = li < cnt;
+        for (int k = 0; k < WC; ++k) {
+            const uint32_t kw = uint32_t(k) + rot < uint32_t(WC) ? uint32_t(k) + rot : uint32_t(k) + rot - WC;
 #pragma unroll
-            for (int k = 0; k < WC; ++k) wv[k][m] = valid ? bf.src[uint64_t(k) * bf.src_ld + base + li] : 0ull;
-            rv[m] = valid ? (bf.src_rid ? bf.src_rid[base + li] : uint32_t(base + li)) : 0u;
-            av[m] = 0u;
+            for (int m = 0; m < KPT; ++m) {
+                const uint32_t li = min(wave * (KPT * 64) + m * 64 + lane, last);
+                wv[k][m] = bf.src[uint64_t(kw) * bf.src_ld + base + li];
+            }
         }
 #pragma unroll
-        for (int m = 0; m < KPT; ++m) {
-            uint64_t x = rid_pass ? uint64_t(rv[m]) : 0ull;
+        for (int m = 0; m < KPT; ++m) rv[m] = uint32_t(base) + wave * (KPT * 64) + m * 64 + lane;
+        if (bf.src_rid) {  // else the pass generates the row ids
 #pragma unroll
-            for (int k = 0; k < WC; ++k)
-                if (uint32_t(k) == ps.word) x = wv[k][m];
-            dig[m] = uint32_t(x >> ps.shift) & dmask;
+            for (int m = 0; m < KPT; ++m) {
+                const uint32_t li = min(wave * (KPT * 64) + m * 64 + lane, last);
+                rv[m] = bf.src_rid[base + li];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < KPT; ++m) av[m] = 0u;
+        if (rid_pass) {
+#pragma unroll
+            for (int m = 0; m < KPT; ++m) dig[m] = (rv[m] >> ps.shift) & dmask;
+        } else {
+#pragma unroll
+            for (int m = 0; m < KPT; ++m) dig[m] = uint32_t(wv[0][m] >> ps.shift) & dmask;
         }
     }
 
@@ -489,7 +502,8 @@ __global__ __launch_bounds__(NT) void k_onesweep_pre(
             if (li < cnt) s_buf[lpos[m]] = wv[k][m];
         }
         __syncthreads();
-        uint64_t *kdst = bf.dst + uint64_t(k) * bf.dst_ld;
+        const uint32_t kw = uint32_t(k) + rot < uint32_t(WC) ? uint32_t(k) + rot : uint32_t(k) + rot - WC;
+        uint64_t *kdst = bf.dst + uint64_t(kw) * bf.dst_ld;
 #pragma unroll
         for (int m = 0; m < KPT; ++m) {
             const uint32_t j = m * NT + tid;
