@@ -8,13 +8,17 @@
 //
 // bucket(x) = the b with T[b] <= prefix(x) < T[b+1].  It is non-decreasing in
 // key order, so concatenating the buckets, each sorted, sorts everything.
-// The MLP only predicts where to start looking: an exponential-then-binary
-// search from the prediction always lands on the exact bucket, so exactness
-// never depends on the network (the splitter method instead searches a
-// 1-in-S sample of T held in LDS, then T itself).
+// The MLP only predicts where to start looking: a search of T from the
+// prediction always lands on the exact bucket, so exactness never depends on
+// the network.  Up to 2^14 buckets T is in LDS and the search is a fixed-depth
+// one over the 2^10 buckets around the guess (all of T when the key lies
+// outside them); beyond, T is in memory and the search gallops outward from
+// the guess; with statistics asked for it is exponential, then binary.  The
+// splitter method needs no network: a binary search of T in LDS (beyond 2^14
+// buckets, of a 1-in-S sample of T in LDS, then of T's run).
 //
 // Sort: assign buckets (+ histogram) -> scan -> group rows by bucket (a
-// stable sort on the bucket id: two one-sweep passes) -> one workgroup per
+// stable sort on the bucket id: two 7-bit passes) -> one workgroup per
 // bucket sorts it in place in LDS by the offset of the first word from the
 // bucket's lower threshold (a counting pass over its top bits, then a rank of
 // each group of equal top bits by the whole offset), then orders runs of equal
