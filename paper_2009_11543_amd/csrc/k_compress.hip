@@ -235,25 +235,35 @@ __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan pla
     if (fits) {
         // 16-byte chunks fully inside [base + b0 - pad, base + b1) are loaded as
         // vectors when they lie inside the key buffer; edge chunks byte by byte.
+        // Every inside chunk's load is issued before any is stored, so a
+        // thread's loads are in flight together; the edge chunks follow.
         const uint64_t nch = (span + 15) / 16;
-        for (uint64_t c = threadIdx.x; c < nch; c += kWG) {
+        constexpr int kCh = (kVarTileBytes / 16 + kWG) / kWG;  // chunks per thread at most
+        uint4 v[kCh];
+#pragma unroll
+        for (int q = 0; q < kCh; ++q) {
+            const uint64_t c = threadIdx.x + uint64_t(q) * kWG;
             const uintptr_t addr = a0 + 16 * c;
-            uint4 v;
-            if (addr >= base + b0 && addr + 16 <= base + b1) {
-                v = *reinterpret_cast<const uint4 *>(addr);
-            } else {
+            if (c < nch && addr >= base + b0 && addr + 16 <= base + b1) v[q] = *reinterpret_cast<const uint4 *>(addr);
+        }
+#pragma unroll
+        for (int q = 0; q < kCh; ++q) {
+            const uint64_t c = threadIdx.x + uint64_t(q) * kWG;
+            if (c >= nch) break;
+            const uintptr_t addr = a0 + 16 * c;
+            if (addr < base + b0 || addr + 16 > base + b1) {
                 uint32_t w[4] = {0, 0, 0, 0};
                 for (int t = 0; t < 16; ++t) {
                     const uintptr_t bt = addr + t;
                     if (bt >= base + b0 && bt < base + b1)
                         w[t >> 2] |= uint32_t(*reinterpret_cast<const uint8_t *>(bt)) << (8 * (t & 3));
                 }
-                v = make_uint4(w[0], w[1], w[2], w[3]);
+                v[q] = make_uint4(w[0], w[1], w[2], w[3]);
             }
-            s_tile[4 * c + 0] = v.x;
-            s_tile[4 * c + 1] = v.y;
-            s_tile[4 * c + 2] = v.z;
-            s_tile[4 * c + 3] = v.w;
+            s_tile[4 * c + 0] = v[q].x;
+            s_tile[4 * c + 1] = v[q].y;
+            s_tile[4 * c + 2] = v[q].z;
+            s_tile[4 * c + 3] = v[q].w;
         }
         for (uint64_t c = 4 * nch + threadIdx.x; c < 4 * nch + 8; c += kWG) s_tile[c] = 0;
     }

@@ -14,6 +14,8 @@
 // key when no index key lies between the two, else index key pos-1; when the
 // next batch key does not share its place, index key pos is its successor.
 // Deletes leave both bitmaps unchanged (Sec. 4.3): they need no kernel.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ckey {
@@ -83,10 +85,30 @@ __global__ __launch_bounds__(kWG) void k_variant(KeySrc k, const uint8_t *__rest
             if (j0 + t < nw)
                 rw[t] = ref ? key_word_bytes(ref, j0 + t, k.L)
                             : view_word<MODE == kLoadBytes ? kLoadBytes : kLoad4>(rv, j0 + t);
+            rw[t] = __builtin_amdgcn_readfirstlane(rw[t]);  // the same for every lane: scalar registers
         }
         for (uint64_t i = uint64_t(blockIdx.x) * kWG + threadIdx.x; i < k.n; i += step) {
             const KeyView v = key_view(k, i, too_long);
-            if (MODE == kLoad16) {  // 16-byte aligned rows: 128-bit loads
+            if (MODE == kLoad16 && j0 + kVG <= nw) {
+                // 16-byte aligned rows, the whole group inside the key: its
+                // 128-bit loads are issued together, then combined.
+                uint4 u[kVG / 4];
+#pragma unroll
+                for (uint32_t c = 0; c < kVG / 4; ++c)
+                    u[c] = *reinterpret_cast<const uint4 *>(v.p + 4 * (j0 + 4 * c));
+#pragma unroll
+                for (uint32_t c = 0; c < kVG / 4; ++c) {
+                    const uint32_t j = j0 + 4 * c;
+                    const uint32_t w4[4] = {u[c].x, u[c].y, u[c].z, u[c].w};
+#pragma unroll
+                    for (uint32_t q = 0; q < 4; ++q) {
+                        const int32_t have = int32_t(v.len) - int32_t(4 * (j + q));
+                        uint32_t x = have > 0 ? __builtin_bswap32(w4[q]) : 0u;
+                        if (have > 0 && have < 4) x &= ~(0xFFFFFFFFu >> (8 * have));
+                        a[4 * c + q] |= x ^ rw[4 * c + q];
+                    }
+                }
+            } else if (MODE == kLoad16) {  // 16-byte aligned rows: 128-bit loads
 #pragma unroll
                 for (uint32_t c = 0; c < kVG / 4; ++c) {
                     const uint32_t j = j0 + 4 * c;
@@ -198,11 +220,17 @@ ckey_status variant_launch(const KeySrc &k, const uint8_t *ref, uint32_t *acc, u
                            hipStream_t st) {
     if (k.n == 0) return CKEY_OK;
     const uint32_t nw = (k.L + 3) / 4;
-    uint64_t blocks = (k.n + kWG - 1) / kWG;
-    if (blocks > 2048) blocks = 2048;
     const size_t lds = nw * sizeof(uint32_t);
+    // The grid-stride loop runs on the workgroups resident at once (a second
+    // round of workgroups would start late and leave the tail uneven).
+    const int mode = load_mode(k);
+    const void *fn = mode == kLoad16 ? reinterpret_cast<const void *>(k_variant<kLoad16>)
+                   : mode == kLoad4  ? reinterpret_cast<const void *>(k_variant<kLoad4>)
+                                     : reinterpret_cast<const void *>(k_variant<kLoadBytes>);
+    uint64_t blocks = (k.n + kWG - 1) / kWG;
+    blocks = std::min<uint64_t>(blocks, resident_grid(fn, kWG, lds));
     const int pr = prof_begin(st, "variant");
-    switch (load_mode(k)) {
+    switch (mode) {
         case kLoad16:
             hipLaunchKernelGGL(k_variant<kLoad16>, dim3(uint32_t(blocks)), dim3(kWG), lds, st, k, ref, acc, flags);
             break;
