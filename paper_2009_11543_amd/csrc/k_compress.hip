@@ -63,7 +63,9 @@ struct SrcWord {
 };
 
 // Gather of one key's D bits into its output words, for a loader that
-// fills the four big-endian words of a 16-byte chunk.
+// fills the four words of a 16-byte chunk: big-endian, or as loaded from
+// memory (little-endian, Loader::kRaw) so that no load's value is needed
+// before the group's other loads are issued.
 // Returns output word 0 when this launch writes it (else 0).
 template <typename Loader>
 __device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const Loader &ld,
@@ -82,9 +84,16 @@ __device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const uint32_t c = c0 + g;
+            if constexpr (Loader::kRaw) {
+                // Memory loads are issued unconditionally (a chunk past the
+                // last one reloads the last; its words are not used), so that
+                // no branch separates them.
+                ld(plan, c < plan.n_chunks ? c : plan.n_chunks - 1, g, x[g]);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[g][q] = 0;
-            if (c < plan.n_chunks) ld(plan, c, g, x[g]);
+                for (int q = 0; q < 4; ++q) x[g][q] = 0;
+                if (c < plan.n_chunks) ld(plan, c, g, x[g]);
+            }
         }
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
@@ -94,7 +103,7 @@ __device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const
             for (int q = 0; q < 4; ++q) {
                 const WordOp &op = plan.op[4 * c + q];
                 if (op.m == 0) continue;
-                uint32_t v = x[g][q] & op.m;
+                uint32_t v = (Loader::kRaw ? __builtin_bswap32(x[g][q]) : x[g][q]) & op.m;
                 if (op.m != 0xFFFFFFFFu) {
 #pragma unroll
                     for (int s = 0; s < 5; ++s) {
@@ -126,21 +135,23 @@ __device__ __forceinline__ uint64_t compress_key(const CompressPlan &plan, const
 
 template <int MODE>
 struct GlobalLoader {
+    static constexpr bool kRaw = MODE != kLoadBytes;  // words as loaded (little-endian)
     const uint8_t *p;
     uint32_t len;
     __device__ __forceinline__ void operator()(const CompressPlan &plan, uint32_t c, int, uint32_t *x) const {
         const uint32_t cb = plan.chunk[c];
         if (MODE == kLoad16) {
             const uint4 v = *reinterpret_cast<const uint4 *>(p + 16 * cb);
-            x[0] = __builtin_bswap32(v.x);
-            x[1] = __builtin_bswap32(v.y);
-            x[2] = __builtin_bswap32(v.z);
-            x[3] = __builtin_bswap32(v.w);
+            x[0] = v.x;
+            x[1] = v.y;
+            x[2] = v.z;
+            x[3] = v.w;
         } else if (MODE == kLoad4) {
+            // A word without D bits may lie past the row: it rereads the
+            // key's first word instead (its value is not used).
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (plan.op[4 * c + q].m)
-                    x[q] = __builtin_bswap32(*reinterpret_cast<const uint32_t *>(p + 16 * cb + 4 * q));
+                x[q] = *reinterpret_cast<const uint32_t *>(plan.op[4 * c + q].m ? p + 16 * cb + 4 * q : p);
         } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -178,6 +189,7 @@ __global__ __launch_bounds__(kWG) void k_compress(KeySrc k, CompressPlan plan,
 constexpr uint32_t kVarTileBytes = 256 * 128;  // keys up to 128 bytes on average per tile
 
 struct LdsLoader {
+    static constexpr bool kRaw = false;
     const uint32_t *s;  // LDS tile, little-endian words
     uint32_t o;         // key's first byte in the tile
     uint32_t len;
@@ -203,6 +215,7 @@ struct LdsLoader {
 // A variable-length key read from the LDS tile (s non-null) or, for a
 // workgroup whose keys exceed the tile, byte by byte from global memory.
 struct VarLoader {
+    static constexpr bool kRaw = false;
     const uint32_t *s;
     uint32_t o;
     uint32_t len;
@@ -283,6 +296,7 @@ __global__ __launch_bounds__(kWG) void k_compress_var(KeySrc k, CompressPlan pla
 // Chunks already in registers, for keys of at most four 16-byte chunks (the
 // compress loop then runs one group, whose slot g is the chunk index).
 struct RegLoader {
+    static constexpr bool kRaw = false;
     const uint4 *v;
     __device__ __forceinline__ void operator()(const CompressPlan &, uint32_t, int g, uint32_t *x) const {
         const uint4 u = v[g];
