@@ -129,7 +129,45 @@ __global__ __launch_bounds__(kWG) void k_dbits(KeySrc k, const uint32_t *__restr
             }
             continue;
         }
-        for (uint32_t j = 0; j < nw; ++j) {
+        uint32_t j = 0;
+        if (MODE == kLoadBytes && total) {
+            // 16 key bytes of both keys per step: the five aligned words around
+            // each key's next four are loaded together (while inside the
+            // buffer), then funnel-shifted; the word-by-word loop below
+            // finishes what is left.
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(k.bytes);
+            const uint64_t oa = uint64_t(pa - k.bytes), ob = uint64_t(pb - k.bytes);
+            const uint32_t sha = 8 * uint32_t(oa & 3), shb = 8 * uint32_t(ob & 3);
+            bool done = false;
+            for (; j + 4 <= nw; j += 4) {
+                const uint64_t wa = (oa >> 2) + j, wb = (ob >> 2) + j;
+                if (4 * (wa + 5) > total || 4 * (wb + 5) > total) break;
+                uint32_t ua[5], ub[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    ua[q] = w[wa + q];
+                    ub[q] = w[wb + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t jq = j + uint32_t(q);
+                    uint32_t x = __builtin_bswap32(sha ? (ua[q] >> sha) | (ua[q + 1] << (32 - sha)) : ua[q]);
+                    uint32_t y = __builtin_bswap32(shb ? (ub[q] >> shb) | (ub[q + 1] << (32 - shb)) : ub[q]);
+                    const int32_t ha = int32_t(la) - int32_t(4 * jq), hb = int32_t(lb) - int32_t(4 * jq);
+                    x = ha <= 0 ? 0u : ha < 4 ? x & ~(0xFFFFFFFFu >> (8 * ha)) : x;
+                    y = hb <= 0 ? 0u : hb < 4 ? y & ~(0xFFFFFFFFu >> (8 * hb)) : y;
+                    if (!done && x != y) {
+                        const uint32_t lz = __clz(x ^ y);
+                        desc |= ((x >> (31 - lz)) & 1u) != 0;
+                        mark(32 * jq + lz);
+                        done = true;
+                    }
+                }
+                if (done) break;
+            }
+            if (done) continue;
+        }
+        for (; j < nw; ++j) {
             uint32_t x, y;
             if (MODE == kLoadBytes && total) {
                 x = key_word_unaligned(k.bytes, total, uint64_t(pa - k.bytes), j, la);

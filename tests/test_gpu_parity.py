@@ -100,6 +100,30 @@ def test_distinction_bits_wide_aligned_rows(ck, L, pad):
     np.testing.assert_array_equal(got.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("L,maxlen", [(64, 64), (120, 100)])
+def test_distinction_bits_long_byte_keys(ck, L, maxlen):
+    """Byte-addressed keys (variable length, and fixed width at an odd stride)
+    with long shared prefixes, so that the first difference lies several
+    16-byte steps in; keys end inside a step, and the last keys sit next to
+    the end of the byte buffer, where the comparison goes word by word."""
+    import torch
+    rng = np.random.default_rng(L)
+    n = 6000
+    lens = rng.integers(1, maxlen + 1, n)
+    rows = rng.choice(np.frombuffer(b"ab", np.uint8), (n, L))
+    rows[:, : L // 2] = 0x41
+    rows[np.arange(L)[None, :] >= lens[:, None]] = 0
+    flat, offs = datagen.pack_varlen(rows, lens)
+    kv = O.Keys(flat, L=L, offsets=offs)
+    perm = O.full_sort(kv)
+    ref, _ = O.dbits(kv, perm)
+    order = torch.from_numpy(perm.view(np.int32)).cuda()
+    got = ck.ckey_distinction_bits(dev_keys(ck, flat=flat, offsets=offs, L=L), order=order)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+    got = ck.ckey_distinction_bits(dev_keys(ck, rows, L=L, stride_pad=3), order=order)
+    np.testing.assert_array_equal(got.cpu().numpy(), ref)
+
+
 # --------------------------------------------------------------- compress --
 
 def bitmaps_for(rows, seed):
