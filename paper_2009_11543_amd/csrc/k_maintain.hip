@@ -75,6 +75,11 @@ __global__ __launch_bounds__(kWG) void k_variant(KeySrc k, const uint8_t *__rest
     bool too_long = false;
     const KeyView rv = ref ? KeyView{ref, k.L} : key_view(k, 0, too_long);
     const int lane = threadIdx.x & 63;
+    // Byte-addressed keys in a 4-byte aligned buffer of `total` bytes: a
+    // group's words come from the aligned words around them (else 0: bytes).
+    const uint64_t total = (MODE == kLoadBytes && (reinterpret_cast<uintptr_t>(k.bytes) & 3u) == 0)
+                               ? (k.offsets ? k.offsets[k.n] : k.n * uint64_t(k.stride))
+                               : 0;
     const uint64_t step = uint64_t(gridDim.x) * kWG;
     for (uint32_t j0 = 0; j0 < nw; j0 += kVG) {
         uint32_t rw[kVG], a[kVG];
@@ -122,6 +127,23 @@ __global__ __launch_bounds__(kWG) void k_variant(KeySrc k, const uint8_t *__rest
                         if (have > 0 && have < 4) x &= ~(0xFFFFFFFFu >> (8 * have));
                         a[4 * c + q] |= x ^ rw[4 * c + q];
                     }
+                }
+            } else if (MODE == kLoadBytes && total && j0 < (v.len + 3) / 4 &&
+                       4 * ((uint64_t(v.p - k.bytes) >> 2) + j0 + kVG + 1) <= total) {
+                // The kVG + 1 aligned words around the group, loaded together,
+                // then funnel-shifted into the key's big-endian words.
+                const uint64_t o = uint64_t(v.p - k.bytes);
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(k.bytes) + (o >> 2) + j0;
+                const uint32_t sh = 8 * uint32_t(o & 3);
+                uint32_t u[kVG + 1];
+#pragma unroll
+                for (uint32_t t = 0; t <= kVG; ++t) u[t] = w[t];
+#pragma unroll
+                for (uint32_t t = 0; t < kVG; ++t) {
+                    const int32_t have = int32_t(v.len) - int32_t(4 * (j0 + t));
+                    uint32_t x = __builtin_bswap32(sh ? (u[t] >> sh) | (u[t + 1] << (32 - sh)) : u[t]);
+                    x = have <= 0 ? 0u : have < 4 ? x & ~(0xFFFFFFFFu >> (8 * have)) : x;
+                    if (j0 + t < nw) a[t] |= x ^ rw[t];
                 }
             } else {
 #pragma unroll
