@@ -80,14 +80,6 @@ struct LdsTables {
     uint16_t rank[CKEY_MAX_KEY_BYTES]; // compressed index of each byte's first position
 };
 
-__device__ __forceinline__ uint8_t key_byte_at(const KeySrc &k, uint64_t row, uint32_t j) {
-    if (k.offsets) {
-        const uint64_t a = k.offsets[row], b = k.offsets[row + 1];
-        return uint64_t(j) < b - a && j < k.L ? k.bytes[a + j] : uint8_t(0);
-    }
-    return k.bytes[row * k.stride + j];
-}
-
 __device__ __forceinline__ uint16_t key_len_of(const KeySrc &k, uint64_t row) {
     if (!k.offsets) return uint16_t(k.L);
     const uint64_t len = k.offsets[row + 1] - k.offsets[row];
@@ -121,9 +113,26 @@ __device__ uint32_t partial_key(const PkArgs &a, const LdsTables &t, uint64_t po
     uint32_t keyq[5] = {0, 0, 0, 0, 0};
     if (c_any) {  // option C (b): read the key by record ID
         deref = true;
+        // The window's five bytes are loaded together, each at an index
+        // clamped into the key (a byte past the key reads its last byte and
+        // is replaced by zero, as are bytes outside the window by the masks).
+        const uint8_t *kp;
+        uint32_t klen;
+        if (a.keys.offsets) {
+            const uint64_t o0 = a.keys.offsets[row], o1 = a.keys.offsets[row + 1];
+            kp = a.keys.bytes + o0;
+            klen = uint32_t(min<uint64_t>(o1 - o0, L));
+        } else {
+            kp = a.keys.bytes + row * a.keys.stride;
+            klen = L;
+        }
+        if (klen > 0) {
+            uint32_t kb[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q)
-            if (wm[q]) keyq[q] = key_byte_at(a.keys, row, b0 + q);
+            for (int q = 0; q < 5; ++q) kb[q] = kp[min(b0 + uint32_t(q), klen - 1)];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) keyq[q] = b0 + uint32_t(q) < klen ? kb[q] : 0u;
+        }
     }
     uint32_t F = 0;  // the compressed key's bits from the window's first class-A position on
     if (a_any) {
