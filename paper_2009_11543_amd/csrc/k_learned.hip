@@ -94,19 +94,48 @@ __global__ void k_thresholds(const uint64_t *__restrict__ sorted, uint64_t m, ui
     T[b] = b == 0 ? 0ull : sorted[(uint64_t(b) * m) / B];
 }
 
+// Sum of v over the wave, returned to every lane: the DPP inclusive scan of
+// wave_incl_scan (shifts within 16-lane rows, then the row broadcasts) in
+// fp32, whose total lane 63 holds.  A fixed order, so the result is the same
+// on every run.
+__device__ __forceinline__ float wave_total(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Forward + backward on M samples; per-block partial sums (fixed order).
 // target == nullptr: sample i = hash(seed, step, j) mod m, target (i+0.5)/m.
+//
+// Lane k of a wave owns hidden unit k: it holds the unit's five weights and
+// bias and sums the unit's gradient over the wave's samples in registers.  A
+// wave takes 64 samples at a time (lane j loads sample j's word and target
+// and computes its features), then steps through them four at a time, each
+// sample's features read from its lane as scalars; the one cross-lane sum per
+// sample is the network output.  The gradient (mean squared error over M):
+// dL/dy = 2(y - t)/M; w2[k] gets dy*h[k]; where unit k is active (a > 0),
+// b1[k] gets dy*w2[k] and w1[k][c] gets dy*w2[k]*f[c]; b2 gets dy.
 __global__ __launch_bounds__(kWG) void k_mlp_grad(const float *__restrict__ p,
                                                   const uint64_t *__restrict__ prefix,
                                                   const float *__restrict__ target, uint64_t m,
                                                   uint32_t M, uint64_t seed, uint32_t step,
                                                   float *__restrict__ partial) {
+    static_assert(kH == 64, "one hidden unit per lane");
+    constexpr int kQ = 4;  // samples in flight per step of a wave
     __shared__ float s_acc[kWG / 64][kNPad];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (int t = tid; t < (kWG / 64) * kNPad; t += kWG) (&s_acc[0][0])[t] = 0.0f;
-    __syncthreads();
     const float invM = 1.0f / float(M);
-    for (uint64_t base = uint64_t(blockIdx.x) * kWG + wave * 64; base < M;
+    float w1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w1[c] = p[4 * lane + c];
+    const float b1 = p[4 * kH + lane], w2 = p[5 * kH + lane], b2 = p[6 * kH];
+    float gw1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float gb1 = 0.0f, gw2 = 0.0f, gb2 = 0.0f, gl = 0.0f;
+    for (uint64_t base = (uint64_t(blockIdx.x) * (kWG / 64) + wave) * 64; base < M;
          base += uint64_t(gridDim.x) * kWG) {
         const uint64_t j = base + lane;
         const bool valid = j < M;
@@ -117,64 +146,89 @@ __global__ __launch_bounds__(kWG) void k_mlp_grad(const float *__restrict__ p,
         const float t = valid ? (target ? target[i] : (float(i) + 0.5f) / float(m)) : 0.0f;
         float f[4];
         mlp_features(x, f);
-        float h[kH];
-        float y = p[6 * kH];
+        const uint32_t nv = uint32_t(min<uint64_t>(64, uint64_t(M) - base));
+        for (uint32_t s0 = 0; s0 < nv; s0 += kQ) {
+            float fs[kQ][4], h[kQ], y[kQ];
 #pragma unroll
-        for (int k = 0; k < kH; ++k) {
-            float a = p[4 * kH + k];
-            a = fmaf(p[4 * k + 0], f[0], a);
-            a = fmaf(p[4 * k + 1], f[1], a);
-            a = fmaf(p[4 * k + 2], f[2], a);
-            a = fmaf(p[4 * k + 3], f[3], a);
-            h[k] = fmaxf(a, 0.0f);
-            y = fmaf(p[5 * kH + k], h[k], y);
-        }
-        const float e = valid ? y - t : 0.0f;
-        const float dy = 2.0f * e * invM;
-        const float db2 = wave_sum(dy);
-        const float ls = wave_sum(e * e * invM);
-        if (lane == 0) {
-            s_acc[wave][6 * kH] += db2;
-            s_acc[wave][kLoss] += ls;
-        }
+            for (int q = 0; q < kQ; ++q) {
+                const int src = int(min<uint32_t>(s0 + q, 63u));
 #pragma unroll
-        for (int k = 0; k < kH; ++k) {
-            const float g = h[k] > 0.0f ? dy * p[5 * kH + k] : 0.0f;
-            const float c_w2 = wave_sum(dy * h[k]);
-            const float c_b1 = wave_sum(g);
-            const float c0 = wave_sum(g * f[0]);
-            const float c1 = wave_sum(g * f[1]);
-            const float c2 = wave_sum(g * f[2]);
-            const float c3 = wave_sum(g * f[3]);
-            if (lane == 0) {
-                s_acc[wave][5 * kH + k] += c_w2;
-                s_acc[wave][4 * kH + k] += c_b1;
-                s_acc[wave][4 * k + 0] += c0;
-                s_acc[wave][4 * k + 1] += c1;
-                s_acc[wave][4 * k + 2] += c2;
-                s_acc[wave][4 * k + 3] += c3;
+                for (int c = 0; c < 4; ++c)
+                    fs[q][c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f[c]), src));
+                float a = b1;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a = fmaf(w1[c], fs[q][c], a);
+                h[q] = fmaxf(a, 0.0f);
+                y[q] = w2 * h[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) y[q] = wave_total(y[q]) + b2;
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) {
+                const int src = int(min<uint32_t>(s0 + q, 63u));
+                const float ts = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), src));
+                const float e = s0 + q < nv ? y[q] - ts : 0.0f;
+                const float dy = 2.0f * e * invM;
+                gw2 = fmaf(dy, h[q], gw2);
+                const float g = h[q] > 0.0f ? dy * w2 : 0.0f;
+                gb1 += g;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) gw1[c] = fmaf(g, fs[q][c], gw1[c]);
+                gb2 += dy;
+                gl = fmaf(e * e, invM, gl);
             }
         }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s_acc[wave][4 * lane + c] = gw1[c];
+    s_acc[wave][4 * kH + lane] = gb1;
+    s_acc[wave][5 * kH + lane] = gw2;
+    if (lane < kNPad - 6 * kH) {  // b2, the loss and the padding
+        const int k = 6 * kH + lane;
+        s_acc[wave][k] = k == 6 * kH ? gb2 : k == kLoss ? gl : 0.0f;
+    }
     __syncthreads();
-    for (int t = tid; t < kNPad; t += kWG) {
+    for (int k = tid; k < kNPad; k += kWG) {
         float s = 0.0f;
 #pragma unroll
-        for (int w = 0; w < kWG / 64; ++w) s += s_acc[w][t];
-        partial[uint64_t(blockIdx.x) * kNPad + t] = s;
+        for (int w = 0; w < kWG / 64; ++w) s += s_acc[w][k];
+        partial[uint64_t(blockIdx.x) * kNPad + k] = s;
     }
 }
 
-// Sum G partial rows in order; then either write grad/loss or take an Adam step.
+// Sum G partial rows and then either write grad/loss or take an Adam step.
+// Block b owns the kRedCols slots from b*kRedCols; its thread (r, c) sums rows
+// r, r + kRedRows, ... of slot c in order (eight loads in flight), and the
+// kRedRows sums are added in the order of r: a fixed order, the same on every
+// run.
+constexpr int kRedCols = 49, kRedRows = 10, kRedBlocks = kNPad / kRedCols;
+static_assert(kRedCols * kRedBlocks == kNPad && kRedCols * kRedRows <= 512, "reduction layout");
 __global__ __launch_bounds__(512) void k_mlp_reduce(const float *__restrict__ partial, uint32_t G,
                                                     float *__restrict__ grad_out,
                                                     float *__restrict__ loss_out, float *p, float *m,
                                                     float *v, float lr, float b1, float b2, float eps,
                                                     uint32_t t) {
-    const int i = threadIdx.x;
-    if (i > kLoss) return;
+    __shared__ float s_part[kRedRows][kRedCols];
+    const int c = threadIdx.x % kRedCols, r = threadIdx.x / kRedCols;
+    const int i = blockIdx.x * kRedCols + c;
+    if (r < kRedRows) {
+        float s = 0.0f;
+        uint32_t g = uint32_t(r);
+        for (; g + 7u * kRedRows < G; g += 8u * kRedRows) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = partial[uint64_t(g + u * kRedRows) * kNPad + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; g < G; g += kRedRows) s += partial[uint64_t(g) * kNPad + i];
+        s_part[r][c] = s;
+    }
+    __syncthreads();
+    if (r != 0 || i > kLoss) return;
     float s = 0.0f;
-    for (uint32_t g = 0; g < G; ++g) s += partial[uint64_t(g) * kNPad + i];
+#pragma unroll
+    for (int q = 0; q < kRedRows; ++q) s += s_part[q][c];
     if (i == kLoss) {
         if (loss_out) *loss_out = s;
         return;
@@ -1324,7 +1378,7 @@ ckey_status model_grad(const void *model, const uint64_t *prefix, const float *t
                        seed, step, partial);
     prof_end(st, pr);
     CKEY_TRY(launch_status());
-    hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(512), 0, st, partial, G, grad, loss, nullptr,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(kRedBlocks), dim3(512), 0, st, partial, G, grad, loss, nullptr,
                        nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 0u);
     return launch_status();
 }
@@ -1344,7 +1398,7 @@ ckey_status model_train(void *model, const uint64_t *prefix, uint64_t m, uint32_
                            partial);
         prof_end(st, pr);
         CKEY_TRY(launch_status());
-        hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(512), 0, st, partial, G, nullptr,
+        hipLaunchKernelGGL(k_mlp_reduce, dim3(kRedBlocks), dim3(512), 0, st, partial, G, nullptr,
                            loss_trace ? loss_trace + (s - 1) : nullptr, p, mm, vv, lr, b1, b2, eps, s);
         CKEY_TRY(launch_status());
     }
