@@ -46,12 +46,16 @@ def splitmix_index(seed, step, j, m):
     return z % m
 
 
-def test_grad_matches_oracle(ck):
+@pytest.mark.parametrize("n", [3000, 70000])
+def test_grad_matches_oracle(ck, n):
+    """Gradient and loss of an explicit batch against the fp64 oracle: 3000
+    samples (a ragged last wave, twelve partial rows) and 70000 (274 partial
+    rows, so the reduction's streams run their eight-load rounds)."""
     import torch
     model = ck.CdfModel(bucket_log2=10, seed=7)
     rng = np.random.default_rng(1)
-    x = rng.integers(0, 2 ** 63, 3000, dtype=np.uint64) * np.uint64(2)
-    t = rng.random(3000).astype(np.float32)
+    x = rng.integers(0, 2 ** 63, n, dtype=np.uint64) * np.uint64(2)
+    t = rng.random(n).astype(np.float32)
     grad, loss = ck.ckey_cdf_grad(model, to_dev(x), torch.from_numpy(t).cuda())
     p = model.params().double().cpu().numpy()
     loss_ref, g_ref = O.mlp_loss_grad(p, O.mlp_features(x), t.astype(np.float64))
@@ -115,6 +119,23 @@ def test_adam_step_matches_oracle(ck):
     np.testing.assert_allclose((p1 - p0)[big], (pr - p0)[big], rtol=1e-3, atol=1e-6)
     T = model.thresholds().cpu().numpy().view(np.uint64)
     np.testing.assert_array_equal(T, O.thresholds(srt, 1 << 8))
+
+
+def test_training_is_deterministic(ck):
+    """The gradient sums run in a fixed order with no atomics: two fits from
+    the same parameters on the same batches (2^16 samples, 256 partial rows
+    a step) end in the same bytes, parameters and loss trace alike."""
+    _, _, perm, _, cko = dna_prefixes(1 << 14, 4)
+    srt = np.ascontiguousarray(cko[0, perm])
+    p0 = host_params(7)
+    runs = []
+    for _ in range(2):
+        model = ck.CdfModel(bucket_log2=8, seed=0)
+        model.set_params(p0)
+        trace = ck.ckey_cdf_fit(model, to_dev(srt), steps=20, batch=1 << 16, lr=1e-2, seed=3)
+        runs.append((model.params().cpu().numpy().tobytes(), trace.cpu().numpy().tobytes()))
+    assert runs[0] == runs[1]
+    assert not np.array_equal(np.frombuffer(runs[0][0], np.float32), p0.astype(np.float32))
 
 
 def test_training_ten_steps_matches_oracle(ck):
