@@ -46,11 +46,12 @@ def splitmix_index(seed, step, j, m):
     return z % m
 
 
-@pytest.mark.parametrize("n", [3000, 70000])
+@pytest.mark.parametrize("n", [1, 65, 3000, 70000])
 def test_grad_matches_oracle(ck, n):
-    """Gradient and loss of an explicit batch against the fp64 oracle: 3000
-    samples (a ragged last wave, twelve partial rows) and 70000 (274 partial
-    rows, so the reduction's streams run their eight-load rounds)."""
+    """Gradient and loss of an explicit batch against the fp64 oracle: one
+    sample, 65 (a full wave and one sample), 3000 (a ragged last wave, twelve
+    partial rows) and 70000 (274 partial rows, so the reduction's streams run
+    their eight-load rounds)."""
     import torch
     model = ck.CdfModel(bucket_log2=10, seed=7)
     rng = np.random.default_rng(1)
