@@ -480,6 +480,25 @@ __device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *
     }
 }
 
+// Before a workgroup records `next` more keys (0: it records no more): adds
+// to the global histogram and clears each pair of packed counters in which a
+// count could otherwise pass 65535, or every pair when next == 0.  Each thread
+// decides for the words it owns; call between barriers.
+template <int AMODE>
+__device__ __forceinline__ void bucket_lds_flush_before(const BucketArgs &a, uint32_t *s, uint32_t next) {
+    if (!a.hist) return;
+    uint32_t *h = bucket_counters<AMODE>(a, s);
+    const uint32_t lim = 65535u - next;  // next <= 65535
+    for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
+        const uint32_t v = h[t];
+        if (next != 0u && (v & 0xFFFFu) <= lim && (v >> 16) <= lim) continue;
+        h[t] = 0u;
+        if (v)
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + 2 * t),
+                      (static_cast<unsigned long long>(v >> 16) << 32) | (v & 0xFFFFu));
+    }
+}
+
 // Compression fused with bucket assignment (k_compress.hip; amode 1 learned,
 // 0 splitter).  Fixed-width keys whose compression fits one launch only (else
 // CKEY_ERR_UNSUPPORTED).

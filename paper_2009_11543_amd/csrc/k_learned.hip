@@ -249,9 +249,13 @@ __global__ __launch_bounds__(512) void k_mlp_reduce(const float *__restrict__ pa
 
 // Stand-alone assignment of first words w0[0..n) (MODE 0: splitter, 1: learned).
 // Persistent: a workgroup loads the thresholds into LDS once and takes the
-// chunks of kBucketKeysPerWG keys blockIdx.x, + gridDim.x, ...; after each
-// chunk its packed 16-bit bucket counters (exact up to 65535) are added to the
-// global histogram and cleared.
+// chunks of kAssignChunk keys blockIdx.x, + gridDim.x, ...  Its packed 16-bit
+// bucket counters are exact up to 65535: after a chunk, a pair of counters is
+// added to the global histogram and cleared only when one of them could pass
+// that with the next chunk's keys, and every pair after the workgroup's last
+// chunk (keys spread over the buckets: one flush per workgroup).
+constexpr uint64_t kAssignChunk = 32 * kBucketWG;
+static_assert(kAssignChunk <= 65535, "a chunk fits the 16-bit counters");
 template <int MODE>
 __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__restrict__ w0,
                                                              uint64_t n, BucketArgs ba,
@@ -260,9 +264,9 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
     bucket_lds_init<MODE>(ba, s_dyn);
     __syncthreads();
     uint32_t probes = 0, err = 0;
-    for (uint64_t c = blockIdx.x; c * kBucketKeysPerWG < n; c += gridDim.x) {
-        const uint64_t i0 = c * kBucketKeysPerWG;
-        const uint64_t i1 = min<uint64_t>(n, i0 + kBucketKeysPerWG);
+    for (uint64_t c = blockIdx.x; c * kAssignChunk < n; c += gridDim.x) {
+        const uint64_t i0 = c * kAssignChunk;
+        const uint64_t i1 = min<uint64_t>(n, i0 + kAssignChunk);
         if (MODE == 0 && !stats) {
             // Splitter: eight keys per thread, all their loads first, then their
             // searches interleaved (every threshold in LDS, or a sample of them).
@@ -327,7 +331,8 @@ __global__ __launch_bounds__(kBucketWG) void k_bucket_assign(const uint64_t *__r
                 (void)bucket_assign_one<MODE>(ba, s_dyn, w0[i], i, probes, err);
         }
         __syncthreads();
-        bucket_lds_flush<MODE>(ba, s_dyn, true);
+        const uint64_t nx = (c + gridDim.x) * kAssignChunk;
+        bucket_lds_flush_before<MODE>(ba, s_dyn, nx < n ? uint32_t(min<uint64_t>(kAssignChunk, n - nx)) : 0u);
         __syncthreads();  // counters cleared before the next chunk's records
     }
     if (stats) {
