@@ -307,15 +307,20 @@ struct RegLoader {
     }
 };
 
-// Compression fused with bucket assignment: each workgroup compresses a
-// range of up to kBucketKeysPerWG keys (grid-stride over its threads), finds
+// Compression fused with bucket assignment: persistent, each workgroup loads
+// its thresholds into LDS once and takes the chunks of kFusedChunk keys
+// blockIdx.x, + gridDim.x, ... (grid-stride over its threads); it finds
 // each key's bucket from its first compressed word while it is in registers
 // (learned: the network's guess, then the exact bucket; splitter: a search of
 // the threshold sample in LDS, then of T in memory), and keeps a packed 16-bit
-// bucket histogram in LDS.  (With every threshold in LDS the splitter's search
+// bucket histogram in LDS, adding a pair of counters to the global histogram
+// between chunks only where one of them could pass 65535 with the next
+// chunk, and every pair after its last chunk.  (With every threshold in LDS the splitter's search
 // is cheap enough that a separate assignment kernel over the first words,
 // after a plain compression, is faster than this one-workgroup-per-CU kernel;
 // with a sample, the search's reads of T overlap the compression's loads here.)
+constexpr uint64_t kFusedChunk = 32 * kBucketWG;
+static_assert(kFusedChunk <= 65535, "a chunk fits the 16-bit counters");
 template <int MODE, int AMODE, int KPI>
 __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, CompressPlan plan,
                                                                uint64_t *__restrict__ ck,
@@ -324,82 +329,84 @@ __global__ __launch_bounds__(kBucketWG) void k_compress_bucket(KeySrc k, Compres
     extern __shared__ uint32_t s_dyn[];
     bucket_lds_init<AMODE>(ba, s_dyn);
     __syncthreads();
-    const uint64_t i0 = uint64_t(blockIdx.x) * kBucketKeysPerWG;
-    const uint64_t i1 = min<uint64_t>(k.n, i0 + kBucketKeysPerWG);
-    if (KPI > 1) {
-        // kLoad16 keys of at most four chunks, KPI keys per thread per
-        // iteration: every key's loads are issued before any of them is
-        // compressed, so their latencies overlap (a loop waits on its own
-        // stores too, as loads and stores share one in-order counter).
-        const uint64_t last = i1 - 1;
-        for (uint64_t base = i0 + threadIdx.x; base < i1; base += uint64_t(KPI) * kBucketWG) {
-            uint4 kc[KPI][4];
-#pragma unroll
-            for (int q = 0; q < KPI; ++q) {
-                const uint64_t r = min<uint64_t>(base + uint64_t(q) * kBucketWG, last);
-                const uint8_t *p = k.bytes + r * k.stride;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)  // unused slots reload chunk 0: in bounds, ignored
-                    kc[q][c] = *reinterpret_cast<const uint4 *>(p + 16 * plan.chunk[uint32_t(c) < plan.n_chunks ? c : 0]);
+    for (uint64_t c = blockIdx.x; c * kFusedChunk < k.n; c += gridDim.x) {
+        const uint64_t i0 = c * kFusedChunk;
+        const uint64_t i1 = min<uint64_t>(k.n, i0 + kFusedChunk);
+        if (KPI > 1) {
+            // kLoad16 keys of at most four chunks, KPI keys per thread per
+            // iteration: every key's loads are issued before any of them is
+            // compressed, so their latencies overlap (a loop waits on its own
+            // stores too, as loads and stores share one in-order counter).
+            const uint64_t last = i1 - 1;
+            for (uint64_t base = i0 + threadIdx.x; base < i1; base += uint64_t(KPI) * kBucketWG) {
+                uint4 kc[KPI][4];
+    #pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = min<uint64_t>(base + uint64_t(q) * kBucketWG, last);
+                    const uint8_t *p = k.bytes + r * k.stride;
+    #pragma unroll
+                    for (int c = 0; c < 4; ++c)  // unused slots reload chunk 0: in bounds, ignored
+                        kc[q][c] = *reinterpret_cast<const uint4 *>(p + 16 * plan.chunk[uint32_t(c) < plan.n_chunks ? c : 0]);
+                }
+                uint64_t w0[KPI];
+    #pragma unroll
+                for (int q = 0; q < KPI; ++q) {
+                    const uint64_t r = base + uint64_t(q) * kBucketWG;
+                    w0[q] = 0;
+                    if (r < i1) {
+                        w0[q] = compress_key(plan, RegLoader{kc[q]}, ck, k.n, r);
+                        if (plan.write_rowids && rowids) rowids[r] = uint32_t(r);
+                    }
+                }
+                if (AMODE == 1 && ba.S == 1) {  // the keys' networks together, searches in LDS
+                    uint32_t g[KPI];
+                    predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
+    #pragma unroll
+                    for (int q = 0; q < KPI; ++q) {
+                        const uint64_t r = base + uint64_t(q) * kBucketWG;
+                        // 2 x 512 buckets around the guess (the trained network's
+                        // rank error is a few hundred buckets at 2^14)
+                        const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q]);
+                        if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
+                    }
+                } else if (AMODE == 1) {  // the keys' networks together, then T in memory searched from the guesses
+                    uint32_t g[KPI], b[KPI];
+                    predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
+                    correct_bucket_n<KPI>(ba.T, ba.B, w0, g, b);
+    #pragma unroll
+                    for (int q = 0; q < KPI; ++q) {
+                        const uint64_t r = base + uint64_t(q) * kBucketWG;
+                        if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
+                    }
+                } else if (AMODE == 0 && ba.S > 1) {  // the keys' sampled searches interleaved
+                    uint32_t b[KPI];
+                    splitter_search_sampled_n<KPI>(ba, s_dyn, w0, b);
+    #pragma unroll
+                    for (int q = 0; q < KPI; ++q) {
+                        const uint64_t r = base + uint64_t(q) * kBucketWG;
+                        if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
+                    }
+                } else {
+    #pragma unroll
+                    for (int q = 0; q < KPI; ++q) {
+                        const uint64_t r = base + uint64_t(q) * kBucketWG;
+                        if (r < i1) bucket_assign_one<AMODE>(ba, s_dyn, w0[q], r);
+                    }
+                }
             }
-            uint64_t w0[KPI];
-#pragma unroll
-            for (int q = 0; q < KPI; ++q) {
-                const uint64_t r = base + uint64_t(q) * kBucketWG;
-                w0[q] = 0;
-                if (r < i1) {
-                    w0[q] = compress_key(plan, RegLoader{kc[q]}, ck, k.n, r);
-                    if (plan.write_rowids && rowids) rowids[r] = uint32_t(r);
-                }
-            }
-            if (AMODE == 1 && ba.S == 1) {  // the keys' networks together, searches in LDS
-                uint32_t g[KPI];
-                predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
-#pragma unroll
-                for (int q = 0; q < KPI; ++q) {
-                    const uint64_t r = base + uint64_t(q) * kBucketWG;
-                    // 2 x 512 buckets around the guess (the trained network's
-                    // rank error is a few hundred buckets at 2^14)
-                    const uint32_t b = correct_bucket_window<512>(reinterpret_cast<const uint64_t *>(s_dyn), ba.B, w0[q], g[q]);
-                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b, r);
-                }
-            } else if (AMODE == 1) {  // the keys' networks together, then T in memory searched from the guesses
-                uint32_t g[KPI], b[KPI];
-                predict_bucket_n<KPI>(ba.p, w0, ba.B, g);
-                correct_bucket_n<KPI>(ba.T, ba.B, w0, g, b);
-#pragma unroll
-                for (int q = 0; q < KPI; ++q) {
-                    const uint64_t r = base + uint64_t(q) * kBucketWG;
-                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
-                }
-            } else if (AMODE == 0 && ba.S > 1) {  // the keys' sampled searches interleaved
-                uint32_t b[KPI];
-                splitter_search_sampled_n<KPI>(ba, s_dyn, w0, b);
-#pragma unroll
-                for (int q = 0; q < KPI; ++q) {
-                    const uint64_t r = base + uint64_t(q) * kBucketWG;
-                    if (r < i1) bucket_record<AMODE>(ba, s_dyn, b[q], r);
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < KPI; ++q) {
-                    const uint64_t r = base + uint64_t(q) * kBucketWG;
-                    if (r < i1) bucket_assign_one<AMODE>(ba, s_dyn, w0[q], r);
-                }
+        } else {
+            for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG) {
+                GlobalLoader<MODE> ld{k.bytes + i * k.stride, k.L};
+                const uint64_t w0 = compress_key(plan, ld, ck, k.n, i);
+                if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
+                bucket_assign_one<AMODE>(ba, s_dyn, w0, i);
             }
         }
         __syncthreads();
-        bucket_lds_flush<AMODE>(ba, s_dyn);
-        return;
+        const uint64_t nx = (c + gridDim.x) * kFusedChunk;
+        bucket_lds_flush_before<AMODE>(ba, s_dyn, nx < k.n ? uint32_t(min<uint64_t>(kFusedChunk, k.n - nx)) : 0u);
+        __syncthreads();  // counters cleared before the next chunk's records
     }
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kBucketWG) {
-        GlobalLoader<MODE> ld{k.bytes + i * k.stride, k.L};
-        const uint64_t w0 = compress_key(plan, ld, ck, k.n, i);
-        if (plan.write_rowids && rowids) rowids[i] = uint32_t(i);
-        bucket_assign_one<AMODE>(ba, s_dyn, w0, i);
-    }
-    __syncthreads();
-    bucket_lds_flush<AMODE>(ba, s_dyn);
 }
 
 }  // namespace
@@ -443,8 +450,11 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
         op.off = sw.off;
     }
     plan.n_chunks = cidx;
-    const uint32_t blocks = uint32_t((k.n + kBucketKeysPerWG - 1) / kBucketKeysPerWG);
     const size_t lds = bucket_lds_bytes(ba, amode);
+    // One pass of workgroups resident at once (each loads its thresholds once).
+    auto grid = [&](const void *fn) {
+        return uint32_t(std::min<uint64_t>((k.n + kFusedChunk - 1) / kFusedChunk, resident_grid(fn, kBucketWG, lds)));
+    };
     constexpr int kKPI = 4;  // keys per thread per iteration
     const bool multi = mode == kLoad16 && cidx <= 4;
     raise_lds_limit(reinterpret_cast<const void *>(k_compress_bucket<kLoad16, 0, kKPI>));
@@ -458,11 +468,13 @@ ckey_status compress_bucket_launch(const KeySrc &k, const uint8_t *bm, uint64_t 
     const int pr_ = prof_begin(st, "compress_bucket");
 #define CKEY_LAUNCH_CB(M, KPI)                                                                         \
     if (amode)                                                                                         \
-        hipLaunchKernelGGL((k_compress_bucket<M, 1, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
-                           plan, ck, rowids, ba);                                                      \
+        hipLaunchKernelGGL((k_compress_bucket<M, 1, KPI>),                                             \
+                           dim3(grid(reinterpret_cast<const void *>(k_compress_bucket<M, 1, KPI>))),   \
+                           dim3(kBucketWG), lds, st, k, plan, ck, rowids, ba);                         \
     else                                                                                               \
-        hipLaunchKernelGGL((k_compress_bucket<M, 0, KPI>), dim3(blocks), dim3(kBucketWG), lds, st, k,   \
-                           plan, ck, rowids, ba);
+        hipLaunchKernelGGL((k_compress_bucket<M, 0, KPI>),                                             \
+                           dim3(grid(reinterpret_cast<const void *>(k_compress_bucket<M, 0, KPI>))),   \
+                           dim3(kBucketWG), lds, st, k, plan, ck, rowids, ba);
     switch (mode) {
         case kLoad16:
             if (multi) {
