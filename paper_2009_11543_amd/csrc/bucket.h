@@ -465,21 +465,6 @@ __device__ __forceinline__ void bucket_assign_one(const BucketArgs &a, uint32_t 
     (void)bucket_assign_one<AMODE>(a, s, x, i, probes, err);
 }
 
-template <int AMODE>
-__device__ __forceinline__ void bucket_lds_flush(const BucketArgs &a, uint32_t *s, bool clear = false) {
-    if (!a.hist) return;
-    uint32_t *h = bucket_counters<AMODE>(a, s);
-    for (uint32_t t = threadIdx.x; t < a.B / 2; t += blockDim.x) {
-        const uint32_t v = h[t];
-        if (clear) h[t] = 0u;
-        // Buckets 2t and 2t+1 in one 64-bit add (hist is 8-byte aligned): the
-        // low count cannot carry into the high one, as every count is < 2^32.
-        if (v)
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + 2 * t),
-                      (static_cast<unsigned long long>(v >> 16) << 32) | (v & 0xFFFFu));
-    }
-}
-
 // Before a workgroup records `next` more keys (0: it records no more): adds
 // to the global histogram and clears each pair of packed counters in which a
 // count could otherwise pass 65535, or every pair when next == 0.  Each thread
@@ -493,6 +478,8 @@ __device__ __forceinline__ void bucket_lds_flush_before(const BucketArgs &a, uin
         const uint32_t v = h[t];
         if (next != 0u && (v & 0xFFFFu) <= lim && (v >> 16) <= lim) continue;
         h[t] = 0u;
+        // Buckets 2t and 2t+1 in one 64-bit add (hist is 8-byte aligned): the
+        // low count cannot carry into the high one, as every count is < 2^32.
         if (v)
             atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + 2 * t),
                       (static_cast<unsigned long long>(v >> 16) << 32) | (v & 0xFFFFu));

@@ -53,6 +53,9 @@ int main(int argc, char **argv) {
         lwin[i] = correct_bucket_window<512>(th, B, x[i], g[i]);
         pr1[i] = predict_bucket(p.data(), x[i], B);
         bucket_record<0>(a, s0.data(), one[i], i);
+        // Every 500 keys a flush as if 65530 more keys were to come: counters
+        // above 5 go to the global histogram, the others stay in LDS.
+        if ((i + 1) % 500 == 0) bucket_lds_flush_before<0>(a, s0.data(), 65530u);
     }
     for (size_t i = 0; i < nx; i += 8) {
         uint64_t xs[8];
@@ -81,7 +84,7 @@ int main(int argc, char **argv) {
         predict_bucket_n<4>(p.data(), xs, B, gq);
         for (int q = 0; q < 4 && i + q < nx; ++q) pr4[i + q] = gq[q];
     }
-    bucket_lds_flush<0>(a, s0.data());
+    bucket_lds_flush_before<0>(a, s0.data(), 0u);  // the last: every pair
     wr(d + "/one.bin", one);
     wr(d + "/many.bin", many);
     wr(d + "/lcorr.bin", lcorr);

@@ -14,7 +14,8 @@ table T (T[0] = 0): the largest b with T[b] <= x.
     arbitrary guesses (near, far, at either end);
   * the network's guess for one key and for four at once agree exactly;
   * the packed 16-bit LDS histogram flushed to the global one equals the
-    bucket counts.
+    bucket counts, with partial flushes on the way (every 500 keys, the pairs
+    holding a count above 5) and the full one at the end.
 An address sanitizer build checks that no search reads outside its LDS image
 or T."""
 import os
